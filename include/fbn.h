@@ -1,0 +1,178 @@
+/*
+ * fbn.h -- C ABI of the MI355X junction-tree inference library.
+ *
+ * The calls follow the problem statement of Jiang, Wen, Mansoor and Mian,
+ * "Fast Parallel Exact Inference on Bayesian Networks" (PPoPP'23 poster):
+ *   - a Bayesian network is a DAG over discrete variables with conditional
+ *     probability tables (Section 1)                      -> fbn_load_net*
+ *   - it is compiled into a junction tree whose cliques and separators
+ *     each hold a potential table (Section 1), with every clique and
+ *     separator marked by its layer and the root chosen for the fewest
+ *     layers (Section 2)                                  -> fbn_build_jt
+ *   - evidence fixes the values of some variables (Section 1); entering it
+ *     is the "reduction" table operation (Section 2)     -> fbn_set_evidence
+ *   - messages pass along the tree and update every table, using the
+ *     marginalisation and extension operations on index mappings between
+ *     tables (Sections 1 and 2), one launch per layer   -> fbn_calibrate
+ *   - the answer is the conditional probability of query variables given
+ *     the evidence (Section 1)                           -> fbn_query_marginals
+ *
+ * Conventions
+ *   Ownership: handles are opaque, created by the library and released by
+ *   the caller (fbn_free_*; NULL is accepted).  Input arrays are borrowed for
+ *   the duration of the call only.  Output arrays are caller-allocated host
+ *   memory with the sizes stated.  A jt copies everything it needs from the
+ *   net, which may be freed right after fbn_build_jt.
+ *   Errors: every call returns an fbn_status; FBN_OK is 0.  No C++ exception
+ *   crosses the ABI.  fbn_last_error() gives a thread-local detail string.
+ *   A failing call leaves the handle in its previous valid state.
+ *   Device and streams: a jt lives on the HIP device that was current when
+ *   it was built; all of its work is enqueued on its stream (options.stream,
+ *   or the legacy default stream when NULL).  fbn_calibrate is asynchronous
+ *   unless it is asked for log_pe / per_slot; the query calls synchronise
+ *   the stream.  One jt must be driven by one host thread at a time;
+ *   separate jts may run concurrently on separate streams.
+ *   Precision: results at the boundary are always float64.
+ */
+#ifndef FBN_H
+#define FBN_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct fbn_net fbn_net;   /* host-only network (DAG + float64 CPTs) */
+typedef struct fbn_jt fbn_jt;     /* compiled junction tree + device state  */
+typedef int32_t fbn_status;
+
+enum {
+    FBN_OK = 0,
+    FBN_E_INVALID_ARG = 1,    /* bad pointer, index, size or evidence         */
+    FBN_E_PARSE = 2,          /* malformed .fbn text                          */
+    FBN_E_IO = 3,             /* file could not be read                       */
+    FBN_E_NOMEM_HOST = 4,
+    FBN_E_NOMEM_DEVICE = 5,   /* the allocator returned NULL                  */
+    FBN_E_TOO_LARGE = 6,      /* a clique exceeds max_clique_entries          */
+    FBN_E_ZERO_EVIDENCE = 7,  /* P(e) = 0 for that slot                       */
+    FBN_E_STATE = 8,          /* call not valid in this state (e.g. host_only) */
+    FBN_E_DEVICE = 9,         /* a HIP runtime call failed                    */
+    FBN_E_UNDERFLOW = 10      /* FP32 message vanished; rerun the case in FP64 */
+};
+
+enum { FBN_FP64 = 0, FBN_FP32_RESCALED = 1 };
+
+/* Device memory comes from the caller when alloc is set (e.g. PyTorch's
+ * caching allocator); otherwise hipMalloc / hipFree are used. */
+typedef struct {
+    void* (*alloc)(void* ctx, size_t bytes, void* stream);  /* NULL on failure */
+    void (*free)(void* ctx, void* ptr, void* stream);
+    void* ctx;
+} fbn_allocator;
+
+typedef struct {
+    int32_t precision;            /* FBN_FP64 or FBN_FP32_RESCALED            */
+    int32_t max_slots;            /* evidence cases resident at once (>= 1)   */
+    uint64_t max_clique_entries;  /* build fails with FBN_E_TOO_LARGE above   */
+    int32_t host_only;            /* 1: compile the tree, no device state     */
+    int32_t tile_entries;         /* table entries per workgroup; 0 = default */
+    fbn_allocator allocator;
+    void* stream;                 /* hipStream_t                              */
+} fbn_jt_options;
+
+typedef struct {
+    int32_t n_vars, n_cliques, n_edges, root, H, D; /* H: root height, D: max depth */
+    uint64_t T;            /* sum of clique table entries                         */
+    uint64_t K;            /* sum over edges of the parent table size (map length) */
+    uint64_t max_clique;   /* largest clique table                                */
+    uint64_t sep_total;    /* sum of separator table entries                      */
+    uint64_t device_bytes; /* device memory held by the jt                        */
+    uint64_t slot_bytes;   /* of which per evidence slot                          */
+} fbn_jt_stats_t;
+
+/* Fill opt with defaults: FP64, 1 slot, 2^31-1 max entries, device build. */
+void fbn_default_options(fbn_jt_options* opt);
+
+/* --- networks (Section 1) -------------------------------------------------
+ * .fbn text: "fbn 1", "vars n", then per variable "var v r k p1..pk", then per
+ * variable "cpt v m x1..xm" (parents in listed order, v fastest; values as C99
+ * hexadecimal or decimal floats), then "end".  Validation: acyclic, r >= 2,
+ * entries finite and >= 0, each row summing to 1 within 1e-9. */
+fbn_status fbn_load_net(const char* path, fbn_net** out);
+fbn_status fbn_load_net_mem(const char* text, size_t len, fbn_net** out);
+/* The same network from arrays: card[n], n_parents[n], parents concatenated,
+ * cpt concatenated per variable in the layout above. */
+fbn_status fbn_net_from_arrays(int32_t n_vars, const int32_t* card, const int32_t* n_parents,
+                               const int32_t* parents, const double* cpt, fbn_net** out);
+void fbn_free_net(fbn_net* net);
+
+/* --- junction tree (Sections 1, 2) ----------------------------------------
+ * Moralise, min-fill triangulation, maximum-weight spanning junction tree,
+ * root of minimum eccentricity (fewest layers), per-edge index maps, prior
+ * potentials, device upload.  opt may be NULL (defaults). */
+fbn_status fbn_build_jt(const fbn_net* net, const fbn_jt_options* opt, fbn_jt** out);
+void fbn_free_jt(fbn_jt* jt);  /* synchronises its stream first */
+/* Replace the stream used by later calls. */
+fbn_status fbn_set_stream(fbn_jt* jt, void* stream);
+
+/* --- evidence: the reduction operation (Section 2) -------------------------
+ * Hard evidence for one slot: distinct variables, 0 <= state < card.  n_obs = 0
+ * clears the slot.  Staged on the host; uploaded by the next fbn_calibrate. */
+fbn_status fbn_set_evidence(fbn_jt* jt, int32_t slot, int32_t n_obs, const int32_t* vars,
+                            const int32_t* states);
+/* Several slots at once: case i uses vars/states[offsets[i] .. offsets[i+1]). */
+fbn_status fbn_set_evidence_batch(fbn_jt* jt, int32_t n_slots, const int32_t* slots,
+                                  const int32_t* offsets, const int32_t* vars, const int32_t* states);
+
+/* --- propagation: marginalisation and extension, layer by layer (Section 2)
+ * Collect then distribute for the listed slots, all slots in the same
+ * launches.  log_pe (n_slots doubles) and per_slot (n_slots statuses) may be
+ * NULL; if either is given the call waits for the device and fills them. */
+fbn_status fbn_calibrate(fbn_jt* jt, int32_t n_slots, const int32_t* slots, double* log_pe,
+                         fbn_status* per_slot);
+
+/* --- queries (Section 1) ---------------------------------------------------
+ * Posterior P(v | e) of each listed variable, concatenated (card[v] doubles
+ * each) into out[0 .. out_len).  Synchronises. */
+fbn_status fbn_query_marginals(fbn_jt* jt, int32_t slot, int32_t n_vars, const int32_t* vars,
+                               double* out, size_t out_len);
+/* All posteriors of several slots: out holds n_slots * sum(card) doubles,
+ * slot-major; log_pe and per_slot as in fbn_calibrate (may be NULL). */
+fbn_status fbn_query_all(fbn_jt* jt, int32_t n_slots, const int32_t* slots, double* out,
+                         size_t out_len, double* log_pe, fbn_status* per_slot);
+/* Asynchronous form of fbn_query_all: enqueues the copies on the jt's stream
+ * into caller-owned host memory (pinned for true overlap); the caller must
+ * synchronise that stream before reading.  per_slot receives raw flags: 0 ok,
+ * 1 zero evidence, 2 FP32 underflow. */
+fbn_status fbn_fetch_async(fbn_jt* jt, int32_t n_slots, const int32_t* slots, double* post_out,
+                           double* log_pe_out, int32_t* flags_out);
+
+const char* fbn_status_str(fbn_status s);
+const char* fbn_last_error(void);
+
+/* --- introspection for structure parity tests ------------------------------ */
+fbn_status fbn_jt_stats(const fbn_jt* jt, fbn_jt_stats_t* out);
+/* Variables of clique c in table layout order (at most cap written; *n gets
+ * the count), with its height (collect layer) and depth (distribute layer). */
+fbn_status fbn_jt_clique(const fbn_jt* jt, int32_t c, int32_t* vars, int32_t cap, int32_t* n,
+                         int32_t* height, int32_t* depth);
+/* Edge e (numbered by ascending child clique id): parent, child, separator
+ * variables ascending. */
+fbn_status fbn_jt_edge(const fbn_jt* jt, int32_t e, int32_t* parent, int32_t* child,
+                       int32_t* sep_vars, int32_t cap, int32_t* n);
+/* The index map of edge e: out[j] = separator entry of parent entry j, for
+ * j < |parent table| (cap must be at least that).  Expanded on the host from
+ * the factored tables the kernels read. */
+fbn_status fbn_jt_index_map(const fbn_jt* jt, int32_t e, int32_t* out, size_t cap);
+/* The same map expanded by a kernel from the device copy of those tables. */
+fbn_status fbn_jt_device_index_map(fbn_jt* jt, int32_t e, int32_t* out, size_t cap);
+/* Elimination order (n_vars), CPT home clique and posterior home clique per variable. */
+fbn_status fbn_jt_elim_order(const fbn_jt* jt, int32_t* order);
+fbn_status fbn_jt_homes(const fbn_jt* jt, int32_t* cpt_home, int32_t* var_home);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

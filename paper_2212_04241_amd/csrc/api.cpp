@@ -1,0 +1,863 @@
+// C ABI of the junction-tree library: network loading and validation, tree
+// compilation and device upload, evidence slots, the layer-by-layer launch
+// sequence, and result retrieval.  See include/fbn.h for the contract.
+#include <hip/hip_runtime_api.h>
+
+#include <algorithm>
+#include <cerrno>
+#include <cmath>
+#include <cstdio>
+#include <cstdlib>
+#include <cstring>
+#include <fstream>
+#include <new>
+#include <sstream>
+#include <string>
+#include <vector>
+
+#include "../../include/fbn.h"
+#include "fbn_internal.h"
+#include "kernels.h"
+#include "plan.h"
+
+using namespace fbn;
+
+namespace {
+
+thread_local std::string g_err;
+
+fbn_status fail(fbn_status s, const std::string& msg) {
+    g_err = msg;
+    return s;
+}
+
+#define HIP_OK(expr)                                                                          \
+    do {                                                                                      \
+        hipError_t e_ = (expr);                                                               \
+        if (e_ != hipSuccess) return fail(FBN_E_DEVICE, std::string(#expr ": ") + hipGetErrorString(e_)); \
+    } while (0)
+
+// ------------------------------------------------------------ net validation
+
+fbn_status check_net(Net& net) {
+    const int n = net.n;
+    for (int v = 0; v < n; v++) {
+        if (net.card[v] < 2 || net.card[v] > 65535) return fail(FBN_E_INVALID_ARG, "variable " + std::to_string(v) + ": cardinality out of range");
+        for (size_t a = 0; a < net.parents[v].size(); a++) {
+            int p = net.parents[v][a];
+            if (p < 0 || p >= n || p == v) return fail(FBN_E_INVALID_ARG, "variable " + std::to_string(v) + ": bad parent");
+            for (size_t b = 0; b < a; b++)
+                if (net.parents[v][b] == p) return fail(FBN_E_INVALID_ARG, "variable " + std::to_string(v) + ": repeated parent");
+        }
+    }
+    // acyclicity by repeatedly removing variables with no remaining parents
+    std::vector<int> indeg(n, 0);
+    std::vector<std::vector<int>> kids(n);
+    for (int v = 0; v < n; v++) {
+        indeg[v] = (int)net.parents[v].size();
+        for (int p : net.parents[v]) kids[p].push_back(v);
+    }
+    std::vector<int> ready;
+    for (int v = 0; v < n; v++)
+        if (!indeg[v]) ready.push_back(v);
+    int done = 0;
+    while (!ready.empty()) {
+        int v = ready.back();
+        ready.pop_back();
+        done++;
+        for (int k : kids[v])
+            if (--indeg[k] == 0) ready.push_back(k);
+    }
+    if (done != n) return fail(FBN_E_INVALID_ARG, "the network has a directed cycle");
+    for (int v = 0; v < n; v++) {
+        if (net.cpt[v].empty()) continue;
+        uint64_t len = (uint64_t)net.card[v];
+        for (int p : net.parents[v]) len *= (uint64_t)net.card[p];
+        if (net.cpt[v].size() != len) return fail(FBN_E_INVALID_ARG, "variable " + std::to_string(v) + ": CPT length");
+        const int r = net.card[v];
+        for (uint64_t row = 0; row < len / (uint64_t)r; row++) {
+            double s = 0.0;
+            for (int x = 0; x < r; x++) {
+                double val = net.cpt[v][row * (uint64_t)r + (uint64_t)x];
+                if (!std::isfinite(val) || val < 0.0) return fail(FBN_E_INVALID_ARG, "variable " + std::to_string(v) + ": CPT entry not finite and non-negative");
+                s += val;
+            }
+            if (std::fabs(s - 1.0) > 1e-9) return fail(FBN_E_INVALID_ARG, "variable " + std::to_string(v) + ": CPT row does not sum to 1");
+        }
+    }
+    return FBN_OK;
+}
+
+// whitespace tokenizer over an in-memory text
+struct Lexer {
+    const char* p;
+    const char* end;
+    bool next(std::string& tok) {
+        while (p < end && (*p == ' ' || *p == '\n' || *p == '\t' || *p == '\r')) p++;
+        if (p >= end) return false;
+        const char* s = p;
+        while (p < end && !(*p == ' ' || *p == '\n' || *p == '\t' || *p == '\r')) p++;
+        tok.assign(s, (size_t)(p - s));
+        return true;
+    }
+    bool integer(long long& x) {
+        std::string t;
+        if (!next(t)) return false;
+        char* e = nullptr;
+        errno = 0;
+        x = std::strtoll(t.c_str(), &e, 10);
+        return errno == 0 && e && *e == 0;
+    }
+    bool real(double& x) {
+        std::string t;
+        if (!next(t)) return false;
+        char* e = nullptr;
+        x = std::strtod(t.c_str(), &e);
+        return e && *e == 0;
+    }
+};
+
+fbn_status parse_net(const char* text, size_t len, Net& net) {
+    Lexer lx{text, text + len};
+    std::string t;
+    long long x = 0, n = 0;
+    if (!lx.next(t) || t != "fbn" || !lx.integer(x) || x != 1) return fail(FBN_E_PARSE, "expected 'fbn 1'");
+    if (!lx.next(t) || t != "vars" || !lx.integer(n) || n <= 0 || n > 1000000) return fail(FBN_E_PARSE, "expected 'vars n'");
+    net.n = (int)n;
+    net.card.assign((size_t)n, 0);
+    net.parents.assign((size_t)n, {});
+    net.cpt.assign((size_t)n, {});
+    std::vector<char> declared((size_t)n, 0), has_cpt((size_t)n, 0);
+    for (;;) {
+        if (!lx.next(t)) return fail(FBN_E_PARSE, "missing 'end'");
+        if (t == "end") break;
+        if (t == "var") {
+            long long v, r, k;
+            if (!lx.integer(v) || !lx.integer(r) || !lx.integer(k) || v < 0 || v >= n || k < 0 || k > n || declared[(size_t)v])
+                return fail(FBN_E_PARSE, "bad 'var' record");
+            declared[(size_t)v] = 1;
+            net.card[(size_t)v] = (int)r;
+            for (long long i = 0; i < k; i++) {
+                long long p;
+                if (!lx.integer(p)) return fail(FBN_E_PARSE, "bad parent list");
+                net.parents[(size_t)v].push_back((int)p);
+            }
+        } else if (t == "cpt") {
+            long long v, m;
+            if (!lx.integer(v) || !lx.integer(m) || v < 0 || v >= n || m <= 0 || has_cpt[(size_t)v])
+                return fail(FBN_E_PARSE, "bad 'cpt' record");
+            has_cpt[(size_t)v] = 1;
+            auto& vals = net.cpt[(size_t)v];
+            vals.resize((size_t)m);
+            for (long long i = 0; i < m; i++)
+                if (!lx.real(vals[(size_t)i])) return fail(FBN_E_PARSE, "bad or missing CPT value");
+        } else {
+            return fail(FBN_E_PARSE, "unknown record '" + t + "'");
+        }
+    }
+    for (long long v = 0; v < n; v++)
+        if (!declared[(size_t)v] || !has_cpt[(size_t)v]) return fail(FBN_E_PARSE, "variable " + std::to_string(v) + " incomplete");
+    for (long long v = 0; v < n; v++) {
+        uint64_t want = (uint64_t)std::max(net.card[(size_t)v], 0);
+        for (int p : net.parents[(size_t)v]) {
+            if (p < 0 || p >= n) return fail(FBN_E_PARSE, "bad parent id");
+            want *= (uint64_t)std::max(net.card[(size_t)p], 0);
+        }
+        if (net.cpt[(size_t)v].size() != want) return fail(FBN_E_PARSE, "variable " + std::to_string(v) + ": CPT length");
+    }
+    return check_net(net);
+}
+
+}  // namespace
+
+struct fbn_net {
+    Net net;
+};
+
+// ------------------------------------------------------------------ jt state
+
+struct fbn_jt {
+    fbn_jt_options opt{};
+    Tree tree;
+    Plan plan;
+    int device = -1;
+    hipStream_t stream = nullptr;
+    std::vector<void*> allocs;
+    // device plan
+    DClique* d_cl = nullptr;
+    DChild* d_ch = nullptr;
+    DHome* d_hm = nullptr;
+    DPiece* d_pc = nullptr;
+    DHomeVar* d_hv = nullptr;
+    DGroup* d_groups = nullptr;
+    DSepFin* d_fins = nullptr;
+    uint64_t* d_dig = nullptr;
+    uint32_t* d_map = nullptr;
+    void* d_prior = nullptr;
+    // per-slot state
+    void* d_psi = nullptr;
+    void* d_sepc = nullptr;
+    void* d_sepd = nullptr;
+    double* d_acc = nullptr;
+    double* d_part = nullptr;
+    int32_t* d_kexp = nullptr;
+    double* d_marg = nullptr;
+    double* d_post = nullptr;
+    double* d_logpe = nullptr;
+    int32_t* d_flags = nullptr;
+    DEvidence* d_ev = nullptr;
+    int32_t* d_slots = nullptr;
+    double* d_out_post = nullptr;
+    double* d_out_logpe = nullptr;
+    int32_t* d_out_flags = nullptr;
+    // host staging (pinned when a device is present)
+    DEvidence* h_ev = nullptr;
+    int32_t* h_slots = nullptr;
+    bool h_pinned = false;
+    std::vector<char> dirty;
+    hipEvent_t staged = nullptr;
+    bool staged_pending = false;
+    // evidence lookup: for each variable, the (clique, layout position) pairs
+    std::vector<std::vector<std::pair<int, int>>> occ;
+    Ctx ctx{};
+    uint64_t device_bytes = 0, slot_bytes = 0;
+};
+
+namespace {
+
+void* dev_alloc(fbn_jt* jt, size_t bytes) {
+    if (bytes == 0) bytes = 256;
+    void* p = nullptr;
+    if (jt->opt.allocator.alloc) {
+        p = jt->opt.allocator.alloc(jt->opt.allocator.ctx, bytes, jt->stream);
+    } else if (hipMalloc(&p, bytes) != hipSuccess) {
+        p = nullptr;
+    }
+    if (p) {
+        jt->allocs.push_back(p);
+        jt->device_bytes += bytes;
+    }
+    return p;
+}
+
+void release(fbn_jt* jt) {
+    if (jt->device >= 0) {
+        hipSetDevice(jt->device);
+        hipStreamSynchronize(jt->stream);
+        for (void* p : jt->allocs) {
+            if (jt->opt.allocator.alloc) {
+                if (jt->opt.allocator.free) jt->opt.allocator.free(jt->opt.allocator.ctx, p, jt->stream);
+            } else {
+                hipFree(p);
+            }
+        }
+        if (jt->staged) hipEventDestroy(jt->staged);
+    }
+    jt->allocs.clear();
+    if (jt->h_pinned) {
+        if (jt->h_ev) hipHostFree(jt->h_ev);
+        if (jt->h_slots) hipHostFree(jt->h_slots);
+    } else {
+        std::free(jt->h_ev);
+        std::free(jt->h_slots);
+    }
+    jt->h_ev = nullptr;
+    jt->h_slots = nullptr;
+}
+
+template <typename V>
+fbn_status upload(fbn_jt* jt, const std::vector<V>& src, V*& dst) {
+    dst = static_cast<V*>(dev_alloc(jt, sizeof(V) * std::max<size_t>(src.size(), 1)));
+    if (!dst) return fail(FBN_E_NOMEM_DEVICE, "device allocation failed");
+    if (!src.empty()) HIP_OK(hipMemcpyAsync(dst, src.data(), sizeof(V) * src.size(), hipMemcpyHostToDevice, jt->stream));
+    return FBN_OK;
+}
+
+fbn_status wait_staged(fbn_jt* jt) {
+    if (jt->staged_pending) {
+        HIP_OK(hipEventSynchronize(jt->staged));
+        jt->staged_pending = false;
+    }
+    return FBN_OK;
+}
+
+fbn_status setup_device(fbn_jt* jt) {
+    Plan& p = jt->plan;
+    const int S = jt->opt.max_slots;
+    const bool f32 = jt->opt.precision == FBN_FP32_RESCALED;
+    const size_t w = f32 ? 4 : 8;
+    HIP_OK(hipGetDevice(&jt->device));
+    jt->stream = static_cast<hipStream_t>(jt->opt.stream);
+    HIP_OK(hipEventCreateWithFlags(&jt->staged, hipEventDisableTiming));
+    fbn_status st;
+    if ((st = upload(jt, p.cliques, jt->d_cl))) return st;
+    if ((st = upload(jt, p.children, jt->d_ch))) return st;
+    if ((st = upload(jt, p.homes, jt->d_hm))) return st;
+    if ((st = upload(jt, p.pieces, jt->d_pc))) return st;
+    if ((st = upload(jt, p.homevars, jt->d_hv))) return st;
+    if ((st = upload(jt, p.groups, jt->d_groups))) return st;
+    if ((st = upload(jt, p.fins, jt->d_fins))) return st;
+    if ((st = upload(jt, p.digits, jt->d_dig))) return st;
+    if ((st = upload(jt, p.maps, jt->d_map))) return st;
+    // prior in table precision (float32: each entry rounded once, to nearest)
+    jt->d_prior = dev_alloc(jt, w * std::max<uint64_t>(p.T, 1));
+    if (!jt->d_prior) return fail(FBN_E_NOMEM_DEVICE, "device allocation failed");
+    if (f32) {
+        std::vector<float> pf(p.prior.size());
+        for (size_t i = 0; i < pf.size(); i++) pf[i] = (float)p.prior[i];
+        HIP_OK(hipMemcpy(jt->d_prior, pf.data(), 4 * pf.size(), hipMemcpyHostToDevice));
+    } else {
+        HIP_OK(hipMemcpy(jt->d_prior, p.prior.data(), 8 * p.prior.size(), hipMemcpyHostToDevice));
+    }
+    // per-slot state
+    const uint64_t psi_stride = (p.T + 63) / 64 * 64;
+    const uint32_t part_stride = (p.n_parts + 63) / 64 * 64 + 64;
+    const uint32_t kexp_stride = (uint32_t)((jt->tree.ne + 1 + 63) / 64 * 64);
+    const uint32_t marg_stride = p.marg_total;
+    const uint32_t ev_stride = (uint32_t)jt->tree.nc;
+    const uint64_t before = jt->device_bytes;
+    struct Req {
+        void** dst;
+        size_t bytes;
+    } reqs[] = {
+        {&jt->d_psi, w * psi_stride * (size_t)S},
+        {&jt->d_sepc, w * p.sep_stride * (size_t)S},
+        {&jt->d_sepd, w * p.sep_stride * (size_t)S},
+        {(void**)&jt->d_acc, 8ull * p.sep_stride * (size_t)S},
+        {(void**)&jt->d_part, 8ull * part_stride * (size_t)S},
+        {(void**)&jt->d_kexp, 4ull * kexp_stride * (size_t)S},
+        {(void**)&jt->d_marg, 8ull * marg_stride * (size_t)S},
+        {(void**)&jt->d_post, 8ull * marg_stride * (size_t)S},
+        {(void**)&jt->d_logpe, 8ull * (size_t)S},
+        {(void**)&jt->d_flags, 4ull * (size_t)S},
+        {(void**)&jt->d_ev, sizeof(DEvidence) * ev_stride * (size_t)S},
+        {(void**)&jt->d_slots, 4ull * (size_t)S},
+        {(void**)&jt->d_out_post, 8ull * marg_stride * (size_t)S},
+        {(void**)&jt->d_out_logpe, 8ull * (size_t)S},
+        {(void**)&jt->d_out_flags, 4ull * (size_t)S},
+    };
+    for (auto& r : reqs) {
+        *r.dst = dev_alloc(jt, r.bytes);
+        if (!*r.dst) return fail(FBN_E_NOMEM_DEVICE, "device allocation failed");
+        HIP_OK(launch_zero(*r.dst, r.bytes, jt->stream));
+    }
+    jt->slot_bytes = (jt->device_bytes - before) / (uint64_t)S;
+    // host staging
+    const size_t evb = sizeof(DEvidence) * ev_stride * (size_t)S;
+    if (hipHostMalloc((void**)&jt->h_ev, evb, hipHostMallocDefault) == hipSuccess &&
+        hipHostMalloc((void**)&jt->h_slots, 4ull * (size_t)S, hipHostMallocDefault) == hipSuccess) {
+        jt->h_pinned = true;
+    } else {
+        return fail(FBN_E_NOMEM_HOST, "pinned host allocation failed");
+    }
+    std::memset(jt->h_ev, 0, evb);
+    Ctx& c = jt->ctx;
+    c.cl = jt->d_cl;
+    c.ch = jt->d_ch;
+    c.hm = jt->d_hm;
+    c.pc = jt->d_pc;
+    c.hv = jt->d_hv;
+    c.dig = jt->d_dig;
+    c.map = jt->d_map;
+    c.prior = jt->d_prior;
+    c.psi = jt->d_psi;
+    c.sepc = jt->d_sepc;
+    c.sepd = jt->d_sepd;
+    c.acc = jt->d_acc;
+    c.part = jt->d_part;
+    c.kexp = jt->d_kexp;
+    c.marg = jt->d_marg;
+    c.post = jt->d_post;
+    c.logpe = jt->d_logpe;
+    c.flags = jt->d_flags;
+    c.ev = jt->d_ev;
+    c.psi_stride = psi_stride;
+    c.sep_stride = p.sep_stride;
+    c.part_stride = part_stride;
+    c.kexp_stride = kexp_stride;
+    c.marg_stride = marg_stride;
+    c.ev_stride = ev_stride;
+    c.nvars = jt->tree.n;
+    c.ne = jt->tree.ne;
+    c.kappa_total = p.kappa_total;
+    c.fp32 = f32 ? 1 : 0;
+    HIP_OK(hipStreamSynchronize(jt->stream));
+    return FBN_OK;
+}
+
+fbn_status check_slots(const fbn_jt* jt, int32_t n, const int32_t* slots) {
+    if (n < 0 || n > jt->opt.max_slots || (n > 0 && !slots)) return fail(FBN_E_INVALID_ARG, "bad slot list");
+    std::vector<char> seen((size_t)jt->opt.max_slots, 0);
+    for (int32_t i = 0; i < n; i++) {
+        if (slots[i] < 0 || slots[i] >= jt->opt.max_slots) return fail(FBN_E_INVALID_ARG, "slot out of range");
+        if (seen[(size_t)slots[i]]) return fail(FBN_E_INVALID_ARG, "slot listed twice");
+        seen[(size_t)slots[i]] = 1;
+    }
+    return FBN_OK;
+}
+
+fbn_status stage_slots(fbn_jt* jt, int32_t n, const int32_t* slots) {
+    fbn_status st = wait_staged(jt);
+    if (st) return st;
+    std::memcpy(jt->h_slots, slots, 4ull * (size_t)n);
+    HIP_OK(hipMemcpyAsync(jt->d_slots, jt->h_slots, 4ull * (size_t)n, hipMemcpyHostToDevice, jt->stream));
+    const size_t per = (size_t)jt->ctx.ev_stride;
+    for (int32_t i = 0; i < n; i++) {
+        const int s = slots[i];
+        if (!jt->dirty[(size_t)s]) continue;
+        int e = s;
+        while (e + 1 < jt->opt.max_slots && jt->dirty[(size_t)e + 1]) e++;  // contiguous run
+        HIP_OK(hipMemcpyAsync(jt->d_ev + (size_t)s * per, jt->h_ev + (size_t)s * per,
+                              sizeof(DEvidence) * per * (size_t)(e - s + 1), hipMemcpyHostToDevice, jt->stream));
+        for (int k = s; k <= e; k++) jt->dirty[(size_t)k] = 0;
+    }
+    HIP_OK(hipEventRecord(jt->staged, jt->stream));
+    jt->staged_pending = true;
+    return FBN_OK;
+}
+
+fbn_status status_of_flag(int32_t f) {
+    if (f & 2) return FBN_E_UNDERFLOW;
+    if (f & 1) return FBN_E_ZERO_EVIDENCE;
+    return FBN_OK;
+}
+
+fbn_status fetch(fbn_jt* jt, int32_t n, double* post, double* logpe, int32_t* flags) {
+    HIP_OK(launch_gather(jt->ctx, jt->d_slots, n, post ? jt->d_out_post : nullptr, logpe ? jt->d_out_logpe : nullptr,
+                         flags ? jt->d_out_flags : nullptr, jt->stream));
+    const size_t per = jt->ctx.marg_stride;
+    if (post) HIP_OK(hipMemcpyAsync(post, jt->d_out_post, 8 * per * (size_t)n, hipMemcpyDeviceToHost, jt->stream));
+    if (logpe) HIP_OK(hipMemcpyAsync(logpe, jt->d_out_logpe, 8ull * (size_t)n, hipMemcpyDeviceToHost, jt->stream));
+    if (flags) HIP_OK(hipMemcpyAsync(flags, jt->d_out_flags, 4ull * (size_t)n, hipMemcpyDeviceToHost, jt->stream));
+    return FBN_OK;
+}
+
+}  // namespace
+
+// ====================================================================== ABI
+
+extern "C" {
+
+void fbn_default_options(fbn_jt_options* opt) {
+    if (!opt) return;
+    std::memset(opt, 0, sizeof(*opt));
+    opt->precision = FBN_FP64;
+    opt->max_slots = 1;
+    opt->max_clique_entries = 0x7fffffffull;
+    opt->host_only = 0;
+    opt->tile_entries = 0;
+    opt->stream = nullptr;
+}
+
+const char* fbn_status_str(fbn_status s) {
+    switch (s) {
+        case FBN_OK: return "ok";
+        case FBN_E_INVALID_ARG: return "invalid argument";
+        case FBN_E_PARSE: return "parse error";
+        case FBN_E_IO: return "i/o error";
+        case FBN_E_NOMEM_HOST: return "out of host memory";
+        case FBN_E_NOMEM_DEVICE: return "out of device memory";
+        case FBN_E_TOO_LARGE: return "clique too large";
+        case FBN_E_ZERO_EVIDENCE: return "evidence has probability zero";
+        case FBN_E_STATE: return "invalid state";
+        case FBN_E_DEVICE: return "device error";
+        case FBN_E_UNDERFLOW: return "float32 underflow";
+        default: return "unknown status";
+    }
+}
+
+const char* fbn_last_error(void) { return g_err.c_str(); }
+
+fbn_status fbn_load_net_mem(const char* text, size_t len, fbn_net** out) {
+    if (!text || !out) return fail(FBN_E_INVALID_ARG, "null argument");
+    *out = nullptr;
+    try {
+        auto* h = new fbn_net();
+        fbn_status st = parse_net(text, len, h->net);
+        if (st) {
+            delete h;
+            return st;
+        }
+        *out = h;
+        return FBN_OK;
+    } catch (const std::bad_alloc&) {
+        return fail(FBN_E_NOMEM_HOST, "out of host memory");
+    } catch (...) {
+        return fail(FBN_E_PARSE, "parse failure");
+    }
+}
+
+fbn_status fbn_load_net(const char* path, fbn_net** out) {
+    if (!path || !out) return fail(FBN_E_INVALID_ARG, "null argument");
+    std::ifstream f(path, std::ios::binary);
+    if (!f) return fail(FBN_E_IO, std::string("cannot open ") + path);
+    std::stringstream ss;
+    ss << f.rdbuf();
+    std::string s = ss.str();
+    return fbn_load_net_mem(s.data(), s.size(), out);
+}
+
+fbn_status fbn_net_from_arrays(int32_t n, const int32_t* card, const int32_t* npar, const int32_t* parents,
+                               const double* cpt, fbn_net** out) {
+    if (!out || n <= 0 || !card || !npar || !cpt) return fail(FBN_E_INVALID_ARG, "null or empty argument");
+    *out = nullptr;
+    try {
+        auto* h = new fbn_net();
+        Net& net = h->net;
+        net.n = n;
+        net.card.assign(card, card + n);
+        net.parents.assign((size_t)n, {});
+        net.cpt.assign((size_t)n, {});
+        size_t po = 0, co = 0;
+        for (int v = 0; v < n; v++) {
+            if (npar[v] < 0 || (npar[v] > 0 && !parents)) {
+                delete h;
+                return fail(FBN_E_INVALID_ARG, "bad parent count");
+            }
+            for (int k = 0; k < npar[v]; k++) net.parents[(size_t)v].push_back(parents[po + (size_t)k]);
+            po += (size_t)npar[v];
+        }
+        for (int v = 0; v < n; v++) {
+            uint64_t len = (uint64_t)std::max(card[v], 0);
+            for (int p : net.parents[(size_t)v]) {
+                if (p < 0 || p >= n) {
+                    delete h;
+                    return fail(FBN_E_INVALID_ARG, "bad parent id");
+                }
+                len *= (uint64_t)std::max(card[p], 0);
+            }
+            net.cpt[(size_t)v].assign(cpt + co, cpt + co + len);
+            co += len;
+        }
+        fbn_status st = check_net(net);
+        if (st) {
+            delete h;
+            return st;
+        }
+        *out = h;
+        return FBN_OK;
+    } catch (const std::bad_alloc&) {
+        return fail(FBN_E_NOMEM_HOST, "out of host memory");
+    }
+}
+
+void fbn_free_net(fbn_net* net) { delete net; }
+
+fbn_status fbn_build_jt(const fbn_net* net, const fbn_jt_options* opt_in, fbn_jt** out) {
+    if (!net || !out) return fail(FBN_E_INVALID_ARG, "null argument");
+    *out = nullptr;
+    fbn_jt_options opt;
+    if (opt_in) opt = *opt_in;
+    else fbn_default_options(&opt);
+    if (opt.max_slots < 1 || (opt.precision != FBN_FP64 && opt.precision != FBN_FP32_RESCALED) ||
+        opt.tile_entries < 0 || opt.tile_entries > kTileMax)
+        return fail(FBN_E_INVALID_ARG, "bad options");
+    if (opt.max_clique_entries == 0 || opt.max_clique_entries > 0x7fffffffull) opt.max_clique_entries = 0x7fffffffull;
+    fbn_jt* jt = nullptr;
+    try {
+        jt = new fbn_jt();
+        jt->opt = opt;
+        int code = 0;
+        std::string err = compile_tree(net->net, opt.max_clique_entries, jt->tree, code);
+        if (!err.empty()) {
+            delete jt;
+            return fail(code ? code : FBN_E_INVALID_ARG, err);
+        }
+        build_plan(jt->tree, opt.tile_entries ? opt.tile_entries : 2048, jt->plan);
+        const std::string bad = check_plan(jt->tree, jt->plan);
+        if (!bad.empty()) {
+            delete jt;
+            return fail(FBN_E_STATE, "internal plan check failed: " + bad);
+        }
+        jt->occ.assign((size_t)jt->tree.n, {});
+        for (int c = 0; c < jt->tree.nc; c++)
+            for (size_t k = 0; k < jt->tree.vars[(size_t)c].size(); k++)
+                jt->occ[(size_t)jt->tree.vars[(size_t)c][k]].push_back({c, (int)k});
+        jt->dirty.assign((size_t)opt.max_slots, 0);
+        if (!opt.host_only) {
+            fbn_status st = setup_device(jt);
+            if (st) {
+                std::string keep = g_err;
+                release(jt);
+                delete jt;
+                g_err = keep;
+                return st;
+            }
+        }
+        *out = jt;
+        return FBN_OK;
+    } catch (const std::bad_alloc&) {
+        if (jt) {
+            release(jt);
+            delete jt;
+        }
+        return fail(FBN_E_NOMEM_HOST, "out of host memory");
+    } catch (const std::exception& e) {
+        if (jt) {
+            release(jt);
+            delete jt;
+        }
+        return fail(FBN_E_TOO_LARGE, e.what());
+    }
+}
+
+void fbn_free_jt(fbn_jt* jt) {
+    if (!jt) return;
+    release(jt);
+    delete jt;
+}
+
+fbn_status fbn_set_stream(fbn_jt* jt, void* stream) {
+    if (!jt) return fail(FBN_E_INVALID_ARG, "null jt");
+    if (jt->opt.host_only) return fail(FBN_E_STATE, "host-only jt");
+    fbn_status st = wait_staged(jt);
+    if (st) return st;
+    HIP_OK(hipStreamSynchronize(jt->stream));
+    jt->stream = static_cast<hipStream_t>(stream);
+    jt->opt.stream = stream;
+    return FBN_OK;
+}
+
+fbn_status fbn_set_evidence(fbn_jt* jt, int32_t slot, int32_t n_obs, const int32_t* vars, const int32_t* states) {
+    if (!jt) return fail(FBN_E_INVALID_ARG, "null jt");
+    if (jt->opt.host_only) return fail(FBN_E_STATE, "host-only jt");
+    if (slot < 0 || slot >= jt->opt.max_slots) return fail(FBN_E_INVALID_ARG, "slot out of range");
+    if (n_obs < 0 || (n_obs > 0 && (!vars || !states))) return fail(FBN_E_INVALID_ARG, "bad evidence arrays");
+    const Tree& t = jt->tree;
+    std::vector<char> seen((size_t)t.n, 0);
+    for (int32_t k = 0; k < n_obs; k++) {
+        const int v = vars[k];
+        if (v < 0 || v >= t.n) return fail(FBN_E_INVALID_ARG, "evidence variable out of range");
+        if (seen[(size_t)v]) return fail(FBN_E_INVALID_ARG, "evidence variable repeated");
+        seen[(size_t)v] = 1;
+        if (states[k] < 0 || states[k] >= t.card[(size_t)v]) return fail(FBN_E_INVALID_ARG, "evidence state out of range");
+    }
+    fbn_status st = wait_staged(jt);
+    if (st) return st;
+    DEvidence* ev = jt->h_ev + (size_t)slot * jt->ctx.ev_stride;
+    std::memset(ev, 0, sizeof(DEvidence) * jt->ctx.ev_stride);
+    const Plan& p = jt->plan;
+    for (int32_t k = 0; k < n_obs; k++) {
+        const int v = vars[k];
+        uint32_t bits = 0;
+        while ((1u << bits) < (uint32_t)t.card[(size_t)v]) bits++;
+        for (const auto& cp : jt->occ[(size_t)v]) {
+            const uint32_t sh = p.dig_shift[p.dig_shift0[(size_t)cp.first] + (size_t)cp.second];
+            ev[cp.first].mask |= (((uint64_t)1 << bits) - 1) << sh;
+            ev[cp.first].want |= (uint64_t)states[k] << sh;
+        }
+    }
+    jt->dirty[(size_t)slot] = 1;
+    return FBN_OK;
+}
+
+fbn_status fbn_set_evidence_batch(fbn_jt* jt, int32_t n_slots, const int32_t* slots, const int32_t* offsets,
+                                  const int32_t* vars, const int32_t* states) {
+    if (!jt || n_slots < 0 || (n_slots > 0 && (!slots || !offsets))) return fail(FBN_E_INVALID_ARG, "bad arguments");
+    for (int32_t i = 0; i < n_slots; i++) {
+        if (offsets[i + 1] < offsets[i]) return fail(FBN_E_INVALID_ARG, "offsets not ascending");
+        fbn_status st = fbn_set_evidence(jt, slots[i], offsets[i + 1] - offsets[i], vars ? vars + offsets[i] : nullptr,
+                                         states ? states + offsets[i] : nullptr);
+        if (st) return st;
+    }
+    return FBN_OK;
+}
+
+fbn_status fbn_calibrate(fbn_jt* jt, int32_t n, const int32_t* slots, double* log_pe, fbn_status* per_slot) {
+    if (!jt) return fail(FBN_E_INVALID_ARG, "null jt");
+    if (jt->opt.host_only) return fail(FBN_E_STATE, "host-only jt");
+    fbn_status st = check_slots(jt, n, slots);
+    if (st) return st;
+    if (n == 0) return FBN_OK;
+    HIP_OK(hipSetDevice(jt->device));
+    if ((st = stage_slots(jt, n, slots))) return st;
+    const Ctx& c = jt->ctx;
+    const Plan& p = jt->plan;
+    const int prec = jt->opt.precision == FBN_FP32_RESCALED ? 1 : 0;
+    hipStream_t s = jt->stream;
+    // clear the per-slot flags of this batch
+    HIP_OK(launch_begin(c, jt->d_slots, n, s));
+    for (const Layer& ly : p.collect) {
+        HIP_OK(launch_collect(c, prec, jt->d_groups + ly.group0, ly.ngroup, jt->d_slots, n, s));
+        HIP_OK(launch_fin_collect(c, prec, jt->d_fins + ly.fin0, ly.nfin, jt->d_slots, n, s));
+    }
+    for (const Layer& ly : p.distribute) {
+        HIP_OK(launch_distribute(c, prec, jt->d_groups + ly.group0, ly.ngroup, jt->d_slots, n, s));
+        HIP_OK(launch_fin_distribute(c, prec, jt->d_fins + ly.fin0, ly.nfin, jt->d_slots, n, s));
+    }
+    HIP_OK(launch_marginals(c, jt->d_slots, n, s));
+    if (log_pe || per_slot) {
+        std::vector<double> lp((size_t)n);
+        std::vector<int32_t> fl((size_t)n);
+        if ((st = fetch(jt, n, nullptr, lp.data(), fl.data()))) return st;
+        HIP_OK(hipStreamSynchronize(s));
+        for (int32_t i = 0; i < n; i++) {
+            if (log_pe) log_pe[i] = lp[(size_t)i];
+            if (per_slot) per_slot[i] = status_of_flag(fl[(size_t)i]);
+        }
+    }
+    return FBN_OK;
+}
+
+fbn_status fbn_query_all(fbn_jt* jt, int32_t n, const int32_t* slots, double* out, size_t out_len, double* log_pe,
+                         fbn_status* per_slot) {
+    if (!jt) return fail(FBN_E_INVALID_ARG, "null jt");
+    if (jt->opt.host_only) return fail(FBN_E_STATE, "host-only jt");
+    fbn_status st = check_slots(jt, n, slots);
+    if (st) return st;
+    if (n == 0) return FBN_OK;
+    const size_t per = jt->ctx.marg_stride;
+    if (out && out_len < per * (size_t)n) return fail(FBN_E_INVALID_ARG, "output too small");
+    HIP_OK(hipSetDevice(jt->device));
+    if ((st = stage_slots(jt, n, slots))) return st;
+    std::vector<double> lp((size_t)n);
+    std::vector<int32_t> fl((size_t)n);
+    if ((st = fetch(jt, n, out, lp.data(), fl.data()))) return st;
+    HIP_OK(hipStreamSynchronize(jt->stream));
+    for (int32_t i = 0; i < n; i++) {
+        if (log_pe) log_pe[i] = lp[(size_t)i];
+        if (per_slot) per_slot[i] = status_of_flag(fl[(size_t)i]);
+    }
+    return FBN_OK;
+}
+
+fbn_status fbn_fetch_async(fbn_jt* jt, int32_t n, const int32_t* slots, double* post_out, double* log_pe_out,
+                           int32_t* flags_out) {
+    if (!jt) return fail(FBN_E_INVALID_ARG, "null jt");
+    if (jt->opt.host_only) return fail(FBN_E_STATE, "host-only jt");
+    fbn_status st = check_slots(jt, n, slots);
+    if (st) return st;
+    if (n == 0) return FBN_OK;
+    HIP_OK(hipSetDevice(jt->device));
+    if ((st = stage_slots(jt, n, slots))) return st;
+    return fetch(jt, n, post_out, log_pe_out, flags_out);
+}
+
+fbn_status fbn_query_marginals(fbn_jt* jt, int32_t slot, int32_t n_vars, const int32_t* vars, double* out,
+                               size_t out_len) {
+    if (!jt) return fail(FBN_E_INVALID_ARG, "null jt");
+    if (jt->opt.host_only) return fail(FBN_E_STATE, "host-only jt");
+    if (slot < 0 || slot >= jt->opt.max_slots) return fail(FBN_E_INVALID_ARG, "slot out of range");
+    if (n_vars < 0 || (n_vars > 0 && (!vars || !out))) return fail(FBN_E_INVALID_ARG, "bad arguments");
+    size_t need = 0;
+    for (int32_t k = 0; k < n_vars; k++) {
+        if (vars[k] < 0 || vars[k] >= jt->tree.n) return fail(FBN_E_INVALID_ARG, "variable out of range");
+        need += (size_t)jt->tree.card[(size_t)vars[k]];
+    }
+    if (out_len < need) return fail(FBN_E_INVALID_ARG, "output too small");
+    std::vector<double> all(jt->ctx.marg_stride);
+    double lp = 0.0;
+    fbn_status ps = FBN_OK;
+    fbn_status st = fbn_query_all(jt, 1, &slot, all.data(), all.size(), &lp, &ps);
+    if (st) return st;
+    if (ps) return fail(ps, fbn_status_str(ps));
+    size_t o = 0;
+    for (int32_t k = 0; k < n_vars; k++) {
+        const DHomeVar& h = jt->plan.homevars[(size_t)vars[k]];
+        for (uint32_t x = 0; x < h.card; x++) out[o++] = all[h.out + x];
+    }
+    return FBN_OK;
+}
+
+fbn_status fbn_jt_stats(const fbn_jt* jt, fbn_jt_stats_t* out) {
+    if (!jt || !out) return fail(FBN_E_INVALID_ARG, "null argument");
+    const Tree& t = jt->tree;
+    std::memset(out, 0, sizeof(*out));
+    out->n_vars = t.n;
+    out->n_cliques = t.nc;
+    out->n_edges = t.ne;
+    out->root = t.root;
+    out->H = t.height[(size_t)t.root];
+    for (int c = 0; c < t.nc; c++) {
+        out->D = std::max(out->D, t.depth[(size_t)c]);
+        out->T += t.size[(size_t)c];
+        out->max_clique = std::max(out->max_clique, t.size[(size_t)c]);
+    }
+    for (int e = 0; e < t.ne; e++) {
+        out->K += t.size[(size_t)t.e_parent[(size_t)e]];
+        out->sep_total += t.e_size[(size_t)e];
+    }
+    out->device_bytes = jt->device_bytes;
+    out->slot_bytes = jt->slot_bytes;
+    return FBN_OK;
+}
+
+fbn_status fbn_jt_clique(const fbn_jt* jt, int32_t c, int32_t* vars, int32_t cap, int32_t* n, int32_t* height,
+                         int32_t* depth) {
+    if (!jt || c < 0 || c >= jt->tree.nc) return fail(FBN_E_INVALID_ARG, "bad clique");
+    const auto& v = jt->tree.vars[(size_t)c];
+    for (int32_t k = 0; k < (int32_t)v.size() && k < cap && vars; k++) vars[k] = v[(size_t)k];
+    if (n) *n = (int32_t)v.size();
+    if (height) *height = jt->tree.height[(size_t)c];
+    if (depth) *depth = jt->tree.depth[(size_t)c];
+    return FBN_OK;
+}
+
+fbn_status fbn_jt_edge(const fbn_jt* jt, int32_t e, int32_t* parent, int32_t* child, int32_t* sep, int32_t cap,
+                       int32_t* n) {
+    if (!jt || e < 0 || e >= jt->tree.ne) return fail(FBN_E_INVALID_ARG, "bad edge");
+    if (parent) *parent = jt->tree.e_parent[(size_t)e];
+    if (child) *child = jt->tree.e_child[(size_t)e];
+    const auto& s = jt->tree.e_sep[(size_t)e];
+    for (int32_t k = 0; k < (int32_t)s.size() && k < cap && sep; k++) sep[k] = s[(size_t)k];
+    if (n) *n = (int32_t)s.size();
+    return FBN_OK;
+}
+
+static const DChild* child_record(const fbn_jt* jt, int32_t e, const DClique** parent) {
+    const int p = jt->tree.e_parent[(size_t)e];
+    const DClique& d = jt->plan.cliques[(size_t)p];
+    const auto& kids = jt->tree.children[(size_t)p];
+    for (size_t k = 0; k < kids.size(); k++)
+        if (jt->tree.pedge[(size_t)kids[k]] == e) {
+            *parent = &d;
+            return &jt->plan.children[d.child0 + k];
+        }
+    return nullptr;
+}
+
+fbn_status fbn_jt_index_map(const fbn_jt* jt, int32_t e, int32_t* out, size_t cap) {
+    if (!jt || !out || e < 0 || e >= jt->tree.ne) return fail(FBN_E_INVALID_ARG, "bad edge");
+    const DClique* d = nullptr;
+    const DChild* r = child_record(jt, e, &d);
+    if (!r) return fail(FBN_E_STATE, "edge record missing");
+    if (cap < d->size) return fail(FBN_E_INVALID_ARG, "output too small");
+    const auto& m = jt->plan.maps;
+    for (uint32_t j = 0; j < d->size; j++) out[j] = (int32_t)(m[r->mh + j / d->L] + m[r->ml + j % d->L]);
+    return FBN_OK;
+}
+
+fbn_status fbn_jt_device_index_map(fbn_jt* jt, int32_t e, int32_t* out, size_t cap) {
+    if (!jt || !out || e < 0 || e >= jt->tree.ne) return fail(FBN_E_INVALID_ARG, "bad edge");
+    if (jt->opt.host_only) return fail(FBN_E_STATE, "host-only jt");
+    const DClique* d = nullptr;
+    const DChild* r = child_record(jt, e, &d);
+    if (!r) return fail(FBN_E_STATE, "edge record missing");
+    if (cap < d->size) return fail(FBN_E_INVALID_ARG, "output too small");
+    HIP_OK(hipSetDevice(jt->device));
+    int32_t* tmp = nullptr;
+    HIP_OK(hipMalloc(&tmp, 4ull * d->size));
+    hipError_t err = launch_expand_map(jt->d_map, r->mh, r->ml, d->L, d->Lmul, d->Lsh, d->size, tmp, jt->stream);
+    if (err == hipSuccess) err = hipMemcpyAsync(out, tmp, 4ull * d->size, hipMemcpyDeviceToHost, jt->stream);
+    if (err == hipSuccess) err = hipStreamSynchronize(jt->stream);
+    hipFree(tmp);
+    if (err != hipSuccess) return fail(FBN_E_DEVICE, hipGetErrorString(err));
+    return FBN_OK;
+}
+
+fbn_status fbn_jt_elim_order(const fbn_jt* jt, int32_t* order) {
+    if (!jt || !order) return fail(FBN_E_INVALID_ARG, "null argument");
+    for (int v = 0; v < jt->tree.n; v++) order[v] = jt->tree.elim_order[(size_t)v];
+    return FBN_OK;
+}
+
+fbn_status fbn_jt_homes(const fbn_jt* jt, int32_t* cpt_home, int32_t* var_home) {
+    if (!jt) return fail(FBN_E_INVALID_ARG, "null jt");
+    for (int v = 0; v < jt->tree.n; v++) {
+        if (cpt_home) cpt_home[v] = jt->tree.cpt_home[(size_t)v];
+        if (var_home) var_home[v] = jt->tree.var_home[(size_t)v];
+    }
+    return FBN_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,128 @@
+// Internal types of the junction-tree library: the host-side network and
+// tree, and the plain-old-data plan records read by the HIP kernels.
+#pragma once
+
+#include <cstdint>
+#include <string>
+#include <vector>
+
+namespace fbn {
+
+// ---------------------------------------------------------------- host model
+
+// A discrete Bayesian network: a DAG with one CPT per variable, parents in
+// listed order and the variable itself fastest (paper, Section 1).
+struct Net {
+    int n = 0;
+    std::vector<int> card;
+    std::vector<std::vector<int>> parents;
+    std::vector<std::vector<double>> cpt;  // empty vectors: structure only
+};
+
+// The compiled junction tree (paper, Section 1: cliques and separators with
+// potential tables; Section 2: layers and root selection).
+struct Tree {
+    int n = 0;
+    std::vector<int> card;
+    std::vector<int> elim_order;
+    int nc = 0;                                  // cliques
+    std::vector<std::vector<int>> vars;          // table layout order
+    std::vector<uint64_t> size;                  // entries per clique
+    int root = 0;
+    std::vector<int> parent, pedge, height, depth;
+    std::vector<std::vector<int>> children;      // ascending id
+    int ne = 0;                                  // edges, by ascending child id
+    std::vector<int> e_parent, e_child;
+    std::vector<std::vector<int>> e_sep;         // ascending variable id
+    std::vector<uint64_t> e_size;
+    std::vector<int> cpt_home, var_home;
+    std::vector<std::vector<double>> prior;      // per clique, layout order, unscaled
+};
+
+// Returns an empty string on success, else the error text.  code receives
+// an fbn_status value.
+std::string compile_tree(const Net& net, uint64_t max_entries, Tree& out, int& code);
+
+// ---------------------------------------------------------------- plan records
+
+// One clique as the kernels see it.  Entry i of the table splits as
+// i = hi * L + lo, where L is the product of the trailing (fastest)
+// variables' cardinalities; every separator index is additive in the
+// digits, so each index map is stored factored as H[hi] + L[lo].
+struct DClique {
+    uint64_t off;        // first entry in the prior / working-table arena
+    uint32_t size;       // entries (< 2^31)
+    uint32_t L;          // low extent
+    uint32_t Lmul, Lsh;  // hi = ((umulhi(i, Lmul) + i) >> Lsh) == i / L
+    uint32_t hdig, ldig; // offsets of the packed-digit tables (uint64 pool)
+    int32_t pedge;       // edge to the parent, -1 at the root
+    uint32_t psep;       // separator-arena offset of the parent separator (root: virtual entry)
+    uint32_t pmh, pml;   // parent-map tables (uint32 pool): entry -> parent separator index
+    uint32_t seg;        // size / |parent separator| (root: size)
+    uint32_t child0;     // first DChild record
+    uint32_t home0;      // first DHome record
+    uint16_t nchild, nhome;
+    uint32_t pad;
+};
+
+// A child edge seen from its parent clique: where its separator lives and
+// the factored index map from parent entries to separator entries.
+struct DChild {
+    uint32_t sep;        // separator-arena offset
+    uint32_t mh, ml;     // map tables (uint32 pool)
+    uint32_t size;       // separator entries
+};
+
+// A variable whose posterior is read from this clique.
+struct DHome {
+    uint32_t out;        // offset of its first state in the per-slot marginal arrays
+    uint32_t shift;      // bit position of its digit in the packed digits
+    uint32_t mask;       // (1 << bits) - 1
+    uint32_t card;
+};
+
+// A contiguous run of one clique's entries handled inside a workgroup.
+struct DPiece {
+    uint32_t clique;
+    uint32_t begin;      // first entry within the clique
+    uint32_t count;
+    uint32_t gofs;       // offset of the run inside the workgroup's tile
+};
+
+// The work of one workgroup in one layer: a packed list of runs.  In a
+// collect layer, a "full" group holds whole parent-separator segments; a
+// "part" group holds one chunk of a single segment too long for one tile,
+// and writes its partial sum to the partial-sum arena.
+struct DGroup {
+    uint32_t piece0;
+    uint32_t npiece;
+    uint32_t total;      // entries in the tile
+    int32_t part;        // partial-sum index, or -1 for a full group
+};
+
+// Separator finalisation after a layer: one record per separator (the
+// root's virtual one-entry separator included, with edge = -1).
+struct DSepFin {
+    uint32_t sep;        // separator-arena offset
+    uint32_t size;
+    uint32_t part0;      // first partial (segment m, chunk c at part0 + m*nchunk + c)
+    uint32_t nchunk;     // 0: the collect kernel wrote whole sums
+    int32_t edge;        // edge id, -1 for the root
+    uint32_t pad;
+};
+
+// Per-slot evidence for one clique: entry i survives the reduction when
+// ((digits(i) ^ want) & mask) == 0.
+struct DEvidence {
+    uint64_t want, mask;
+};
+
+struct DHomeVar {        // for the posterior finaliser: one per variable
+    uint32_t out, card;
+};
+
+constexpr int kBlock = 256;       // threads per workgroup
+constexpr int kTileMax = 4096;    // entries per workgroup tile
+constexpr int kMaxPieces = 64;    // runs per workgroup
+
+}  // namespace fbn

@@ -1,0 +1,54 @@
+// Launch interface of the layer kernels (implemented in kernels.hip).
+#pragma once
+
+#include <hip/hip_runtime_api.h>
+
+#include "fbn_internal.h"
+
+namespace fbn {
+
+// Device pointers and per-slot strides for one junction tree.  Per-slot
+// arrays are slot-major: slot s starts at base + s * stride.
+struct Ctx {
+    const DClique* cl;
+    const DChild* ch;
+    const DHome* hm;
+    const DPiece* pc;
+    const DHomeVar* hv;
+    const uint64_t* dig;
+    const uint32_t* map;
+    const void* prior;     // T
+    void* psi;             // T, working tables (psi_stride)
+    void* sepc;            // T, collect messages, rescaled (sep_stride)
+    void* sepd;            // T, distribute ratios, rescaled (sep_stride)
+    double* acc;           // float64 separator accumulators (sep_stride)
+    double* part;          // float64 partial sums (part_stride)
+    int32_t* kexp;         // collect rescale exponents (kexp_stride)
+    double* marg;          // float64 marginal accumulators (marg_stride)
+    double* post;          // float64 posteriors (marg_stride)
+    double* logpe;         // per slot
+    int32_t* flags;        // per slot: bit 0 zero evidence, bit 1 FP32 underflow
+    const DEvidence* ev;   // ev_stride per slot
+    uint64_t psi_stride;
+    uint32_t sep_stride, part_stride, kexp_stride, marg_stride, ev_stride;
+    int32_t nvars, ne, kappa_total, fp32;
+};
+
+// prec: 0 = float64 tables, 1 = float32 tables
+hipError_t launch_collect(const Ctx& c, int prec, const DGroup* groups, uint32_t ngroups,
+                          const int32_t* slots, int nslots, hipStream_t s);
+hipError_t launch_fin_collect(const Ctx& c, int prec, const DSepFin* fins, uint32_t nfins,
+                              const int32_t* slots, int nslots, hipStream_t s);
+hipError_t launch_distribute(const Ctx& c, int prec, const DGroup* groups, uint32_t ngroups,
+                             const int32_t* slots, int nslots, hipStream_t s);
+hipError_t launch_fin_distribute(const Ctx& c, int prec, const DSepFin* fins, uint32_t nfins,
+                                 const int32_t* slots, int nslots, hipStream_t s);
+hipError_t launch_marginals(const Ctx& c, const int32_t* slots, int nslots, hipStream_t s);
+hipError_t launch_gather(const Ctx& c, const int32_t* slots, int nslots, double* post_out,
+                         double* logpe_out, int32_t* flags_out, hipStream_t s);
+hipError_t launch_begin(const Ctx& c, const int32_t* slots, int nslots, hipStream_t s);
+hipError_t launch_expand_map(const uint32_t* map, uint32_t mh, uint32_t ml, uint32_t L, uint32_t Lmul,
+                             uint32_t Lsh, uint32_t n, int32_t* out, hipStream_t s);
+hipError_t launch_zero(void* p, size_t bytes, hipStream_t s);
+
+}  // namespace fbn

@@ -1,0 +1,51 @@
+// Device plan: everything the layer kernels read, laid out on the host and
+// uploaded once per network.
+#pragma once
+
+#include "fbn_internal.h"
+
+namespace fbn {
+
+struct Layer {
+    uint32_t group0 = 0, ngroup = 0;  // into Plan::groups
+    uint32_t fin0 = 0, nfin = 0;      // into Plan::fins (separators finalised after it)
+};
+
+struct Plan {
+    int tile = 2048;
+    uint64_t T = 0;                   // prior / working-table entries
+    uint32_t sep_total = 0;           // separator entries over all edges
+    uint32_t sep_stride = 0;          // per slot: sep_total + 1 (root's virtual entry) rounded
+    uint32_t n_parts = 0;             // partial sums per slot
+    uint32_t marg_total = 0;          // sum of cardinalities
+    int kappa_total = 0;              // sum of clique prior exponents
+    std::vector<DClique> cliques;
+    std::vector<DChild> children;
+    std::vector<DHome> homes;
+    std::vector<DHomeVar> homevars;   // per variable
+    std::vector<DPiece> pieces;
+    std::vector<DGroup> groups;
+    std::vector<DSepFin> fins;
+    std::vector<Layer> collect;       // by height 0..H
+    std::vector<Layer> distribute;    // by depth 0..D
+    std::vector<uint64_t> digits;     // packed-digit tables
+    std::vector<uint32_t> maps;       // factored index maps
+    std::vector<double> prior;        // scaled by 2^-kappa_c per clique, arena order
+    std::vector<int> kappa;           // per clique
+    std::vector<uint32_t> sep_off;    // per edge
+    std::vector<uint32_t> dig_shift;  // per clique, per layout position: bit shift
+    std::vector<uint32_t> dig_shift0; // start of each clique's entries in dig_shift
+};
+
+void build_plan(const Tree& t, int tile, Plan& p);
+
+// Checks, on the host, every bound the kernels rely on: tile and run sizes,
+// run alignment to separator segments, table offsets and every value of the
+// factored maps and packed digits.  Returns "" or the first violation.
+std::string check_plan(const Tree& t, const Plan& p);
+
+// Magic numbers for unsigned division by d of numerators below 2^31
+// (Granlund and Montgomery, 1994): q = (umulhi(n, mul) + n) >> sh.
+void magic_u32(uint32_t d, uint32_t& mul, uint32_t& sh);
+
+}  // namespace fbn

@@ -1,0 +1,156 @@
+"""CPU tests of the library's host side (no GPU needed).
+
+The junction tree the library compiles (cliques, layouts, edges,
+separators, root, layers, homes) and every index map must equal the
+oracle's bit for bit on the same network: the structure is a deterministic
+function of the network under the fixed tie-breaks of both implementations,
+and the two share no code.
+"""
+import ctypes
+import os
+import re
+
+import numpy as np
+import pytest
+from hypothesis import given, settings, strategies as st, HealthCheck
+
+import fbngen
+import oracle
+from paper_2212_04241_amd import fbn
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _host_jt(net, **kw):
+    return fbn.JT(fbn.net_from_spec(net), host_only=True, **kw)
+
+
+def compare_structure(net, ojt, ljt, maps="all"):
+    s = ljt.stats
+    assert (s["n_cliques"], s["n_edges"], s["root"], s["H"], s["D"]) == \
+        (ojt.n_cliques, ojt.n_edges, ojt.root, ojt.H, ojt.D)
+    assert (s["T"], s["K"], s["max_clique"]) == (ojt.T, ojt.K, ojt.max_clique)
+    assert np.array_equal(fbn.jt_elim_order(ljt), ojt.elim_order())
+    for c in range(ojt.n_cliques):
+        lv, lh, ld = fbn.jt_clique(ljt, c)
+        ov, oh, od = ojt.clique(c)
+        assert np.array_equal(lv, ov) and (lh, ld) == (oh, od), c
+    la, lb = fbn.jt_homes(ljt)
+    oa, ob = ojt.homes()
+    assert np.array_equal(la, oa) and np.array_equal(lb, ob)
+    edges = range(ojt.n_edges) if maps == "all" else maps
+    for e in range(ojt.n_edges):
+        lp, lc, ls = fbn.jt_edge(ljt, e)
+        op, oc, os_ = ojt.edge(e)
+        assert (lp, lc) == (op, oc) and np.array_equal(ls, os_), e
+    for e in edges:
+        assert np.array_equal(fbn.jt_index_map(ljt, e, net.card), ojt.index_map(e)), e
+
+
+@settings(max_examples=60, deadline=None, suppress_health_check=[HealthCheck.too_slow])
+@given(seed=st.integers(0, 2**31 - 1), n=st.integers(1, 40), max_card=st.integers(2, 5),
+       p_max=st.integers(0, 4), window=st.sampled_from([None, 3, 8]))
+def test_structure_and_maps_bit_exact_random(seed, n, max_card, p_max, window):
+    net = fbngen.random_small_net(seed, n, max_card=max_card, p_max=p_max, window=window)
+    try:
+        ojt = oracle.compile_net(net, max_entries=1 << 22)
+    except oracle.OracleError:
+        with pytest.raises(fbn.FbnError):
+            _host_jt(net, max_clique_entries=1 << 22)
+        return
+    compare_structure(net, ojt, _host_jt(net, max_clique_entries=1 << 22))
+
+
+@pytest.mark.parametrize("key", ["C1", "C2"])
+def test_structure_and_maps_bit_exact_workloads(key):
+    net = fbngen.make_net(key, 0)
+    compare_structure(net, oracle.compile_net(net), _host_jt(net))
+
+
+def test_structure_bit_exact_hub_workload():
+    # the ~10^7-entry clique network: structure in full, maps of a few edges
+    net = fbngen.make_net("C3", 0, with_cpts=False)
+    ojt = oracle.compile_net(net, structure_only=True)
+    ljt = _host_jt(fbngen.Net(net.card, net.parents, [np.ones(net.cpt_size(v)) / net.card[v]
+                                                      for v in range(net.n)]))
+    sizes = [(ojt.clique_size(ojt.edge(e)[0]), e) for e in range(ojt.n_edges)]
+    pick = [e for _, e in sorted(sizes)[:6]] + [max(sizes)[1]]
+    compare_structure(net, ojt, ljt, maps=pick)
+
+
+def test_text_and_arrays_give_same_tree():
+    net = fbngen.random_small_net(5, 12, max_card=4)
+    a = fbn.JT(fbn.load_net_mem(net.to_text()), host_only=True)
+    b = _host_jt(net)
+    for c in range(a.stats["n_cliques"]):
+        assert np.array_equal(fbn.jt_clique(a, c)[0], fbn.jt_clique(b, c)[0])
+
+
+# ---------------------------------------------------------------- ABI surface
+
+def test_library_exports_every_declared_symbol():
+    with open(os.path.join(ROOT, "include", "fbn.h")) as f:
+        hdr = f.read()
+    names = sorted(set(re.findall(r"\b(fbn_[a-z_0-9]+)\s*\(", hdr)))
+    assert "fbn_calibrate" in names and "fbn_build_jt" in names
+    L = ctypes.CDLL(fbn.LIB_PATH)
+    missing = [n for n in names if not hasattr(L, n)]
+    assert not missing, missing
+
+
+@pytest.mark.parametrize("text,code", [
+    ("fbn 1\nvars 2\nvar 0 2 1 1\nvar 1 2 1 0\ncpt 0 4\n.5 .5 .5 .5\ncpt 1 4\n.5 .5 .5 .5\nend\n", fbn.FBN_E_INVALID_ARG),
+    ("fbn 1\nvars 1\nvar 0 1 0\ncpt 0 1\n1\nend\n", fbn.FBN_E_INVALID_ARG),
+    ("fbn 1\nvars 1\nvar 0 2 0\ncpt 0 2\n0.5 0.6\nend\n", fbn.FBN_E_INVALID_ARG),
+    ("fbn 1\nvars 1\nvar 0 2 0\ncpt 0 2\n0.5\nend\n", fbn.FBN_E_PARSE),
+    ("fbn 2\nvars 1\n", fbn.FBN_E_PARSE),
+    ("fbn 1\nvars 1\nvar 0 2 0\ncpt 0 2\n0.5 0.5\n", fbn.FBN_E_PARSE),
+])
+def test_library_rejects_bad_networks(text, code):
+    with pytest.raises(fbn.FbnError) as ei:
+        fbn.load_net_mem(text)
+    assert ei.value.code == code
+
+
+def test_missing_file_is_io_error():
+    with pytest.raises(fbn.FbnError) as ei:
+        fbn.load_net("/nonexistent/x.fbn")
+    assert ei.value.code == fbn.FBN_E_IO
+
+
+def test_too_large_clique_rejected():
+    net = fbngen.make_net("C1", 0)
+    with pytest.raises(fbn.FbnError) as ei:
+        _host_jt(net, max_clique_entries=16)
+    assert ei.value.code == fbn.FBN_E_TOO_LARGE
+
+
+def test_host_only_jt_refuses_device_calls():
+    jt = _host_jt(fbngen.make_net("C1", 0))
+    for call in (lambda: fbn.set_evidence(jt, 0, [0], [0]), lambda: fbn.calibrate(jt, [0])):
+        with pytest.raises(fbn.FbnError) as ei:
+            call()
+        assert ei.value.code == fbn.FBN_E_STATE
+
+
+def test_bad_options_rejected():
+    net = fbn.net_from_spec(fbngen.make_net("C1", 0))
+    for kw in ({"max_slots": 0}, {"precision": 7}, {"tile_entries": 1 << 20}):
+        with pytest.raises(fbn.FbnError) as ei:
+            fbn.JT(net, host_only=True, **kw)
+        assert ei.value.code == fbn.FBN_E_INVALID_ARG
+
+
+@pytest.mark.parametrize("tile", [1, 7, 64, 100, 333, 2048, 4096])
+@pytest.mark.parametrize("key", ["C1", "C2"])
+def test_plan_bounds_check_passes_for_any_tile(key, tile):
+    # the build runs the plan checker (every kernel index bound) and fails
+    # with FBN_E_STATE if any bound is violated
+    _host_jt(fbngen.make_net(key, 0), tile_entries=tile)
+
+
+@settings(max_examples=40, deadline=None, suppress_health_check=[HealthCheck.too_slow])
+@given(seed=st.integers(0, 2**31 - 1), n=st.integers(1, 30), tile=st.sampled_from([1, 5, 64, 129, 2048]))
+def test_plan_bounds_check_random(seed, n, tile):
+    net = fbngen.random_small_net(seed, n, max_card=6, p_max=3, window=5)
+    _host_jt(net, tile_entries=tile, max_clique_entries=1 << 24)
