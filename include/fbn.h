@@ -149,6 +149,18 @@ fbn_status fbn_query_all(fbn_jt* jt, int32_t n_slots, const int32_t* slots, doub
 fbn_status fbn_fetch_async(fbn_jt* jt, int32_t n_slots, const int32_t* slots, double* post_out,
                            double* log_pe_out, int32_t* flags_out);
 
+/* --- kernel timing ----------------------------------------------------------
+ * When enabled, every kernel launch of fbn_calibrate is bracketed by HIP
+ * events on the jt's stream.  fbn_jt_profile_read waits for the stream and
+ * returns, per kernel kind (0 collect layer, 1 collect separator finalise,
+ * 2 distribute layer, 3 distribute separator finalise, 4 posteriors), the
+ * summed milliseconds, launch count and algorithmic bytes (table entries
+ * each layer must read or write, times the entry width, times slots), then
+ * resets the counters.  Arrays have FBN_PROFILE_KINDS entries. */
+enum { FBN_PROFILE_KINDS = 5 };
+fbn_status fbn_jt_profile_enable(fbn_jt* jt, int32_t on);
+fbn_status fbn_jt_profile_read(fbn_jt* jt, double* ms, int64_t* launches, double* bytes);
+
 const char* fbn_status_str(fbn_status s);
 const char* fbn_last_error(void);
 

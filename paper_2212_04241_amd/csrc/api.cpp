@@ -186,7 +186,9 @@ struct fbn_jt {
     // device plan
     DClique* d_cl = nullptr;
     DChild* d_ch = nullptr;
-    DHome* d_hm = nullptr;
+    DTarget* d_tg = nullptr;
+    DMargVar* d_mv = nullptr;
+    DWork* d_works = nullptr;
     DPiece* d_pc = nullptr;
     DHomeVar* d_hv = nullptr;
     DGroup* d_groups = nullptr;
@@ -221,6 +223,19 @@ struct fbn_jt {
     std::vector<std::vector<std::pair<int, int>>> occ;
     Ctx ctx{};
     uint64_t device_bytes = 0, slot_bytes = 0;
+    // kernel timing
+    struct Rec {
+        hipEvent_t a, b;
+        int kind;
+        double bytes;
+    };
+    bool prof = false;
+    std::vector<Rec> recs;
+    std::vector<hipEvent_t> pool;
+    double prof_ms[FBN_PROFILE_KINDS] = {}, prof_bytes[FBN_PROFILE_KINDS] = {};
+    int64_t prof_n[FBN_PROFILE_KINDS] = {};
+    // per layer: table entries, and separator entries finalised after it
+    std::vector<uint64_t> coll_entries, coll_sep, dist_entries, dist_sep;
 };
 
 namespace {
@@ -252,6 +267,13 @@ void release(fbn_jt* jt) {
             }
         }
         if (jt->staged) hipEventDestroy(jt->staged);
+        for (auto& r : jt->recs) {
+            hipEventDestroy(r.a);
+            hipEventDestroy(r.b);
+        }
+        for (hipEvent_t e : jt->pool) hipEventDestroy(e);
+        jt->recs.clear();
+        jt->pool.clear();
     }
     jt->allocs.clear();
     if (jt->h_pinned) {
@@ -292,7 +314,9 @@ fbn_status setup_device(fbn_jt* jt) {
     fbn_status st;
     if ((st = upload(jt, p.cliques, jt->d_cl))) return st;
     if ((st = upload(jt, p.children, jt->d_ch))) return st;
-    if ((st = upload(jt, p.homes, jt->d_hm))) return st;
+    if ((st = upload(jt, p.targets, jt->d_tg))) return st;
+    if ((st = upload(jt, p.margvars, jt->d_mv))) return st;
+    if ((st = upload(jt, p.works, jt->d_works))) return st;
     if ((st = upload(jt, p.pieces, jt->d_pc))) return st;
     if ((st = upload(jt, p.homevars, jt->d_hv))) return st;
     if ((st = upload(jt, p.groups, jt->d_groups))) return st;
@@ -354,7 +378,8 @@ fbn_status setup_device(fbn_jt* jt) {
     Ctx& c = jt->ctx;
     c.cl = jt->d_cl;
     c.ch = jt->d_ch;
-    c.hm = jt->d_hm;
+    c.tg = jt->d_tg;
+    c.mv = jt->d_mv;
     c.pc = jt->d_pc;
     c.hv = jt->d_hv;
     c.dig = jt->d_dig;
@@ -413,6 +438,29 @@ fbn_status stage_slots(fbn_jt* jt, int32_t n, const int32_t* slots) {
     }
     HIP_OK(hipEventRecord(jt->staged, jt->stream));
     jt->staged_pending = true;
+    return FBN_OK;
+}
+
+template <class F>
+fbn_status timed(fbn_jt* jt, int kind, double bytes, F launch) {
+    if (!jt->prof) {
+        HIP_OK(launch());
+        return FBN_OK;
+    }
+    hipEvent_t ev[2];
+    for (int k = 0; k < 2; k++) {
+        if (jt->pool.empty()) {
+            hipEvent_t e;
+            HIP_OK(hipEventCreate(&e));
+            jt->pool.push_back(e);
+        }
+        ev[k] = jt->pool.back();
+        jt->pool.pop_back();
+    }
+    HIP_OK(hipEventRecord(ev[0], jt->stream));
+    HIP_OK(launch());
+    HIP_OK(hipEventRecord(ev[1], jt->stream));
+    jt->recs.push_back({ev[0], ev[1], kind, bytes});
     return FBN_OK;
 }
 
@@ -569,6 +617,23 @@ fbn_status fbn_build_jt(const fbn_net* net, const fbn_jt_options* opt_in, fbn_jt
             delete jt;
             return fail(FBN_E_STATE, "internal plan check failed: " + bad);
         }
+        {
+            const Tree& t = jt->tree;
+            const Plan& p = jt->plan;
+            jt->coll_entries.assign(p.collect.size(), 0);
+            jt->dist_entries.assign(p.distribute.size(), 0);
+            for (int c = 0; c < t.nc; c++) {
+                jt->coll_entries[(size_t)t.height[(size_t)c]] += t.size[(size_t)c];
+                jt->dist_entries[(size_t)t.depth[(size_t)c]] += t.size[(size_t)c];
+            }
+            auto sep_sum = [&](const std::vector<Layer>& ls, std::vector<uint64_t>& out) {
+                out.assign(ls.size(), 0);
+                for (size_t k = 0; k < ls.size(); k++)
+                    for (uint32_t f = ls[k].fin0; f < ls[k].fin0 + ls[k].nfin; f++) out[k] += p.fins[f].size;
+            };
+            sep_sum(p.collect, jt->coll_sep);
+            sep_sum(p.distribute, jt->dist_sep);
+        }
         jt->occ.assign((size_t)jt->tree.n, {});
         for (int c = 0; c < jt->tree.nc; c++)
             for (size_t k = 0; k < jt->tree.vars[(size_t)c].size(); k++)
@@ -677,15 +742,33 @@ fbn_status fbn_calibrate(fbn_jt* jt, int32_t n, const int32_t* slots, double* lo
     hipStream_t s = jt->stream;
     // clear the per-slot flags of this batch
     HIP_OK(launch_begin(c, jt->d_slots, n, s));
-    for (const Layer& ly : p.collect) {
-        HIP_OK(launch_collect(c, prec, jt->d_groups + ly.group0, ly.ngroup, jt->d_slots, n, s));
-        HIP_OK(launch_fin_collect(c, prec, jt->d_fins + ly.fin0, ly.nfin, jt->d_slots, n, s));
+    const double w = prec ? 4.0 : 8.0, nb = (double)n;
+    for (size_t h = 0; h < p.collect.size(); h++) {
+        const Layer& ly = p.collect[h];
+        // reads the prior, writes the working table
+        if ((st = timed(jt, 0, 2.0 * w * nb * (double)jt->coll_entries[h], [&] {
+                 return launch_collect(c, prec, jt->d_groups + ly.group0, ly.ngroup, jt->d_slots, n, s);
+             })))
+            return st;
+        if ((st = timed(jt, 1, 2.0 * w * nb * (double)jt->coll_sep[h], [&] {
+                 return launch_fin_collect(c, prec, jt->d_fins + ly.fin0, ly.nfin, jt->d_slots, n, s);
+             })))
+            return st;
     }
-    for (const Layer& ly : p.distribute) {
-        HIP_OK(launch_distribute(c, prec, jt->d_groups + ly.group0, ly.ngroup, jt->d_slots, n, s));
-        HIP_OK(launch_fin_distribute(c, prec, jt->d_fins + ly.fin0, ly.nfin, jt->d_slots, n, s));
+    for (size_t d = 0; d < p.distribute.size(); d++) {
+        const Layer& ly = p.distribute[d];
+        // reads the working table
+        if ((st = timed(jt, 2, w * nb * (double)jt->dist_entries[d], [&] {
+                 return launch_distribute(c, prec, jt->d_works + ly.group0, ly.ngroup, jt->d_slots, n, s);
+             })))
+            return st;
+        if ((st = timed(jt, 3, 2.0 * w * nb * (double)jt->dist_sep[d], [&] {
+                 return launch_fin_distribute(c, prec, jt->d_fins + ly.fin0, ly.nfin, jt->d_slots, n, s);
+             })))
+            return st;
     }
-    HIP_OK(launch_marginals(c, jt->d_slots, n, s));
+    if ((st = timed(jt, 4, 16.0 * nb * (double)c.marg_stride, [&] { return launch_marginals(c, jt->d_slots, n, s); })))
+        return st;
     if (log_pe || per_slot) {
         std::vector<double> lp((size_t)n);
         std::vector<int32_t> fl((size_t)n);
@@ -842,6 +925,37 @@ fbn_status fbn_jt_device_index_map(fbn_jt* jt, int32_t e, int32_t* out, size_t c
     if (err == hipSuccess) err = hipStreamSynchronize(jt->stream);
     hipFree(tmp);
     if (err != hipSuccess) return fail(FBN_E_DEVICE, hipGetErrorString(err));
+    return FBN_OK;
+}
+
+fbn_status fbn_jt_profile_enable(fbn_jt* jt, int32_t on) {
+    if (!jt) return fail(FBN_E_INVALID_ARG, "null jt");
+    if (jt->opt.host_only) return fail(FBN_E_STATE, "host-only jt");
+    jt->prof = on != 0;
+    return FBN_OK;
+}
+
+fbn_status fbn_jt_profile_read(fbn_jt* jt, double* ms, int64_t* launches, double* bytes) {
+    if (!jt) return fail(FBN_E_INVALID_ARG, "null jt");
+    if (jt->opt.host_only) return fail(FBN_E_STATE, "host-only jt");
+    HIP_OK(hipStreamSynchronize(jt->stream));
+    for (auto& r : jt->recs) {
+        float t = 0.f;
+        HIP_OK(hipEventElapsedTime(&t, r.a, r.b));
+        jt->prof_ms[r.kind] += (double)t;
+        jt->prof_bytes[r.kind] += r.bytes;
+        jt->prof_n[r.kind] += 1;
+        jt->pool.push_back(r.a);
+        jt->pool.push_back(r.b);
+    }
+    jt->recs.clear();
+    for (int k = 0; k < FBN_PROFILE_KINDS; k++) {
+        if (ms) ms[k] = jt->prof_ms[k];
+        if (launches) launches[k] = jt->prof_n[k];
+        if (bytes) bytes[k] = jt->prof_bytes[k];
+        jt->prof_ms[k] = jt->prof_bytes[k] = 0.0;
+        jt->prof_n[k] = 0;
+    }
     return FBN_OK;
 }
 

@@ -101,14 +101,50 @@ struct DGroup {
 };
 
 // Separator finalisation after a layer: one record per separator (the
-// root's virtual one-entry separator included, with edge = -1).
+// root's virtual one-entry separator included, with edge = -1; in the
+// distribute sweep also one-variable virtual separators, edge = -2, which
+// carry the posterior of a variable that lies in no real separator).
 struct DSepFin {
     uint32_t sep;        // separator-arena offset
     uint32_t size;
-    uint32_t part0;      // first partial (segment m, chunk c at part0 + m*nchunk + c)
-    uint32_t nchunk;     // 0: the collect kernel wrote whole sums
-    int32_t edge;        // edge id, -1 for the root
+    uint32_t part0;      // first partial (entry m, chunk c at part0 + m*nchunk + c)
+    uint32_t nchunk;     // 0: the layer kernel wrote whole sums
+    int32_t edge;        // edge id, -1 root, -2 virtual
+    uint32_t mv0, nmv;   // posterior variables read from this separator
     uint32_t pad;
+};
+
+// A variable whose posterior is the marginal of a calibrated separator.
+struct DMargVar {
+    uint32_t out;        // offset of its first state in the per-slot marginal arrays
+    uint32_t stride;     // stride of the variable in the separator layout
+    uint32_t card;
+    uint32_t pad;
+};
+
+// Distribute-sweep marginalisation of clique C onto a target separator S
+// (S's variables kept, the rest summed).  With C's entries as rows of L
+// (i = row * L + lo):
+//   target groups g < G enumerate the digits of S's variables among the row
+//   variables; the rows of group g are RG[g] + RQ[k], k < NQ;
+//   within a row, output t < nPL gathers the lo offsets LP[t] + LQ[u], u < nQL;
+//   output (g, t) is separator entry TB[g] + TV[t].
+struct DTarget {
+    uint32_t clique;
+    uint32_t G, NQ, nPL, nQL;
+    uint32_t rg, rq, tb, lp, lq, tv;  // uint32 pool offsets
+    uint32_t sep;        // separator-arena offset of S
+    int32_t part0;       // partial sums of S when a group's rows span work items, else -1
+    uint32_t nchunk;
+};
+
+// One workgroup of the distribute gather: groups [g0, g0+ng) x rows
+// [k0, k0+nk) of one target, at most one tile of entries.
+struct DWork {
+    uint32_t target;
+    uint32_t g0, ng, k0, nk;
+    uint32_t nkmul, nksh;  // division by nk
+    uint32_t chunk;        // k0 / nk
 };
 
 // Per-slot evidence for one clique: entry i survives the reduction when

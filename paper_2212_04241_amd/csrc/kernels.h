@@ -12,7 +12,8 @@ namespace fbn {
 struct Ctx {
     const DClique* cl;
     const DChild* ch;
-    const DHome* hm;
+    const DTarget* tg;
+    const DMargVar* mv;
     const DPiece* pc;
     const DHomeVar* hv;
     const uint64_t* dig;
@@ -39,7 +40,7 @@ hipError_t launch_collect(const Ctx& c, int prec, const DGroup* groups, uint32_t
                           const int32_t* slots, int nslots, hipStream_t s);
 hipError_t launch_fin_collect(const Ctx& c, int prec, const DSepFin* fins, uint32_t nfins,
                               const int32_t* slots, int nslots, hipStream_t s);
-hipError_t launch_distribute(const Ctx& c, int prec, const DGroup* groups, uint32_t ngroups,
+hipError_t launch_distribute(const Ctx& c, int prec, const DWork* works, uint32_t nworks,
                              const int32_t* slots, int nslots, hipStream_t s);
 hipError_t launch_fin_distribute(const Ctx& c, int prec, const DSepFin* fins, uint32_t nfins,
                                  const int32_t* slots, int nslots, hipStream_t s);

@@ -206,62 +206,78 @@ __global__ __launch_bounds__(kBlock) void k_fin_collect(Ctx c, const DSepFin* __
     }
     const double scale = ldexp(1.0, -k);
     T* __restrict__ sepc = static_cast<T*>(c.sepc) + (uint64_t)slot * c.sep_stride;
-    for (uint32_t m = threadIdx.x; m < f.size; m += kBlock) {
-        sepc[f.sep + m] = (T)(acc[f.sep + m] * scale);
-        acc[f.sep + m] = 0.0;
-    }
+    for (uint32_t m = threadIdx.x; m < f.size; m += kBlock) sepc[f.sep + m] = (T)(acc[f.sep + m] * scale);
     if (threadIdx.x == 0) kexp[f.edge] = k;
 }
 
 // --------------------------------------------------------------- distribute
 
+// One workgroup marginalises a block of one clique onto one target
+// separator: it stages ng groups x nk rows of the clique (each row L
+// consecutive entries, read coalesced and extended by the parent's
+// distribute ratio on the way in) in LDS, then every separator entry of the
+// block is summed by a fixed set of lanes in a fixed order -- no atomics,
+// so results do not depend on scheduling.
 template <typename T>
-__global__ __launch_bounds__(kBlock) void k_distribute(Ctx c, const DGroup* __restrict__ groups,
-                                                       const int32_t* __restrict__ slots) {
-    __shared__ DPiece pcs[kMaxPieces];
-    const DGroup g = groups[blockIdx.x];
+__global__ __launch_bounds__(kBlock) void k_dist_gather(Ctx c, const DWork* __restrict__ works,
+                                                        const int32_t* __restrict__ slots) {
+    __shared__ T vals[kTileMax];
+    const DWork w = works[blockIdx.x];
     const int slot = slots[blockIdx.y];
-    for (uint32_t k = threadIdx.x; k < g.npiece; k += kBlock) pcs[k] = c.pc[g.piece0 + k];
+    const DTarget tg = c.tg[w.target];
+    const DClique q = c.cl[tg.clique];
+    const T* __restrict__ psi = static_cast<const T*>(c.psi) + (uint64_t)slot * c.psi_stride + q.off;
+    const T* __restrict__ sepd = static_cast<const T*>(c.sepd) + (uint64_t)slot * c.sep_stride;
+    const uint32_t* __restrict__ map = c.map;
+
+    const uint32_t n = w.ng * w.nk * q.L;
+    for (uint32_t idx = threadIdx.x; idx < n; idx += kBlock) {
+        const uint32_t ri = mdiv(idx, q.Lmul, q.Lsh);
+        const uint32_t l = idx - ri * q.L;
+        const uint32_t gg = mdiv(ri, w.nkmul, w.nksh);
+        const uint32_t k = ri - gg * w.nk;
+        const uint32_t row = map[tg.rg + w.g0 + gg] + map[tg.rq + w.k0 + k];
+        T v = psi[row * q.L + l];
+        if (q.pedge >= 0) v *= sepd[q.psep + map[q.pmh + row] + map[q.pml + l]];
+        vals[idx] = v;
+    }
     __syncthreads();
 
-    const T* __restrict__ psi = static_cast<const T*>(c.psi) + (uint64_t)slot * c.psi_stride;
-    const T* __restrict__ sepd = static_cast<const T*>(c.sepd) + (uint64_t)slot * c.sep_stride;
+    // outputs (gg, t); tpo lanes per output, power of two within a wave
+    const uint32_t nout = w.ng * tg.nPL;
+    uint32_t tpo = 1;
+    while (tpo < 64 && tpo * 2 * nout <= (uint32_t)kBlock) tpo *= 2;
+    const uint32_t sub = threadIdx.x & (tpo - 1);
+    const uint32_t per = w.nk * tg.nQL;  // summands of one output
     double* __restrict__ acc = c.acc + (uint64_t)slot * c.sep_stride;
-    double* __restrict__ marg = c.marg + (uint64_t)slot * c.marg_stride;
-
-    uint32_t p = 0;
-    int cur = -1;
-    DClique q{};
-    for (uint32_t gi = threadIdx.x; gi < g.total; gi += kBlock) {
-        while (gi >= pcs[p].gofs + pcs[p].count) p++;
-        if ((int)p != cur) {
-            cur = (int)p;
-            q = c.cl[pcs[p].clique];
-        }
-        const uint32_t i = pcs[p].begin + (gi - pcs[p].gofs);
-        const uint32_t hi = mdiv(i, q.Lmul, q.Lsh);
-        const uint32_t lo = i - hi * q.L;
-        T v = psi[q.off + i];
-        if (q.pedge >= 0) v *= sepd[q.psep + c.map[q.pmh + hi] + c.map[q.pml + lo]];
-        if (v == T(0)) continue;
-        const double dv = (double)v;
-        for (uint32_t k = 0; k < q.nchild; k++) {
-            const DChild ch = c.ch[q.child0 + k];
-            unsafeAtomicAdd(&acc[ch.sep + c.map[ch.mh + hi] + c.map[ch.ml + lo]], dv);
-        }
-        if (q.nhome) {
-            const uint64_t d = c.dig[q.hdig + hi] | c.dig[q.ldig + lo];
-            for (uint32_t k = 0; k < q.nhome; k++) {
-                const DHome h = c.hm[q.home0 + k];
-                unsafeAtomicAdd(&marg[h.out + (uint32_t)((d >> h.shift) & h.mask)], dv);
+    double* __restrict__ part = c.part + (uint64_t)slot * c.part_stride;
+    for (uint32_t base = 0; base < nout * tpo; base += kBlock) {
+        const uint32_t o = (base + threadIdx.x) / tpo;
+        double s = 0.0;
+        uint32_t gg = 0, t = 0;
+        if (o < nout) {
+            gg = o / tg.nPL;
+            t = o - gg * tg.nPL;
+            const uint32_t lp = map[tg.lp + t];
+            for (uint32_t j = sub; j < per; j += tpo) {
+                const uint32_t k = j / tg.nQL;
+                const uint32_t u = j - k * tg.nQL;
+                s += (double)vals[(gg * w.nk + k) * q.L + lp + map[tg.lq + u]];
             }
+        }
+        for (uint32_t o2 = tpo / 2; o2 > 0; o2 >>= 1) s += __shfl_xor(s, (int)o2, kWave);
+        if (o < nout && sub == 0) {
+            const uint32_t m = map[tg.tb + w.g0 + gg] + map[tg.tv + t];
+            if (tg.part0 < 0) acc[tg.sep + m] = s;
+            else part[(uint32_t)tg.part0 + m * tg.nchunk + w.chunk] = s;
         }
     }
 }
 
-// After a distribute layer: new/old separator ratio (0/0 = 0), rescaled by
-// an exact power of two; the float64 accumulator is left for the next
-// collect to overwrite.
+// After a distribute layer, per separator (real or one-variable virtual):
+// finish the new separator table S* (summing partials), read the posterior
+// marginals of the variables assigned to it, and for a real separator form
+// the new/old ratio S*/S (0/0 = 0) rescaled by an exact power of two.
 template <typename T>
 __global__ __launch_bounds__(kBlock) void k_fin_distribute(Ctx c, const DSepFin* __restrict__ fins,
                                                            const int32_t* __restrict__ slots) {
@@ -269,36 +285,63 @@ __global__ __launch_bounds__(kBlock) void k_fin_distribute(Ctx c, const DSepFin*
     const DSepFin f = fins[blockIdx.x];
     const int slot = slots[blockIdx.y];
     double* __restrict__ acc = c.acc + (uint64_t)slot * c.sep_stride;
+    const double* __restrict__ part = c.part + (uint64_t)slot * c.part_stride;
+    if (f.nchunk) {
+        for (uint32_t m = threadIdx.x; m < f.size; m += kBlock) {
+            double v = 0.0;
+            const double* pp = part + f.part0 + (uint64_t)m * f.nchunk;
+            for (uint32_t k = 0; k < f.nchunk; k++) v += pp[k];
+            acc[f.sep + m] = v;
+        }
+        __syncthreads();
+    }
+    // posteriors: each state of each assigned variable is a block-wide sum
+    // over the separator entries carrying that state
+    double* __restrict__ marg = c.marg + (uint64_t)slot * c.marg_stride;
+    for (uint32_t a = 0; a < f.nmv; a++) {
+        const DMargVar mv = c.mv[f.mv0 + a];
+        const uint32_t per = f.size / mv.card;
+        for (uint32_t x = 0; x < mv.card; x++) {
+            double s = 0.0;
+            for (uint32_t e = threadIdx.x; e < per; e += kBlock) {
+                const uint32_t o = e / mv.stride;
+                s += acc[f.sep + (o * mv.card + x) * mv.stride + (e - o * mv.stride)];
+            }
+            s = block_sum(s, red);
+            if (threadIdx.x == 0) marg[mv.out + x] = s;
+        }
+    }
+    if (f.edge < 0) return;
     const T* __restrict__ sepc = static_cast<const T*>(c.sepc) + (uint64_t)slot * c.sep_stride;
     T* __restrict__ sepd = static_cast<T*>(c.sepd) + (uint64_t)slot * c.sep_stride;
     double mx = 0.0;
     for (uint32_t m = threadIdx.x; m < f.size; m += kBlock) {
         const double den = (double)sepc[f.sep + m];
         const double r = den == 0.0 ? 0.0 : acc[f.sep + m] / den;
-        acc[f.sep + m] = r;
         mx = fmax(mx, r);
     }
     mx = block_max(mx, red);
     int k = 0;
     if (mx > 0.0) frexp(mx, &k);
     const double scale = ldexp(1.0, -k);
-    for (uint32_t m = threadIdx.x; m < f.size; m += kBlock) sepd[f.sep + m] = (T)(acc[f.sep + m] * scale);
+    for (uint32_t m = threadIdx.x; m < f.size; m += kBlock) {
+        const double den = (double)sepc[f.sep + m];
+        const double r = den == 0.0 ? 0.0 : acc[f.sep + m] / den;
+        sepd[f.sep + m] = (T)(r * scale);
+    }
 }
 
-// Posteriors: normalise each variable's marginal; clear the accumulators.
+// Posteriors: normalise each variable's marginal.
 __global__ __launch_bounds__(kBlock) void k_marginals(Ctx c, const int32_t* __restrict__ slots) {
     const int slot = slots[blockIdx.x];
-    double* marg = c.marg + (uint64_t)slot * c.marg_stride;
+    const double* marg = c.marg + (uint64_t)slot * c.marg_stride;
     double* post = c.post + (uint64_t)slot * c.marg_stride;
     bool empty = false;
     for (int v = threadIdx.x; v < c.nvars; v += kBlock) {
         const DHomeVar h = c.hv[v];
         double s = 0.0;
         for (uint32_t x = 0; x < h.card; x++) s += marg[h.out + x];
-        for (uint32_t x = 0; x < h.card; x++) {
-            post[h.out + x] = s > 0.0 ? marg[h.out + x] / s : 0.0;
-            marg[h.out + x] = 0.0;
-        }
+        for (uint32_t x = 0; x < h.card; x++) post[h.out + x] = s > 0.0 ? marg[h.out + x] / s : 0.0;
         if (!(s > 0.0)) empty = true;
     }
     if (empty) atomicOr(&c.flags[slot], c.fp32 ? 2 : 1);
@@ -356,12 +399,12 @@ hipError_t launch_fin_collect(const Ctx& c, int prec, const DSepFin* fins, uint3
     return hipGetLastError();
 }
 
-hipError_t launch_distribute(const Ctx& c, int prec, const DGroup* groups, uint32_t ngroups, const int32_t* slots,
+hipError_t launch_distribute(const Ctx& c, int prec, const DWork* works, uint32_t nworks, const int32_t* slots,
                              int nslots, hipStream_t s) {
-    if (!ngroups || !nslots) return hipSuccess;
-    dim3 grid(ngroups, (unsigned)nslots);
-    if (prec) hipLaunchKernelGGL(k_distribute<float>, grid, dim3(kBlock), 0, s, c, groups, slots);
-    else hipLaunchKernelGGL(k_distribute<double>, grid, dim3(kBlock), 0, s, c, groups, slots);
+    if (!nworks || !nslots) return hipSuccess;
+    dim3 grid(nworks, (unsigned)nslots);
+    if (prec) hipLaunchKernelGGL(k_dist_gather<float>, grid, dim3(kBlock), 0, s, c, works, slots);
+    else hipLaunchKernelGGL(k_dist_gather<double>, grid, dim3(kBlock), 0, s, c, works, slots);
     return hipGetLastError();
 }
 

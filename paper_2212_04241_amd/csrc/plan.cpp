@@ -8,13 +8,15 @@
 // cardinalities) each map is exactly H[hi] + Lo[lo]: two small tables per
 // edge instead of one entry per clique entry.  The digits themselves are
 // packed into one 64-bit word per entry the same way (hi word | lo word),
-// which lets the kernels test evidence and read a home variable's state with
-// a mask and a shift.
+// which lets the kernels test evidence with a mask.
 //
 // Work is laid out per layer (Section 2: all the table entries of a layer
-// form one parallel task): the entries of every clique in the layer are cut
-// into runs and packed into workgroup tiles of at most `tile` entries, so
-// many small cliques share a workgroup and a huge clique spreads over many.
+// form one parallel task).  Collect: the entries of every clique in the
+// layer are cut into runs aligned to parent-separator segments and packed
+// into workgroup tiles, so many small cliques share a workgroup and a huge
+// clique spreads over many.  Distribute: every marginalisation of a clique
+// onto a child separator becomes a list of workgroups, each gathering whole
+// rows of the clique for a block of separator entries (no atomics).
 #include "plan.h"
 
 #include <algorithm>
@@ -38,13 +40,16 @@ static uint32_t bits_for(int r) {
     return b;
 }
 
+static uint32_t mdiv_host(uint32_t n, uint32_t mul, uint32_t sh) {
+    return (uint32_t)(((uint64_t)(((uint64_t)n * mul) >> 32) + n) >> sh);
+}
+
 namespace {
 
 struct Packer {
     Plan& p;
     int tile;
     int32_t open = -1;  // index of the open full group, or -1
-    void close() { open = -1; }
     void add_full(uint32_t clique, uint32_t begin, uint32_t count) {
         if (open >= 0) {
             DGroup& g = p.groups[(size_t)open];
@@ -75,26 +80,45 @@ struct Packer {
     }
 };
 
+// Append the mixed-radix enumeration over layout positions `pos` (last
+// fastest) of sum_k digit_k * weight[pos_k] to pool; returns its offset.
+uint32_t enumerate(const std::vector<int>& pos, const std::vector<int>& card_at, const std::vector<uint64_t>& weight,
+                   std::vector<uint32_t>& pool) {
+    const uint32_t start = (uint32_t)pool.size();
+    uint64_t count = 1;
+    for (int k : pos) count *= (uint64_t)card_at[(size_t)k];
+    std::vector<int> dg(pos.size(), 0);
+    for (uint64_t x = 0; x < count; x++) {
+        uint64_t v = 0;
+        for (size_t a = 0; a < pos.size(); a++) v += (uint64_t)dg[a] * weight[(size_t)pos[a]];
+        if (v > 0xffffffffull) throw std::runtime_error("index table overflow");
+        pool.push_back((uint32_t)v);
+        for (size_t a = pos.size(); a-- > 0;) {
+            if (++dg[a] < card_at[(size_t)pos[a]]) break;
+            dg[a] = 0;
+        }
+    }
+    return start;
+}
+
 }  // namespace
 
 std::string check_plan(const Tree& t, const Plan& p) {
-    auto bad = [](const std::string& s) { return s; };
     const size_t nc = p.cliques.size();
-    if (nc != (size_t)t.nc) return bad("clique count");
+    if (nc != (size_t)t.nc) return "clique count";
     uint64_t sum = 0;
     for (size_t c = 0; c < nc; c++) {
         const DClique& d = p.cliques[c];
-        if (d.off != sum || d.size != t.size[c] || d.size == 0) return bad("clique offset/size");
+        if (d.off != sum || d.size != t.size[c] || d.size == 0) return "clique offset/size";
         sum += d.size;
-        if (d.L == 0 || d.size % d.L) return bad("split");
+        if (d.L == 0 || d.L > (uint32_t)kTileMax || d.size % d.L) return "split";
         const uint32_t rows = d.size / d.L;
         for (uint32_t x : {0u, d.size - 1, d.size / 2, d.L, d.L - 1})
-            if (x < d.size && (uint32_t)(((uint64_t)(((uint64_t)x * d.Lmul) >> 32) + x) >> d.Lsh) != x / d.L)
-                return bad("magic division");
-        if ((uint64_t)d.hdig + rows > p.digits.size() || (uint64_t)d.ldig + d.L > p.digits.size()) return bad("digit tables");
+            if (x < d.size && mdiv_host(x, d.Lmul, d.Lsh) != x / d.L) return "magic division";
+        if ((uint64_t)d.hdig + rows > p.digits.size() || (uint64_t)d.ldig + d.L > p.digits.size()) return "digit tables";
         const uint32_t psize = (int)c == t.root ? 1u : (uint32_t)t.e_size[(size_t)t.pedge[c]];
-        if (d.seg == 0 || d.size != d.seg * psize) return bad("segment");
-        if ((uint64_t)d.psep + psize > p.sep_total + 1ull) return bad("parent separator offset");
+        if (d.seg == 0 || d.size != d.seg * psize) return "segment";
+        if ((uint64_t)d.psep + psize > p.sep_real) return "parent separator offset";
         auto check_map = [&](uint32_t mh, uint32_t ml, uint32_t limit) -> bool {
             if ((uint64_t)mh + rows > p.maps.size() || (uint64_t)ml + d.L > p.maps.size()) return false;
             uint64_t mx_h = 0, mx_l = 0;
@@ -102,57 +126,93 @@ std::string check_plan(const Tree& t, const Plan& p) {
             for (uint32_t l = 0; l < d.L; l++) mx_l = std::max<uint64_t>(mx_l, p.maps[ml + l]);
             return mx_h + mx_l < limit;
         };
-        if ((int)c != t.root && !check_map(d.pmh, d.pml, psize)) return bad("parent map range");
-        if ((uint64_t)d.child0 + d.nchild > p.children.size() || d.nchild != t.children[c].size()) return bad("children");
+        if ((int)c != t.root && !check_map(d.pmh, d.pml, psize)) return "parent map range";
+        if ((uint64_t)d.child0 + d.nchild > p.children.size() || d.nchild != t.children[c].size()) return "children";
         for (uint32_t k = 0; k < d.nchild; k++) {
             const DChild& r = p.children[d.child0 + k];
-            if ((uint64_t)r.sep + r.size > p.sep_total) return bad("child separator offset");
-            if (!check_map(r.mh, r.ml, r.size)) return bad("child map range");
-        }
-        if ((uint64_t)d.home0 + d.nhome > p.homes.size()) return bad("homes");
-        for (uint32_t k = 0; k < d.nhome; k++) {
-            const DHome& h = p.homes[d.home0 + k];
-            if ((uint64_t)h.out + h.card > p.marg_total) return bad("home range");
-            if (h.mask + 1 < h.card || h.shift >= 64) return bad("home digit");
+            if ((uint64_t)r.sep + r.size > p.sep_total) return "child separator offset";
+            if (!check_map(r.mh, r.ml, r.size)) return "child map range";
         }
     }
-    if (sum != p.T) return bad("arena size");
-    auto check_layers = [&](const std::vector<Layer>& layers, bool collect) -> std::string {
-        for (const Layer& ly : layers) {
-            if ((uint64_t)ly.group0 + ly.ngroup > p.groups.size()) return "layer groups";
-            if ((uint64_t)ly.fin0 + ly.nfin > p.fins.size()) return "layer fins";
-            for (uint32_t g = ly.group0; g < ly.group0 + ly.ngroup; g++) {
-                const DGroup& G = p.groups[g];
-                if (G.total == 0 || G.total > (uint32_t)p.tile || G.total > (uint32_t)kTileMax) return "tile size";
-                if (G.npiece == 0 || G.npiece > (uint32_t)kMaxPieces) return "piece count";
-                if ((uint64_t)G.piece0 + G.npiece > p.pieces.size()) return "piece range";
-                if (G.part >= 0 && (G.npiece != 1 || (uint32_t)G.part >= p.n_parts || !collect)) return "partial group";
-                uint32_t ofs = 0;
-                for (uint32_t k = 0; k < G.npiece; k++) {
-                    const DPiece& pc = p.pieces[G.piece0 + k];
-                    if (pc.clique >= nc || pc.count == 0 || pc.gofs != ofs) return "piece layout";
-                    const DClique& d = p.cliques[pc.clique];
-                    if ((uint64_t)pc.begin + pc.count > d.size) return "piece bounds";
-                    if (collect && G.part < 0 && (pc.begin % d.seg || pc.count % d.seg)) return "piece alignment";
-                    if (collect && G.part >= 0 && pc.begin / d.seg != (pc.begin + pc.count - 1) / d.seg) return "partial piece spans segments";
-                    ofs += pc.count;
-                }
-                if (ofs != G.total) return "tile total";
+    if (sum != p.T) return "arena size";
+    // collect layers
+    for (const Layer& ly : p.collect) {
+        if ((uint64_t)ly.group0 + ly.ngroup > p.groups.size()) return "layer groups";
+        if ((uint64_t)ly.fin0 + ly.nfin > p.fins.size()) return "layer fins";
+        for (uint32_t g = ly.group0; g < ly.group0 + ly.ngroup; g++) {
+            const DGroup& G = p.groups[g];
+            if (G.total == 0 || G.total > (uint32_t)p.tile || G.total > (uint32_t)kTileMax) return "tile size";
+            if (G.npiece == 0 || G.npiece > (uint32_t)kMaxPieces) return "piece count";
+            if ((uint64_t)G.piece0 + G.npiece > p.pieces.size()) return "piece range";
+            if (G.part >= 0 && (G.npiece != 1 || (uint32_t)G.part >= p.n_parts)) return "partial group";
+            uint32_t ofs = 0;
+            for (uint32_t k = 0; k < G.npiece; k++) {
+                const DPiece& pc = p.pieces[G.piece0 + k];
+                if (pc.clique >= nc || pc.count == 0 || pc.gofs != ofs) return "piece layout";
+                const DClique& d = p.cliques[pc.clique];
+                if ((uint64_t)pc.begin + pc.count > d.size) return "piece bounds";
+                if (G.part < 0 && (pc.begin % d.seg || pc.count % d.seg)) return "piece alignment";
+                if (G.part >= 0 && pc.begin / d.seg != (pc.begin + pc.count - 1) / d.seg) return "partial piece spans segments";
+                ofs += pc.count;
             }
-            for (uint32_t f = ly.fin0; f < ly.fin0 + ly.nfin; f++) {
-                const DSepFin& F = p.fins[f];
-                if ((uint64_t)F.sep + F.size > p.sep_total + 1ull) return "fin range";
-                if (F.nchunk && (uint64_t)F.part0 + (uint64_t)F.size * F.nchunk > p.n_parts) return "fin partials";
-                if (F.edge >= t.ne || (F.edge < 0 && F.size != 1)) return "fin edge";
-            }
+            if (ofs != G.total) return "tile total";
         }
-        return "";
-    };
-    std::string e = check_layers(p.collect, true);
-    if (!e.empty()) return e;
-    e = check_layers(p.distribute, false);
-    if (!e.empty()) return e;
-    if ((uint64_t)p.sep_stride < (uint64_t)p.sep_total + 1) return "separator stride";
+    }
+    // distribute layers
+    for (const Layer& ly : p.distribute) {
+        if ((uint64_t)ly.group0 + ly.ngroup > p.works.size()) return "layer works";
+        if ((uint64_t)ly.fin0 + ly.nfin > p.fins.size()) return "layer fins";
+        for (uint32_t w = ly.group0; w < ly.group0 + ly.ngroup; w++) {
+            const DWork& W = p.works[w];
+            if (W.target >= p.targets.size()) return "work target";
+            const DTarget& tg = p.targets[W.target];
+            if (tg.clique >= nc) return "target clique";
+            const DClique& d = p.cliques[tg.clique];
+            if (W.ng == 0 || W.nk == 0 || (uint64_t)W.g0 + W.ng > tg.G || (uint64_t)W.k0 + W.nk > tg.NQ) return "work range";
+            if ((uint64_t)W.ng * W.nk * d.L > (uint64_t)kTileMax) return "work tile";
+            for (uint32_t x : {0u, W.nk - 1, W.nk, W.ng * W.nk - 1})
+                if (mdiv_host(x, W.nkmul, W.nksh) != x / W.nk) return "work magic";
+            if ((uint64_t)tg.G * tg.NQ * d.L != d.size || (uint64_t)tg.nPL * tg.nQL != d.L) return "target factorisation";
+            if (tg.part0 >= 0 && (W.ng != 1 || W.chunk >= tg.nchunk)) return "work partial";
+            if (tg.part0 < 0 && (W.k0 != 0 || W.nk != tg.NQ)) return "work rows";
+        }
+    }
+    for (const DTarget& tg : p.targets) {
+        if (tg.clique >= nc) return "target clique";
+        const DClique& d = p.cliques[tg.clique];
+        if ((uint64_t)tg.rg + tg.G > p.maps.size() || (uint64_t)tg.tb + tg.G > p.maps.size() ||
+            (uint64_t)tg.rq + tg.NQ > p.maps.size() || (uint64_t)tg.lp + tg.nPL > p.maps.size() ||
+            (uint64_t)tg.tv + tg.nPL > p.maps.size() || (uint64_t)tg.lq + tg.nQL > p.maps.size())
+            return "target tables";
+        // every row and lo offset gathered lies inside the clique
+        uint64_t mx_row = 0, mx_q = 0, mx_lp = 0, mx_lq = 0;
+        for (uint32_t g = 0; g < tg.G; g++) mx_row = std::max<uint64_t>(mx_row, p.maps[tg.rg + g]);
+        for (uint32_t k = 0; k < tg.NQ; k++) mx_q = std::max<uint64_t>(mx_q, p.maps[tg.rq + k]);
+        if (mx_row + mx_q >= d.size / d.L) return "target rows";
+        for (uint32_t t2 = 0; t2 < tg.nPL; t2++) mx_lp = std::max<uint64_t>(mx_lp, p.maps[tg.lp + t2]);
+        for (uint32_t u = 0; u < tg.nQL; u++) mx_lq = std::max<uint64_t>(mx_lq, p.maps[tg.lq + u]);
+        if (mx_lp + mx_lq >= d.L) return "target lows";
+        // every output index lands inside the separator
+        uint64_t mg = 0, mt = 0;
+        for (uint32_t g = 0; g < tg.G; g++) mg = std::max<uint64_t>(mg, p.maps[tg.tb + g]);
+        for (uint32_t t2 = 0; t2 < tg.nPL; t2++) mt = std::max<uint64_t>(mt, p.maps[tg.tv + t2]);
+        const uint64_t sz = (uint64_t)tg.G * tg.nPL;
+        if (mg + mt >= sz) return "target output range";
+        if ((uint64_t)tg.sep + sz > p.sep_stride) return "target separator offset";
+        if (tg.part0 >= 0 && (uint64_t)tg.part0 + sz * tg.nchunk > p.n_parts) return "target partials";
+    }
+    for (const DSepFin& F : p.fins) {
+        if ((uint64_t)F.sep + F.size > p.sep_stride) return "fin range";
+        if (F.nchunk && (uint64_t)F.part0 + (uint64_t)F.size * F.nchunk > p.n_parts) return "fin partials";
+        if (F.edge >= t.ne || F.edge < -2 || (F.edge == -1 && F.size != 1)) return "fin edge";
+        if ((uint64_t)F.mv0 + F.nmv > p.margvars.size()) return "fin posterior vars";
+        for (uint32_t k = 0; k < F.nmv; k++) {
+            const DMargVar& m = p.margvars[F.mv0 + k];
+            if ((uint64_t)m.out + m.card > p.marg_total || m.card == 0 || m.stride == 0) return "posterior var range";
+            if ((uint64_t)m.stride * m.card > F.size || F.size % ((uint64_t)m.stride * m.card)) return "posterior var stride";
+        }
+    }
+    if ((uint64_t)p.sep_stride < (uint64_t)p.sep_real) return "separator stride";
     return "";
 }
 
@@ -163,16 +223,35 @@ void build_plan(const Tree& t, int tile, Plan& p) {
     p.tile = tile;
     const int nc = t.nc;
 
-    // separator arena: edges in id order, then the root's virtual entry
+    // ---- separator arena: real edges in id order, the root's virtual
+    // entry, then one-variable virtual separators for private variables
     p.sep_off.resize((size_t)t.ne);
     uint64_t so = 0;
     for (int e = 0; e < t.ne; e++) {
         p.sep_off[(size_t)e] = (uint32_t)so;
         so += t.e_size[(size_t)e];
     }
-    if (so + 1 > 0x7fffffffull) throw std::runtime_error("separators too large");
     p.sep_total = (uint32_t)so;
-    p.sep_stride = (uint32_t)((so + 1 + 63) / 64 * 64);
+    so += 1;
+    p.sep_real = (uint32_t)so;
+
+    // posterior source: smallest real separator containing the variable
+    // (lowest edge id on ties); a variable in no separator lies in exactly
+    // one clique and gets a virtual one-variable separator there
+    p.post_sep.assign((size_t)t.n, -1);
+    std::vector<uint32_t> vsep_off((size_t)t.n, 0);
+    for (int e = 0; e < t.ne; e++)
+        for (int v : t.e_sep[(size_t)e]) {
+            int& s = p.post_sep[(size_t)v];
+            if (s < 0 || t.e_size[(size_t)e] < t.e_size[(size_t)s]) s = e;
+        }
+    for (int v = 0; v < t.n; v++)
+        if (p.post_sep[(size_t)v] < 0) {
+            vsep_off[(size_t)v] = (uint32_t)so;
+            so += (uint64_t)t.card[(size_t)v];
+        }
+    if (so > 0x7fffffffull) throw std::runtime_error("separators too large");
+    p.sep_stride = (uint32_t)((so + 63) / 64 * 64);
 
     // marginal offsets
     std::vector<uint32_t> marg_off((size_t)t.n);
@@ -184,17 +263,17 @@ void build_plan(const Tree& t, int tile, Plan& p) {
     }
     p.marg_total = mo;
 
-    std::vector<std::vector<int>> homed((size_t)nc);
-    for (int v = 0; v < t.n; v++) homed[(size_t)t.var_home[(size_t)v]].push_back(v);
-
-    // per-clique records, tables in id order
+    // ---- per-clique records, tables in id order
     p.cliques.resize((size_t)nc);
     p.kappa.assign((size_t)nc, 0);
+    std::vector<int> splitq((size_t)nc);
     uint64_t off = 0;
     for (int c = 0; c < nc; c++) {
         const auto& lay = t.vars[(size_t)c];
         const int m = (int)lay.size();
         const uint64_t size = t.size[(size_t)c];
+        std::vector<int> card_at((size_t)m);
+        for (int k = 0; k < m; k++) card_at[(size_t)k] = t.card[(size_t)lay[(size_t)k]];
         DClique& d = p.cliques[(size_t)c];
         d = DClique{};
         d.off = off;
@@ -205,45 +284,48 @@ void build_plan(const Tree& t, int tile, Plan& p) {
         uint64_t L = 1;
         while (q > 0 && L < 64) {
             q--;
-            L *= (uint64_t)t.card[(size_t)lay[(size_t)q]];
+            L *= (uint64_t)card_at[(size_t)q];
         }
+        if (L > (uint64_t)kTileMax) throw std::runtime_error("a variable's cardinality is too large for the tile");
+        splitq[(size_t)c] = q;
         const uint64_t rows = size / L;
         d.L = (uint32_t)L;
         magic_u32(d.L, d.Lmul, d.Lsh);
+        std::vector<int> hi_pos, lo_pos;
+        for (int k = 0; k < q; k++) hi_pos.push_back(k);
+        for (int k = q; k < m; k++) lo_pos.push_back(k);
         // digit bit positions, layout order from the lowest bits
-        std::vector<uint32_t> shift((size_t)m), nbits((size_t)m);
+        std::vector<uint32_t> shift((size_t)m);
         uint32_t sh = 0;
         for (int k = 0; k < m; k++) {
             shift[(size_t)k] = sh;
-            nbits[(size_t)k] = bits_for(t.card[(size_t)lay[(size_t)k]]);
-            sh += nbits[(size_t)k];
+            sh += bits_for(card_at[(size_t)k]);
         }
         if (sh > 64) throw std::runtime_error("clique digits exceed 64 bits");
         p.dig_shift0.push_back((uint32_t)p.dig_shift.size());
         for (int k = 0; k < m; k++) p.dig_shift.push_back(shift[(size_t)k]);
-        // a factored table: value(row or lo) = sum over positions in [a, b)
-        // of digit * weight[position]
-        auto table = [&](int a, int b, uint64_t count, const std::vector<uint64_t>& weight, bool packed,
-                         auto& pool) -> uint32_t {
-            const uint32_t start = (uint32_t)pool.size();
-            std::vector<int> dg((size_t)(b - a), 0);
-            for (uint64_t x = 0; x < count; x++) {
-                uint64_t val = 0;
-                for (int k = a; k < b; k++) {
-                    const uint64_t digit = (uint64_t)dg[(size_t)(k - a)];
-                    val += packed ? (digit << shift[(size_t)k]) : digit * weight[(size_t)k];
+        {
+            // packed digits: enumerate with weights 2^shift (exact in uint64)
+            auto packed = [&](const std::vector<int>& pos) {
+                const uint32_t start = (uint32_t)p.digits.size();
+                uint64_t count = 1;
+                for (int k : pos) count *= (uint64_t)card_at[(size_t)k];
+                std::vector<int> dg(pos.size(), 0);
+                for (uint64_t x = 0; x < count; x++) {
+                    uint64_t v = 0;
+                    for (size_t a = 0; a < pos.size(); a++) v |= (uint64_t)dg[a] << shift[(size_t)pos[a]];
+                    p.digits.push_back(v);
+                    for (size_t a = pos.size(); a-- > 0;) {
+                        if (++dg[a] < card_at[(size_t)pos[a]]) break;
+                        dg[a] = 0;
+                    }
                 }
-                pool.push_back((typename std::remove_reference<decltype(pool)>::type::value_type)val);
-                for (int k = b - 1; k >= a; k--) {
-                    if (++dg[(size_t)(k - a)] < t.card[(size_t)lay[(size_t)k]]) break;
-                    dg[(size_t)(k - a)] = 0;
-                }
-            }
-            return start;
-        };
-        std::vector<uint64_t> none((size_t)m, 0);
-        d.hdig = table(0, q, rows, none, true, p.digits);
-        d.ldig = table(q, m, L, none, true, p.digits);
+                return start;
+            };
+            d.hdig = packed(hi_pos);
+            d.ldig = packed(lo_pos);
+        }
+        (void)rows;
         // parent map (prefix of the layout) and segment length
         if (c == t.root) {
             d.pedge = -1;
@@ -257,13 +339,13 @@ void build_plan(const Tree& t, int tile, Plan& p) {
             uint64_t s = 1;
             for (int k = ns - 1; k >= 0; k--) {
                 w[(size_t)k] = s;
-                s *= (uint64_t)t.card[(size_t)lay[(size_t)k]];
+                s *= (uint64_t)card_at[(size_t)k];
             }
             d.pedge = e;
             d.psep = p.sep_off[(size_t)e];
             d.seg = (uint32_t)(size / t.e_size[(size_t)e]);
-            d.pmh = table(0, q, rows, w, false, p.maps);
-            d.pml = table(q, m, L, w, false, p.maps);
+            d.pmh = enumerate(hi_pos, card_at, w, p.maps);
+            d.pml = enumerate(lo_pos, card_at, w, p.maps);
         }
         // child maps: separator variables ascending, last fastest
         d.child0 = (uint32_t)p.children.size();
@@ -281,19 +363,12 @@ void build_plan(const Tree& t, int tile, Plan& p) {
             DChild r{};
             r.sep = p.sep_off[(size_t)e];
             r.size = (uint32_t)t.e_size[(size_t)e];
-            r.mh = table(0, q, rows, w, false, p.maps);
-            r.ml = table(q, m, L, w, false, p.maps);
+            r.mh = enumerate(hi_pos, card_at, w, p.maps);
+            r.ml = enumerate(lo_pos, card_at, w, p.maps);
             p.children.push_back(r);
         }
-        // home variables
-        d.home0 = (uint32_t)p.homes.size();
-        d.nhome = (uint16_t)homed[(size_t)c].size();
-        for (int v : homed[(size_t)c]) {
-            int k = 0;
-            while (lay[(size_t)k] != v) k++;
-            p.homes.push_back({marg_off[(size_t)v], shift[(size_t)k], (1u << nbits[(size_t)k]) - 1u,
-                               (uint32_t)t.card[(size_t)v]});
-        }
+        d.home0 = 0;
+        d.nhome = 0;
         // scaled prior: max scaled into [0.5, 1) by an exact power of two
         double mx = 0.0;
         for (double x : t.prior[(size_t)c]) mx = std::max(mx, x);
@@ -354,34 +429,156 @@ void build_plan(const Tree& t, int tile, Plan& p) {
         ly.nfin = (uint32_t)fins.size();
         p.fins.insert(p.fins.end(), fins.begin(), fins.end());
     }
-    p.n_parts = parts;
 
-    // ---- distribute layers (depth); after layer d the separators towards
-    // the children of its cliques are finalised
+    // ---- distribute layers (depth): marginalise each clique onto each child
+    // separator and onto the virtual separator of each private variable
     p.distribute.assign((size_t)D + 1, Layer());
+    const uint32_t dtile_base = (uint32_t)std::max(tile, 64);
     for (int dd = 0; dd <= D; dd++) {
         Layer& ly = p.distribute[(size_t)dd];
-        ly.group0 = (uint32_t)p.groups.size();
-        Packer pk{p, tile};
+        ly.group0 = (uint32_t)p.works.size();
         std::vector<DSepFin> fins;
         for (int c = 0; c < nc; c++) {
             if (t.depth[(size_t)c] != dd) continue;
+            const auto& lay = t.vars[(size_t)c];
+            const int m = (int)lay.size();
+            const int q = splitq[(size_t)c];
             const DClique& d = p.cliques[(size_t)c];
-            for (uint32_t b = 0; b < d.size; b += (uint32_t)tile) pk.add_full((uint32_t)c, b, std::min((uint32_t)tile, d.size - b));
+            std::vector<int> card_at((size_t)m);
+            for (int k = 0; k < m; k++) card_at[(size_t)k] = t.card[(size_t)lay[(size_t)k]];
+            // strides of the positions among the row digits and the lo digits
+            std::vector<uint64_t> rstride((size_t)m, 0), lstride((size_t)m, 0);
+            uint64_t s = 1;
+            for (int k = q - 1; k >= 0; k--) {
+                rstride[(size_t)k] = s;
+                s *= (uint64_t)card_at[(size_t)k];
+            }
+            s = 1;
+            for (int k = m - 1; k >= q; k--) {
+                lstride[(size_t)k] = s;
+                s *= (uint64_t)card_at[(size_t)k];
+            }
+            // one target per child separator and per private variable
+            struct Tgt {
+                std::vector<int> vars;  // target variables, ascending = its layout
+                uint32_t sep;
+                int edge;               // >= 0 real, -2 virtual
+            };
+            std::vector<Tgt> tgts;
             for (int ch : t.children[(size_t)c]) {
                 const int e = t.pedge[(size_t)ch];
+                tgts.push_back({t.e_sep[(size_t)e], p.sep_off[(size_t)e], e});
+            }
+            for (int v : lay)
+                if (p.post_sep[(size_t)v] < 0) tgts.push_back({{v}, vsep_off[(size_t)v], -2});
+            for (const Tgt& tg0 : tgts) {
+                // target strides (ascending variable order, last fastest)
+                std::vector<uint64_t> tstride((size_t)m, 0);
+                uint64_t ts = 1;
+                std::vector<char> keep((size_t)m, 0);
+                for (size_t a = tg0.vars.size(); a-- > 0;) {
+                    for (int k = 0; k < m; k++)
+                        if (lay[(size_t)k] == tg0.vars[a]) {
+                            tstride[(size_t)k] = ts;
+                            keep[(size_t)k] = 1;
+                        }
+                    ts *= (uint64_t)t.card[(size_t)tg0.vars[a]];
+                }
+                const uint64_t tsize = ts;
+                std::vector<int> Phi, Qhi, Plo, Qlo;
+                for (int k = 0; k < m; k++) {
+                    if (k < q) (keep[(size_t)k] ? Phi : Qhi).push_back(k);
+                    else (keep[(size_t)k] ? Plo : Qlo).push_back(k);
+                }
+                DTarget T{};
+                T.clique = (uint32_t)c;
+                auto prod = [&](const std::vector<int>& ps) {
+                    uint64_t x = 1;
+                    for (int k : ps) x *= (uint64_t)card_at[(size_t)k];
+                    return (uint32_t)x;
+                };
+                T.G = prod(Phi);
+                T.NQ = prod(Qhi);
+                T.nPL = prod(Plo);
+                T.nQL = prod(Qlo);
+                T.rg = enumerate(Phi, card_at, rstride, p.maps);
+                T.tb = enumerate(Phi, card_at, tstride, p.maps);
+                T.rq = enumerate(Qhi, card_at, rstride, p.maps);
+                T.lp = enumerate(Plo, card_at, lstride, p.maps);
+                T.tv = enumerate(Plo, card_at, tstride, p.maps);
+                T.lq = enumerate(Qlo, card_at, lstride, p.maps);
+                T.sep = tg0.sep;
+                T.part0 = -1;
+                T.nchunk = 0;
+                const uint32_t ti = (uint32_t)p.targets.size();
+                const uint32_t dtile = std::min<uint32_t>((uint32_t)kTileMax, std::max(dtile_base, d.L));
+                const uint64_t group_entries = (uint64_t)T.NQ * d.L;
+                if (group_entries <= dtile) {
+                    const uint32_t per = std::max<uint32_t>(1, (uint32_t)(dtile / group_entries));
+                    for (uint32_t g0 = 0; g0 < T.G; g0 += per) {
+                        DWork W{};
+                        W.target = ti;
+                        W.g0 = g0;
+                        W.ng = std::min(per, T.G - g0);
+                        W.k0 = 0;
+                        W.nk = T.NQ;
+                        magic_u32(W.nk, W.nkmul, W.nksh);
+                        W.chunk = 0;
+                        p.works.push_back(W);
+                    }
+                } else {
+                    const uint32_t nk = std::max<uint32_t>(1, dtile / d.L);
+                    T.nchunk = (T.NQ + nk - 1) / nk;
+                    T.part0 = (int32_t)parts;
+                    parts += (uint32_t)(tsize * T.nchunk);
+                    for (uint32_t g = 0; g < T.G; g++)
+                        for (uint32_t ck = 0; ck < T.nchunk; ck++) {
+                            DWork W{};
+                            W.target = ti;
+                            W.g0 = g;
+                            W.ng = 1;
+                            W.k0 = ck * nk;
+                            W.nk = std::min(nk, T.NQ - W.k0);
+                            magic_u32(W.nk, W.nkmul, W.nksh);
+                            W.chunk = ck;
+                            p.works.push_back(W);
+                        }
+                }
+                p.targets.push_back(T);
+                // finalise record with the posterior variables it carries
                 DSepFin f{};
-                f.sep = p.sep_off[(size_t)e];
-                f.size = (uint32_t)t.e_size[(size_t)e];
-                f.edge = e;
+                f.sep = tg0.sep;
+                f.size = (uint32_t)tsize;
+                f.edge = tg0.edge;
+                f.nchunk = T.part0 >= 0 ? T.nchunk : 0;
+                f.part0 = T.part0 >= 0 ? (uint32_t)T.part0 : 0;
+                f.mv0 = (uint32_t)p.margvars.size();
+                if (tg0.edge >= 0) {
+                    uint64_t st = 1;
+                    std::vector<uint64_t> vs(tg0.vars.size());
+                    for (size_t a = tg0.vars.size(); a-- > 0;) {
+                        vs[a] = st;
+                        st *= (uint64_t)t.card[(size_t)tg0.vars[a]];
+                    }
+                    for (size_t a = 0; a < tg0.vars.size(); a++) {
+                        const int v = tg0.vars[a];
+                        if (p.post_sep[(size_t)v] == tg0.edge)
+                            p.margvars.push_back({marg_off[(size_t)v], (uint32_t)vs[a], (uint32_t)t.card[(size_t)v], 0});
+                    }
+                } else {
+                    const int v = tg0.vars[0];
+                    p.margvars.push_back({marg_off[(size_t)v], 1u, (uint32_t)t.card[(size_t)v], 0});
+                }
+                f.nmv = (uint32_t)p.margvars.size() - f.mv0;
                 fins.push_back(f);
             }
         }
-        ly.ngroup = (uint32_t)p.groups.size() - ly.group0;
+        ly.ngroup = (uint32_t)p.works.size() - ly.group0;
         ly.fin0 = (uint32_t)p.fins.size();
         ly.nfin = (uint32_t)fins.size();
         p.fins.insert(p.fins.end(), fins.begin(), fins.end());
     }
+    p.n_parts = parts;
 }
 
 }  // namespace fbn

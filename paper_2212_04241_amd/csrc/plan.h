@@ -7,7 +7,7 @@
 namespace fbn {
 
 struct Layer {
-    uint32_t group0 = 0, ngroup = 0;  // into Plan::groups
+    uint32_t group0 = 0, ngroup = 0;  // collect: into Plan::groups; distribute: into Plan::works
     uint32_t fin0 = 0, nfin = 0;      // into Plan::fins (separators finalised after it)
 };
 
@@ -26,6 +26,11 @@ struct Plan {
     std::vector<DPiece> pieces;
     std::vector<DGroup> groups;
     std::vector<DSepFin> fins;
+    std::vector<DTarget> targets;     // distribute marginalisations
+    std::vector<DWork> works;         // distribute workgroups
+    std::vector<DMargVar> margvars;   // posterior variables per finalised separator
+    std::vector<int> post_sep;        // per variable: edge whose separator gives its posterior, -1 virtual
+    uint32_t sep_real = 0;            // entries of real separators + the root's virtual entry
     std::vector<Layer> collect;       // by height 0..H
     std::vector<Layer> distribute;    // by depth 0..D
     std::vector<uint64_t> digits;     // packed-digit tables

@@ -61,6 +61,13 @@ def lib():
         return _lib
     if not os.path.exists(LIB_PATH):
         raise ImportError(f"{LIB_PATH} is missing: build it with `python -m paper_2212_04241_amd.build`")
+    # torch bundles its own HIP runtime under the same soname; load it first so
+    # that torch and this library share one runtime in the process
+    if os.environ.get("FBN_NO_TORCH") != "1":
+        try:
+            import torch  # noqa: F401
+        except ImportError:
+            pass
     L = C.CDLL(LIB_PATH)
     P = C.POINTER
     i32p, f64p, vpp = P(C.c_int32), P(C.c_double), P(C.c_void_p)
@@ -86,6 +93,8 @@ def lib():
         "fbn_jt_edge": (C.c_int32, [C.c_void_p, C.c_int32, i32p, i32p, i32p, C.c_int32, i32p]),
         "fbn_jt_index_map": (C.c_int32, [C.c_void_p, C.c_int32, i32p, C.c_size_t]),
         "fbn_jt_device_index_map": (C.c_int32, [C.c_void_p, C.c_int32, i32p, C.c_size_t]),
+        "fbn_jt_profile_enable": (C.c_int32, [C.c_void_p, C.c_int32]),
+        "fbn_jt_profile_read": (C.c_int32, [C.c_void_p, f64p, P(C.c_int64), f64p]),
         "fbn_jt_elim_order": (C.c_int32, [C.c_void_p, i32p]),
         "fbn_jt_homes": (C.c_int32, [C.c_void_p, i32p, i32p]),
     }
@@ -310,6 +319,25 @@ def jt_device_index_map(jt: JT, e: int, card) -> np.ndarray:
     _check(lib().fbn_jt_device_index_map(jt._h, e, out.ctypes.data_as(C.POINTER(C.c_int32)), out.size),
            "fbn_jt_device_index_map")
     return out
+
+
+PROFILE_KINDS = ("collect", "collect_finalise", "distribute", "distribute_finalise", "posteriors")
+
+
+def jt_profile_enable(jt: JT, on: bool = True) -> None:
+    _check(lib().fbn_jt_profile_enable(jt._h, 1 if on else 0), "fbn_jt_profile_enable")
+
+
+def jt_profile_read(jt: JT) -> dict:
+    """{kind: (ms, launches, algorithmic bytes)} since the last read."""
+    n = len(PROFILE_KINDS)
+    ms = np.zeros(n, dtype=np.float64)
+    cnt = np.zeros(n, dtype=np.int64)
+    by = np.zeros(n, dtype=np.float64)
+    _check(lib().fbn_jt_profile_read(jt._h, ms.ctypes.data_as(C.POINTER(C.c_double)),
+                                     cnt.ctypes.data_as(C.POINTER(C.c_int64)),
+                                     by.ctypes.data_as(C.POINTER(C.c_double))), "fbn_jt_profile_read")
+    return {k: (float(ms[i]), int(cnt[i]), float(by[i])) for i, k in enumerate(PROFILE_KINDS)}
 
 
 def jt_elim_order(jt: JT) -> np.ndarray:
