@@ -559,7 +559,8 @@ int orc_compile(const orc_net* net, uint64_t max_entries, orc_jt** out) {
     for (int c = 0; c < nc; c++) free(nbr[c]);
     free(nbr); free(deg); free(dist); free(queue); free(tree_i); free(tree_j);
 
-    /* 6. edges numbered by ascending child id; separators ascending */
+    /* 6. edges numbered by ascending child id; separator membership (the
+     * order of a separator's variables is fixed with the layouts below) */
     jt->pedge = malloc(sizeof(int) * (size_t)nc);
     jt->e_par = malloc(sizeof(int) * (size_t)(ne > 0 ? ne : 1));
     jt->e_chi = malloc(sizeof(int) * (size_t)(ne > 0 ? ne : 1));
@@ -588,25 +589,37 @@ int orc_compile(const orc_net* net, uint64_t max_entries, orc_jt** out) {
         }
     }
 
-    /* 7. layouts: root ascending; others [separator asc] ++ [rest asc] */
-    for (int c = 0; c < nc; c++) {
-        int m = jt->cn[c];
-        int* lay = malloc(sizeof(int) * (size_t)m);
-        int k = 0;
-        if (c != jt->root) {
-            int e = jt->pedge[c];
-            for (int a = 0; a < jt->e_n[e]; a++) lay[k++] = jt->e_sep[e][a];
-            for (int a = 0; a < m; a++)
-                if (!contains(jt->e_sep[e], jt->e_n[e], jt->cvars[c][a])) lay[k++] = jt->cvars[c][a];
-        } else {
-            for (int a = 0; a < m; a++) lay[k++] = jt->cvars[c][a];
+    /* 7. layouts, from the root down: the root ascending; a separator's
+     * variables in the order they take in its parent's layout; a non-root
+     * clique [its parent separator, in that order] ++ [the rest ascending] */
+    int maxd = 0;
+    for (int c = 0; c < nc; c++) if (jt->depth[c] > maxd) maxd = jt->depth[c];
+    for (int d = 0; d <= maxd; d++)
+        for (int c = 0; c < nc; c++) {
+            if (jt->depth[c] != d) continue;
+            int m = jt->cn[c];
+            int* lay = malloc(sizeof(int) * (size_t)m);
+            int k = 0;
+            if (c != jt->root) {
+                int e = jt->pedge[c], p = jt->parent[c];
+                int* ordered = malloc(sizeof(int) * (size_t)(jt->e_n[e] + 1));
+                int q = 0;
+                for (int b = 0; b < jt->cn[p]; b++)      /* parent layout is final */
+                    if (contains(jt->e_sep[e], jt->e_n[e], jt->cvars[p][b])) ordered[q++] = jt->cvars[p][b];
+                free(jt->e_sep[e]);
+                jt->e_sep[e] = ordered;
+                for (int a = 0; a < jt->e_n[e]; a++) lay[k++] = jt->e_sep[e][a];
+                for (int a = 0; a < m; a++)
+                    if (!contains(jt->e_sep[e], jt->e_n[e], jt->cvars[c][a])) lay[k++] = jt->cvars[c][a];
+            } else {
+                for (int a = 0; a < m; a++) lay[k++] = jt->cvars[c][a];
+            }
+            free(jt->cvars[c]);
+            jt->cvars[c] = lay;
+            jt->cstride[c] = malloc(sizeof(int64_t) * (size_t)m);
+            int64_t s = 1;
+            for (int a = m - 1; a >= 0; a--) { jt->cstride[c][a] = s; s *= net->card[lay[a]]; }
         }
-        free(jt->cvars[c]);
-        jt->cvars[c] = lay;
-        jt->cstride[c] = malloc(sizeof(int64_t) * (size_t)m);
-        int64_t s = 1;
-        for (int a = m - 1; a >= 0; a--) { jt->cstride[c][a] = s; s *= net->card[lay[a]]; }
-    }
 
     /* 8. index maps: map_e[j] = separator index of parent entry j */
     for (int e = 0; e < ne; e++) {

@@ -22,8 +22,9 @@
  *   -> Kruskal maximum-weight spanning tree over all clique pairs
  *      (key: -|sep|, product of sep cardinalities, i, j)
  *   -> root = minimum eccentricity (ties: lowest id), BFS depth, height
- *   -> layouts: root ascending; others [sep vars asc] ++ [rest asc],
- *      last variable fastest
+ *   -> layouts: root ascending; a separator's variables in the order
+ *      they take in its parent's layout; other cliques [parent separator]
+ *      ++ [rest ascending]; last variable fastest
  *   -> one index map per edge (parent entry -> separator entry)
  *   -> priors: product of CPTs homed at the smallest containing clique
  *   -> evidence, collect (ascending height,id), P(e), distribute
@@ -68,7 +69,8 @@ int  orc_probe_cap(const orc_net* net, uint64_t max_entries, int32_t* clique, in
 void orc_jt_stats(const orc_jt* jt, int64_t* stats);
 /* vars in layout order; returns count */
 int  orc_jt_clique(const orc_jt* jt, int c, int32_t* vars, int cap, int32_t* height, int32_t* depth);
-/* edge e (edges numbered by ascending child id); sep vars ascending; returns count */
+/* edge e (edges numbered by ascending child id); sep vars in the separator's
+ * layout order (their order in the parent's layout); returns count */
 int  orc_jt_edge(const orc_jt* jt, int e, int32_t* parent, int32_t* child, int32_t* sep, int cap);
 /* map_e[j] for j < |parent table| */
 int  orc_jt_map(const orc_jt* jt, int e, int64_t* out, size_t cap);
