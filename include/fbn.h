@@ -171,7 +171,8 @@ fbn_status fbn_jt_stats(const fbn_jt* jt, fbn_jt_stats_t* out);
 fbn_status fbn_jt_clique(const fbn_jt* jt, int32_t c, int32_t* vars, int32_t cap, int32_t* n,
                          int32_t* height, int32_t* depth);
 /* Edge e (numbered by ascending child clique id): parent, child, separator
- * variables ascending. */
+ * variables in the separator's table layout, which is the order they take in
+ * the parent clique's layout. */
 fbn_status fbn_jt_edge(const fbn_jt* jt, int32_t e, int32_t* parent, int32_t* child,
                        int32_t* sep_vars, int32_t cap, int32_t* n);
 /* The index map of edge e: out[j] = separator entry of parent entry j, for

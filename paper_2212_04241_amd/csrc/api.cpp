@@ -189,6 +189,7 @@ struct fbn_jt {
     DTarget* d_tg = nullptr;
     DMargVar* d_mv = nullptr;
     DWork* d_works = nullptr;
+    DWTarget* d_wt = nullptr;
     DPiece* d_pc = nullptr;
     DHomeVar* d_hv = nullptr;
     DGroup* d_groups = nullptr;
@@ -317,6 +318,7 @@ fbn_status setup_device(fbn_jt* jt) {
     if ((st = upload(jt, p.targets, jt->d_tg))) return st;
     if ((st = upload(jt, p.margvars, jt->d_mv))) return st;
     if ((st = upload(jt, p.works, jt->d_works))) return st;
+    if ((st = upload(jt, p.wtargets, jt->d_wt))) return st;
     if ((st = upload(jt, p.pieces, jt->d_pc))) return st;
     if ((st = upload(jt, p.homevars, jt->d_hv))) return st;
     if ((st = upload(jt, p.groups, jt->d_groups))) return st;
@@ -380,6 +382,7 @@ fbn_status setup_device(fbn_jt* jt) {
     c.ch = jt->d_ch;
     c.tg = jt->d_tg;
     c.mv = jt->d_mv;
+    c.wt = jt->d_wt;
     c.pc = jt->d_pc;
     c.hv = jt->d_hv;
     c.dig = jt->d_dig;
@@ -406,6 +409,7 @@ fbn_status setup_device(fbn_jt* jt) {
     c.ne = jt->tree.ne;
     c.kappa_total = p.kappa_total;
     c.fp32 = f32 ? 1 : 0;
+    c.tile = p.stage;
     HIP_OK(hipStreamSynchronize(jt->stream));
     return FBN_OK;
 }
@@ -611,7 +615,9 @@ fbn_status fbn_build_jt(const fbn_net* net, const fbn_jt_options* opt_in, fbn_jt
             delete jt;
             return fail(code ? code : FBN_E_INVALID_ARG, err);
         }
-        build_plan(jt->tree, opt.tile_entries ? opt.tile_entries : 2048, jt->plan);
+        // default tile: 8 KB of table per slot, so four slots share a workgroup
+        const int def_tile = opt.precision == FBN_FP32_RESCALED ? 2048 : 1024;
+        build_plan(jt->tree, opt.tile_entries ? opt.tile_entries : def_tile, jt->plan);
         const std::string bad = check_plan(jt->tree, jt->plan);
         if (!bad.empty()) {
             delete jt;

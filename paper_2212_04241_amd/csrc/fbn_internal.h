@@ -138,13 +138,24 @@ struct DTarget {
     uint32_t nchunk;
 };
 
-// One workgroup of the distribute gather: groups [g0, g0+ng) x rows
-// [k0, k0+nk) of one target, at most one tile of entries.
+// One workgroup of the distribute gather, in one of two forms.
+//   npiece == 0: groups [g0, g0+ng) x rows [k0, k0+nk) of one target, at
+//     most one tile of entries (large cliques).
+//   npiece  > 0: whole small cliques (runs in Plan::pieces) staged once in
+//     LDS, and every target of each of them (records in Plan::wtargets).
 struct DWork {
     uint32_t target;
     uint32_t g0, ng, k0, nk;
     uint32_t nkmul, nksh;  // division by nk
     uint32_t chunk;        // k0 / nk
+    uint32_t piece0, npiece, total;
+    uint32_t wt0, nwt, nout;
+};
+
+// A target of a packed distribute workgroup: its clique is run `piece` of
+// the workgroup, and its outputs are numbered from out0 within the group.
+struct DWTarget {
+    uint32_t target, piece, out0, pad;
 };
 
 // Per-slot evidence for one clique: entry i survives the reduction when

@@ -14,6 +14,7 @@ struct Ctx {
     const DChild* ch;
     const DTarget* tg;
     const DMargVar* mv;
+    const DWTarget* wt;
     const DPiece* pc;
     const DHomeVar* hv;
     const uint64_t* dig;
@@ -33,7 +34,17 @@ struct Ctx {
     uint64_t psi_stride;
     uint32_t sep_stride, part_stride, kexp_stride, marg_stride, ev_stride;
     int32_t nvars, ne, kappa_total, fp32;
+    uint32_t tile;         // LDS entries reserved per slot in a workgroup
 };
+
+// Bytes of LDS a layer workgroup stages; slots per workgroup times tile
+// times the entry width must fit.
+constexpr int kStageBytes = 32768;
+// Slots one workgroup carries for a tile of `tile` entries of width w.
+inline int slots_per_block(uint32_t tile, int w) {
+    int b = kStageBytes / (int)(tile * (uint32_t)w);
+    return b >= 4 ? 4 : (b >= 2 ? 2 : 1);
+}
 
 // prec: 0 = float64 tables, 1 = float32 tables
 hipError_t launch_collect(const Ctx& c, int prec, const DGroup* groups, uint32_t ngroups,

@@ -15,14 +15,20 @@
 //     kept for log P(e).
 //   distribute layer (cliques of depth d, root first)
 //     phi*[i] = psi[i] * Rd_parent[pmap(i)]  (extension by new/old ratio),
-//     scattered into every child separator and every home variable's
-//     marginal (marginalisation onto non-contiguous index sets).
-//   distribute finalise: Rd = S_new / S_old (0/0 = 0), rescaled.
+//     gathered onto every child separator (marginalisation onto a
+//     non-contiguous index set): whole rows of the clique are staged in LDS
+//     and each separator entry is summed by fixed lanes in a fixed order.
+//   distribute finalise: posterior marginals from the calibrated separator;
+//     Rd = S_new / S_old (0/0 = 0), rescaled.
 //
-// The tables stream through HBM once per layer pass (coalesced runs of
-// consecutive entries); index maps come from small factored tables
-// (H[hi] + L[lo]) that stay in cache; all arithmetic on the separator
-// sums and the scale factors is float64.
+// A workgroup carries B evidence slots (cases) of the same tile: index
+// maps, packed digits and prior values are computed once per entry and
+// reused for every slot, and the per-slot gathers are independent loads in
+// flight together.  Tables stream through HBM in coalesced runs of
+// consecutive entries; index maps come from small factored tables
+// (H[hi] + L[lo]) that stay in cache; separator sums and scale factors are
+// float64.  No atomics on data, so a case gives bitwise the same result
+// alone or in any batch.
 #include <hip/hip_runtime.h>
 
 #include "kernels.h"
@@ -32,6 +38,7 @@ namespace {
 
 constexpr int kWave = 64;
 constexpr int kWaves = kBlock / kWave;
+constexpr int kMaxKids = 8;  // child maps held in registers; more use a loop
 
 __device__ __forceinline__ uint32_t mdiv(uint32_t n, uint32_t mul, uint32_t sh) {
     return (uint32_t)(((uint64_t)__umulhi(n, mul) + n) >> sh);
@@ -49,7 +56,7 @@ __device__ __forceinline__ double wave_max(double v) {
     return v;
 }
 
-// Block-wide reductions; every thread gets the result.
+// Block-wide sum; every thread gets the result.
 __device__ __forceinline__ double block_sum(double v, double* scratch) {
     v = wave_sum(v);
     const int lane = threadIdx.x & (kWave - 1), w = threadIdx.x / kWave;
@@ -62,114 +69,131 @@ __device__ __forceinline__ double block_sum(double v, double* scratch) {
     return s;
 }
 
-__device__ __forceinline__ double block_max(double v, double* scratch) {
-    v = wave_max(v);
-    const int lane = threadIdx.x & (kWave - 1), w = threadIdx.x / kWave;
-    __syncthreads();
-    if (lane == 0) scratch[w] = v;
-    __syncthreads();
-    double s = scratch[0];
-#pragma unroll
-    for (int k = 1; k < kWaves; k++) s = fmax(s, scratch[k]);
-    return s;
-}
-
 // ------------------------------------------------------------------ collect
 
-template <typename T>
+template <typename T, int B>
 __global__ __launch_bounds__(kBlock) void k_collect(Ctx c, const DGroup* __restrict__ groups,
-                                                    const int32_t* __restrict__ slots) {
-    __shared__ T vals[kTileMax];
+                                                    const int32_t* __restrict__ slots, int nslots) {
+    __shared__ __align__(16) unsigned char stage[kStageBytes];
     __shared__ DPiece pcs[kMaxPieces];
     __shared__ double red[kWaves];
+    T* vals = reinterpret_cast<T*>(stage);
     const DGroup g = groups[blockIdx.x];
-    const int slot = slots[blockIdx.y];
+    int sl[B];
+#pragma unroll
+    for (int b = 0; b < B; b++) {
+        const int k = (int)blockIdx.y * B + b;
+        sl[b] = k < nslots ? slots[k] : -1;
+    }
     for (uint32_t k = threadIdx.x; k < g.npiece; k += kBlock) pcs[k] = c.pc[g.piece0 + k];
     __syncthreads();
 
     const T* __restrict__ prior = static_cast<const T*>(c.prior);
-    T* __restrict__ psi = static_cast<T*>(c.psi) + (uint64_t)slot * c.psi_stride;
-    const T* __restrict__ sepc = static_cast<const T*>(c.sepc) + (uint64_t)slot * c.sep_stride;
-    const DEvidence* __restrict__ ev = c.ev + (uint64_t)slot * c.ev_stride;
-
+    const uint32_t* __restrict__ map = c.map;
     uint32_t p = 0;
     int cur = -1;
     DClique q{};
-    DEvidence e{};
+    DEvidence e[B];
+    uint64_t anyev = 0;
     for (uint32_t gi = threadIdx.x; gi < g.total; gi += kBlock) {
         while (gi >= pcs[p].gofs + pcs[p].count) p++;
         if ((int)p != cur) {
             cur = (int)p;
             q = c.cl[pcs[p].clique];
-            e = ev[pcs[p].clique];
+            anyev = 0;
+#pragma unroll
+            for (int b = 0; b < B; b++) {
+                e[b] = sl[b] >= 0 ? c.ev[(uint64_t)sl[b] * c.ev_stride + pcs[p].clique] : DEvidence{0, 0};
+                anyev |= e[b].mask;
+            }
         }
         const uint32_t i = pcs[p].begin + (gi - pcs[p].gofs);
         const uint32_t hi = mdiv(i, q.Lmul, q.Lsh);
         const uint32_t lo = i - hi * q.L;
-        T v = prior[q.off + i];
-        if (e.mask) {
-            const uint64_t d = c.dig[q.hdig + hi] | c.dig[q.ldig + lo];
-            if ((d ^ e.want) & e.mask) v = T(0);
+        const T pv = prior[q.off + i];
+        const uint64_t d = anyev ? (c.dig[q.hdig + hi] | c.dig[q.ldig + lo]) : 0;
+        uint32_t jk[kMaxKids];
+#pragma unroll
+        for (int k = 0; k < kMaxKids; k++)
+            if (k < (int)q.nchild) {
+                const DChild ch = c.ch[q.child0 + k];
+                jk[k] = ch.sep + map[ch.mh + hi] + map[ch.ml + lo];
+            }
+#pragma unroll
+        for (int b = 0; b < B; b++) {
+            if (sl[b] < 0) continue;
+            const T* __restrict__ sepc = static_cast<const T*>(c.sepc) + (uint64_t)sl[b] * c.sep_stride;
+            T v = ((d ^ e[b].want) & e[b].mask) ? T(0) : pv;
+#pragma unroll
+            for (int k = 0; k < kMaxKids; k++)
+                if (k < (int)q.nchild) v *= sepc[jk[k]];
+            for (uint32_t k = kMaxKids; k < q.nchild; k++) {
+                const DChild ch = c.ch[q.child0 + k];
+                v *= sepc[ch.sep + map[ch.mh + hi] + map[ch.ml + lo]];
+            }
+            static_cast<T*>(c.psi)[(uint64_t)sl[b] * c.psi_stride + q.off + i] = v;
+            vals[b * c.tile + gi] = v;
         }
-        for (uint32_t k = 0; k < q.nchild; k++) {
-            const DChild ch = c.ch[q.child0 + k];
-            v *= sepc[ch.sep + c.map[ch.mh + hi] + c.map[ch.ml + lo]];
-        }
-        psi[q.off + i] = v;
-        vals[gi] = v;
     }
     __syncthreads();
 
     // marginalise onto the parent separator: contiguous segments of q.seg
-    double* __restrict__ acc = c.acc + (uint64_t)slot * c.sep_stride;
     const int lane = threadIdx.x & (kWave - 1), wid = threadIdx.x / kWave;
-    if (g.part >= 0) {
-        double s = 0.0;
-        for (uint32_t k = threadIdx.x; k < g.total; k += kBlock) s += (double)vals[k];
-        s = block_sum(s, red);
-        if (threadIdx.x == 0) c.part[(uint64_t)slot * c.part_stride + (uint32_t)g.part] = s;
-        return;
-    }
-    for (uint32_t r = 0; r < g.npiece; r++) {
-        const DPiece pc = pcs[r];
-        const DClique qq = c.cl[pc.clique];
-        const uint32_t seg = qq.seg;
-        const uint32_t nseg = pc.count / seg;
-        const uint32_t out0 = qq.psep + pc.begin / seg;
-        if (seg >= 32) {
-            for (uint32_t s = (uint32_t)wid; s < nseg; s += kWaves) {
-                double a = 0.0;
-                for (uint32_t k = (uint32_t)lane; k < seg; k += kWave) a += (double)vals[pc.gofs + s * seg + k];
-                a = wave_sum(a);
-                if (lane == 0) acc[out0 + s] = a;
-            }
-        } else {
-            for (uint32_t s = threadIdx.x; s < nseg; s += kBlock) {
-                double a = 0.0;
-                for (uint32_t k = 0; k < seg; k++) a += (double)vals[pc.gofs + s * seg + k];
-                acc[out0 + s] = a;
+#pragma unroll
+    for (int b = 0; b < B; b++) {
+        if (sl[b] < 0) continue;
+        const T* v = vals + b * c.tile;
+        double* __restrict__ acc = c.acc + (uint64_t)sl[b] * c.sep_stride;
+        if (g.part >= 0) {
+            double s = 0.0;
+            for (uint32_t k = threadIdx.x; k < g.total; k += kBlock) s += (double)v[k];
+            s = block_sum(s, red);
+            if (threadIdx.x == 0) c.part[(uint64_t)sl[b] * c.part_stride + (uint32_t)g.part] = s;
+            continue;
+        }
+        for (uint32_t r = 0; r < g.npiece; r++) {
+            const DPiece pc = pcs[r];
+            const DClique qq = c.cl[pc.clique];
+            const uint32_t seg = qq.seg;
+            const uint32_t nseg = pc.count / seg;
+            const uint32_t out0 = qq.psep + pc.begin / seg;
+            if (seg >= 32) {
+                for (uint32_t s = (uint32_t)wid; s < nseg; s += kWaves) {
+                    double a = 0.0;
+                    for (uint32_t k = (uint32_t)lane; k < seg; k += kWave) a += (double)v[pc.gofs + s * seg + k];
+                    a = wave_sum(a);
+                    if (lane == 0) acc[out0 + s] = a;
+                }
+            } else {
+                for (uint32_t s = threadIdx.x; s < nseg; s += kBlock) {
+                    double a = 0.0;
+                    for (uint32_t k = 0; k < seg; k++) a += (double)v[pc.gofs + s * seg + k];
+                    acc[out0 + s] = a;
+                }
             }
         }
     }
 }
 
-// After a collect layer: finish each separator message (sum partial sums
-// where a segment spanned several tiles), rescale it by an exact power of two
-// so its largest entry lies in [0.5, 1), store it in table precision, record
-// the exponent, and clear the float64 accumulator for the distribute sweep.
-// The root's one-entry virtual separator yields log P(e).
+// After a collect layer, one wave per separator: finish the message (sum
+// partial sums where a segment spanned several tiles), rescale it by an
+// exact power of two so its largest entry lies in [0.5, 1), store it in
+// table precision and record the exponent.  The root's one-entry virtual
+// separator yields log P(e).
 template <typename T>
-__global__ __launch_bounds__(kBlock) void k_fin_collect(Ctx c, const DSepFin* __restrict__ fins,
+__global__ __launch_bounds__(kBlock) void k_fin_collect(Ctx c, const DSepFin* __restrict__ fins, uint32_t nfins,
                                                         const int32_t* __restrict__ slots) {
-    __shared__ double red[kWaves];
-    const DSepFin f = fins[blockIdx.x];
+    const uint32_t fi = blockIdx.x * kWaves + threadIdx.x / kWave;
+    if (fi >= nfins) return;
+    const uint32_t lane = threadIdx.x & (kWave - 1);
+    const DSepFin f = fins[fi];
     const int slot = slots[blockIdx.y];
     double* __restrict__ acc = c.acc + (uint64_t)slot * c.sep_stride;
     const double* __restrict__ part = c.part + (uint64_t)slot * c.part_stride;
     int32_t* kexp = c.kexp + (uint64_t)slot * c.kexp_stride;
 
     double mx = 0.0;
-    for (uint32_t m = threadIdx.x; m < f.size; m += kBlock) {
+    for (uint32_t m = lane; m < f.size; m += kWave) {
         double v;
         if (f.nchunk) {
             v = 0.0;
@@ -181,121 +205,197 @@ __global__ __launch_bounds__(kBlock) void k_fin_collect(Ctx c, const DSepFin* __
         }
         mx = fmax(mx, v);
     }
-    mx = block_max(mx, red);
+    mx = wave_max(mx);
 
     if (f.edge < 0) {
-        if (threadIdx.x == 0) {
+        if (lane == 0) {
             const double z = acc[f.sep];
-            acc[f.sep] = 0.0;
             long long ks = c.kappa_total;
             for (int e = 0; e < c.ne; e++) ks += kexp[e];
             if (z > 0.0) {
                 c.logpe[slot] = log(z) + 0.69314718055994530942 * (double)ks;
             } else {
                 c.logpe[slot] = -INFINITY;
-                c.flags[slot] |= c.fp32 ? 2 : 1;
+                atomicOr(&c.flags[slot], c.fp32 ? 2 : 1);
             }
         }
         return;
     }
     int k = 0;
-    if (mx > 0.0) {
-        frexp(mx, &k);
-    } else if (threadIdx.x == 0) {
-        c.flags[slot] |= c.fp32 ? 2 : 1;
-    }
+    if (mx > 0.0) frexp(mx, &k);
+    else if (lane == 0) atomicOr(&c.flags[slot], c.fp32 ? 2 : 1);
     const double scale = ldexp(1.0, -k);
     T* __restrict__ sepc = static_cast<T*>(c.sepc) + (uint64_t)slot * c.sep_stride;
-    for (uint32_t m = threadIdx.x; m < f.size; m += kBlock) sepc[f.sep + m] = (T)(acc[f.sep + m] * scale);
-    if (threadIdx.x == 0) kexp[f.edge] = k;
+    for (uint32_t m = lane; m < f.size; m += kWave) sepc[f.sep + m] = (T)(acc[f.sep + m] * scale);
+    if (lane == 0) kexp[f.edge] = k;
 }
 
 // --------------------------------------------------------------- distribute
 
-// One workgroup marginalises a block of one clique onto one target
-// separator: it stages ng groups x nk rows of the clique (each row L
-// consecutive entries, read coalesced and extended by the parent's
-// distribute ratio on the way in) in LDS, then every separator entry of the
-// block is summed by a fixed set of lanes in a fixed order -- no atomics,
-// so results do not depend on scheduling.
-template <typename T>
+// One workgroup marginalises clique entries onto target separators, for B
+// slots at once.
+//   Large clique: ng groups x nk rows of one target (each row L consecutive
+//   entries, read coalesced and extended by the parent's distribute ratio
+//   on the way in) are staged in LDS; every separator entry of the block is
+//   summed by a fixed set of lanes in a fixed order.
+//   Packed small cliques: each whole clique is staged once, and all of its
+//   targets are summed from LDS.
+template <typename T, int B>
 __global__ __launch_bounds__(kBlock) void k_dist_gather(Ctx c, const DWork* __restrict__ works,
-                                                        const int32_t* __restrict__ slots) {
-    __shared__ T vals[kTileMax];
+                                                        const int32_t* __restrict__ slots, int nslots) {
+    __shared__ __align__(16) unsigned char stage[kStageBytes];
+    __shared__ DPiece pcs[kMaxPieces];
+    __shared__ DWTarget wts[kMaxPieces];
+    T* vals = reinterpret_cast<T*>(stage);
     const DWork w = works[blockIdx.x];
-    const int slot = slots[blockIdx.y];
-    const DTarget tg = c.tg[w.target];
-    const DClique q = c.cl[tg.clique];
-    const T* __restrict__ psi = static_cast<const T*>(c.psi) + (uint64_t)slot * c.psi_stride + q.off;
-    const T* __restrict__ sepd = static_cast<const T*>(c.sepd) + (uint64_t)slot * c.sep_stride;
+    int sl[B];
+#pragma unroll
+    for (int b = 0; b < B; b++) {
+        const int k = (int)blockIdx.y * B + b;
+        sl[b] = k < nslots ? slots[k] : -1;
+    }
     const uint32_t* __restrict__ map = c.map;
+    const uint32_t lane = threadIdx.x & (kWave - 1);
+    const bool packed = w.npiece > 0;
 
-    const uint32_t n = w.ng * w.nk * q.L;
-    for (uint32_t idx = threadIdx.x; idx < n; idx += kBlock) {
-        const uint32_t ri = mdiv(idx, q.Lmul, q.Lsh);
-        const uint32_t l = idx - ri * q.L;
-        const uint32_t gg = mdiv(ri, w.nkmul, w.nksh);
-        const uint32_t k = ri - gg * w.nk;
-        const uint32_t row = map[tg.rg + w.g0 + gg] + map[tg.rq + w.k0 + k];
-        T v = psi[row * q.L + l];
-        if (q.pedge >= 0) v *= sepd[q.psep + map[q.pmh + row] + map[q.pml + l]];
-        vals[idx] = v;
+    // ---- stage: phi* = psi * parent ratio, for every slot
+    DTarget tg{};
+    DClique q{};
+    uint32_t n;
+    if (packed) {
+        for (uint32_t k = threadIdx.x; k < w.npiece; k += kBlock) pcs[k] = c.pc[w.piece0 + k];
+        for (uint32_t k = threadIdx.x; k < w.nwt; k += kBlock) wts[k] = c.wt[w.wt0 + k];
+        __syncthreads();
+        n = w.total;
+    } else {
+        tg = c.tg[w.target];
+        q = c.cl[tg.clique];
+        n = w.ng * w.nk * q.L;
+    }
+    uint32_t p = 0;
+    int cur = -1;
+    for (uint32_t gi = threadIdx.x; gi < n; gi += kBlock) {
+        uint64_t ent;   // entry index within the clique
+        uint32_t row, l;
+        if (packed) {
+            while (gi >= pcs[p].gofs + pcs[p].count) p++;
+            if ((int)p != cur) {
+                cur = (int)p;
+                q = c.cl[pcs[p].clique];
+            }
+            ent = gi - pcs[p].gofs;
+            row = mdiv((uint32_t)ent, q.Lmul, q.Lsh);
+            l = (uint32_t)ent - row * q.L;
+        } else {
+            const uint32_t ri = mdiv(gi, q.Lmul, q.Lsh);
+            l = gi - ri * q.L;
+            const uint32_t gg = mdiv(ri, w.nkmul, w.nksh);
+            const uint32_t k = ri - gg * w.nk;
+            row = map[tg.rg + w.g0 + gg] + map[tg.rq + w.k0 + k];
+            ent = (uint64_t)row * q.L + l;
+        }
+        const uint32_t pr = q.pedge >= 0 ? q.psep + map[q.pmh + row] + map[q.pml + l] : 0u;
+#pragma unroll
+        for (int b = 0; b < B; b++) {
+            if (sl[b] < 0) continue;
+            T v = static_cast<const T*>(c.psi)[(uint64_t)sl[b] * c.psi_stride + q.off + ent];
+            if (q.pedge >= 0) v *= static_cast<const T*>(c.sepd)[(uint64_t)sl[b] * c.sep_stride + pr];
+            vals[b * c.tile + gi] = v;
+        }
     }
     __syncthreads();
 
-    // outputs (gg, t); tpo lanes per output, power of two within a wave
-    const uint32_t nout = w.ng * tg.nPL;
+    // ---- outputs: tpo lanes per separator entry, B sums each
+    const uint32_t nout = packed ? w.nout : w.ng * tg.nPL;
     uint32_t tpo = 1;
     while (tpo < 64 && tpo * 2 * nout <= (uint32_t)kBlock) tpo *= 2;
-    const uint32_t sub = threadIdx.x & (tpo - 1);
-    const uint32_t per = w.nk * tg.nQL;  // summands of one output
-    double* __restrict__ acc = c.acc + (uint64_t)slot * c.sep_stride;
-    double* __restrict__ part = c.part + (uint64_t)slot * c.part_stride;
+    const uint32_t sub = lane & (tpo - 1);
+    uint32_t a = 0;
     for (uint32_t base = 0; base < nout * tpo; base += kBlock) {
         const uint32_t o = (base + threadIdx.x) / tpo;
-        double s = 0.0;
-        uint32_t gg = 0, t = 0;
+        double s[B];
+#pragma unroll
+        for (int b = 0; b < B; b++) s[b] = 0.0;
+        uint32_t m = 0, sep = 0, gofs = 0;
+        int32_t part0 = -1;
+        uint32_t nchunk = 0;
         if (o < nout) {
-            gg = o / tg.nPL;
-            t = o - gg * tg.nPL;
-            const uint32_t lp = map[tg.lp + t];
-            for (uint32_t j = sub; j < per; j += tpo) {
-                const uint32_t k = j / tg.nQL;
-                const uint32_t u = j - k * tg.nQL;
-                s += (double)vals[(gg * w.nk + k) * q.L + lp + map[tg.lq + u]];
+            DTarget t2 = tg;
+            uint32_t L = q.L, g, t, nk, rowbase;
+            if (packed) {
+                while (a + 1 < w.nwt && o >= wts[a + 1].out0) a++;
+                const DWTarget wt = wts[a];
+                t2 = c.tg[wt.target];
+                const DPiece pc = pcs[wt.piece];
+                L = c.cl[pc.clique].L;
+                gofs = pc.gofs;
+                const uint32_t oo = o - wt.out0;
+                g = oo / t2.nPL;
+                t = oo - g * t2.nPL;
+                nk = t2.NQ;
+                rowbase = 0;
+                m = map[t2.tb + g] + map[t2.tv + t];
+            } else {
+                g = o / t2.nPL;
+                t = o - g * t2.nPL;
+                nk = w.nk;
+                rowbase = g * w.nk;
+                m = map[t2.tb + w.g0 + g] + map[t2.tv + t];
             }
+            const uint32_t lp = map[t2.lp + t];
+            const uint32_t per = nk * t2.nQL;
+            for (uint32_t j = sub; j < per; j += tpo) {
+                const uint32_t k = j / t2.nQL;
+                const uint32_t u = j - k * t2.nQL;
+                const uint32_t row = packed ? map[t2.rg + g] + map[t2.rq + k] : rowbase + k;
+                const uint32_t idx = gofs + row * L + lp + map[t2.lq + u];
+#pragma unroll
+                for (int b = 0; b < B; b++) s[b] += (double)vals[b * c.tile + idx];
+            }
+            sep = t2.sep;
+            part0 = t2.part0;
+            nchunk = t2.nchunk;
         }
-        for (uint32_t o2 = tpo / 2; o2 > 0; o2 >>= 1) s += __shfl_xor(s, (int)o2, kWave);
+#pragma unroll
+        for (int b = 0; b < B; b++)
+            for (uint32_t o2 = tpo / 2; o2 > 0; o2 >>= 1) s[b] += __shfl_xor(s[b], (int)o2, kWave);
         if (o < nout && sub == 0) {
-            const uint32_t m = map[tg.tb + w.g0 + gg] + map[tg.tv + t];
-            if (tg.part0 < 0) acc[tg.sep + m] = s;
-            else part[(uint32_t)tg.part0 + m * tg.nchunk + w.chunk] = s;
+#pragma unroll
+            for (int b = 0; b < B; b++) {
+                if (sl[b] < 0) continue;
+                if (part0 < 0) c.acc[(uint64_t)sl[b] * c.sep_stride + sep + m] = s[b];
+                else c.part[(uint64_t)sl[b] * c.part_stride + (uint32_t)part0 + m * nchunk + w.chunk] = s[b];
+            }
         }
     }
 }
 
-// After a distribute layer, per separator (real or one-variable virtual):
-// finish the new separator table S* (summing partials), read the posterior
-// marginals of the variables assigned to it, and for a real separator form
-// the new/old ratio S*/S (0/0 = 0) rescaled by an exact power of two.
+// After a distribute layer, one wave per separator (real or one-variable
+// virtual): finish the new separator table S* (summing partials), read the
+// posterior marginals of the variables assigned to it, and for a real
+// separator form the new/old ratio S*/S (0/0 = 0) rescaled by an exact
+// power of two.
 template <typename T>
-__global__ __launch_bounds__(kBlock) void k_fin_distribute(Ctx c, const DSepFin* __restrict__ fins,
+__global__ __launch_bounds__(kBlock) void k_fin_distribute(Ctx c, const DSepFin* __restrict__ fins, uint32_t nfins,
                                                            const int32_t* __restrict__ slots) {
-    __shared__ double red[kWaves];
-    const DSepFin f = fins[blockIdx.x];
+    const uint32_t fi = blockIdx.x * kWaves + threadIdx.x / kWave;
+    if (fi >= nfins) return;
+    const uint32_t lane = threadIdx.x & (kWave - 1);
+    const DSepFin f = fins[fi];
     const int slot = slots[blockIdx.y];
     double* __restrict__ acc = c.acc + (uint64_t)slot * c.sep_stride;
     const double* __restrict__ part = c.part + (uint64_t)slot * c.part_stride;
     if (f.nchunk) {
-        for (uint32_t m = threadIdx.x; m < f.size; m += kBlock) {
+        for (uint32_t m = lane; m < f.size; m += kWave) {
             double v = 0.0;
             const double* pp = part + f.part0 + (uint64_t)m * f.nchunk;
             for (uint32_t k = 0; k < f.nchunk; k++) v += pp[k];
             acc[f.sep + m] = v;
         }
-        __syncthreads();
+        // other lanes of this wave read these sums below
+        __threadfence_block();
     }
-    // posteriors: each state of each assigned variable is a block-wide sum
+    // posteriors: each state of each assigned variable is a wave-wide sum
     // over the separator entries carrying that state
     double* __restrict__ marg = c.marg + (uint64_t)slot * c.marg_stride;
     for (uint32_t a = 0; a < f.nmv; a++) {
@@ -303,31 +403,29 @@ __global__ __launch_bounds__(kBlock) void k_fin_distribute(Ctx c, const DSepFin*
         const uint32_t per = f.size / mv.card;
         for (uint32_t x = 0; x < mv.card; x++) {
             double s = 0.0;
-            for (uint32_t e = threadIdx.x; e < per; e += kBlock) {
+            for (uint32_t e = lane; e < per; e += kWave) {
                 const uint32_t o = e / mv.stride;
                 s += acc[f.sep + (o * mv.card + x) * mv.stride + (e - o * mv.stride)];
             }
-            s = block_sum(s, red);
-            if (threadIdx.x == 0) marg[mv.out + x] = s;
+            s = wave_sum(s);
+            if (lane == 0) marg[mv.out + x] = s;
         }
     }
     if (f.edge < 0) return;
     const T* __restrict__ sepc = static_cast<const T*>(c.sepc) + (uint64_t)slot * c.sep_stride;
     T* __restrict__ sepd = static_cast<T*>(c.sepd) + (uint64_t)slot * c.sep_stride;
     double mx = 0.0;
-    for (uint32_t m = threadIdx.x; m < f.size; m += kBlock) {
+    for (uint32_t m = lane; m < f.size; m += kWave) {
         const double den = (double)sepc[f.sep + m];
-        const double r = den == 0.0 ? 0.0 : acc[f.sep + m] / den;
-        mx = fmax(mx, r);
+        mx = fmax(mx, den == 0.0 ? 0.0 : acc[f.sep + m] / den);
     }
-    mx = block_max(mx, red);
+    mx = wave_max(mx);
     int k = 0;
     if (mx > 0.0) frexp(mx, &k);
     const double scale = ldexp(1.0, -k);
-    for (uint32_t m = threadIdx.x; m < f.size; m += kBlock) {
+    for (uint32_t m = lane; m < f.size; m += kWave) {
         const double den = (double)sepc[f.sep + m];
-        const double r = den == 0.0 ? 0.0 : acc[f.sep + m] / den;
-        sepd[f.sep + m] = (T)(r * scale);
+        sepd[f.sep + m] = (T)((den == 0.0 ? 0.0 : acc[f.sep + m] / den) * scale);
     }
 }
 
@@ -379,41 +477,71 @@ __global__ void k_zero(uint32_t* __restrict__ p, size_t words) {
         p[k] = 0u;
 }
 
+template <typename T, int B>
+void launch_collect_b(const Ctx& c, const DGroup* groups, uint32_t ngroups, const int32_t* slots, int nslots,
+                      hipStream_t s) {
+    dim3 grid(ngroups, (unsigned)((nslots + B - 1) / B));
+    hipLaunchKernelGGL((k_collect<T, B>), grid, dim3(kBlock), 0, s, c, groups, slots, nslots);
+}
+
+template <typename T, int B>
+void launch_gather_b(const Ctx& c, const DWork* works, uint32_t nworks, const int32_t* slots, int nslots,
+                     hipStream_t s) {
+    dim3 grid(nworks, (unsigned)((nslots + B - 1) / B));
+    hipLaunchKernelGGL((k_dist_gather<T, B>), grid, dim3(kBlock), 0, s, c, works, slots, nslots);
+}
+
+template <typename T>
+void launch_collect_t(const Ctx& c, const DGroup* groups, uint32_t ngroups, const int32_t* slots, int nslots,
+                      hipStream_t s) {
+    const int B = nslots >= 4 ? slots_per_block(c.tile, sizeof(T)) : 1;
+    if (B >= 4) launch_collect_b<T, 4>(c, groups, ngroups, slots, nslots, s);
+    else if (B == 2) launch_collect_b<T, 2>(c, groups, ngroups, slots, nslots, s);
+    else launch_collect_b<T, 1>(c, groups, ngroups, slots, nslots, s);
+}
+
+template <typename T>
+void launch_gather_t(const Ctx& c, const DWork* works, uint32_t nworks, const int32_t* slots, int nslots,
+                     hipStream_t s) {
+    const int B = nslots >= 4 ? slots_per_block(c.tile, sizeof(T)) : 1;
+    if (B >= 4) launch_gather_b<T, 4>(c, works, nworks, slots, nslots, s);
+    else if (B == 2) launch_gather_b<T, 2>(c, works, nworks, slots, nslots, s);
+    else launch_gather_b<T, 1>(c, works, nworks, slots, nslots, s);
+}
+
 }  // namespace
 
 hipError_t launch_collect(const Ctx& c, int prec, const DGroup* groups, uint32_t ngroups, const int32_t* slots,
                           int nslots, hipStream_t s) {
     if (!ngroups || !nslots) return hipSuccess;
-    dim3 grid(ngroups, (unsigned)nslots);
-    if (prec) hipLaunchKernelGGL(k_collect<float>, grid, dim3(kBlock), 0, s, c, groups, slots);
-    else hipLaunchKernelGGL(k_collect<double>, grid, dim3(kBlock), 0, s, c, groups, slots);
+    if (prec) launch_collect_t<float>(c, groups, ngroups, slots, nslots, s);
+    else launch_collect_t<double>(c, groups, ngroups, slots, nslots, s);
     return hipGetLastError();
 }
 
 hipError_t launch_fin_collect(const Ctx& c, int prec, const DSepFin* fins, uint32_t nfins, const int32_t* slots,
                               int nslots, hipStream_t s) {
     if (!nfins || !nslots) return hipSuccess;
-    dim3 grid(nfins, (unsigned)nslots);
-    if (prec) hipLaunchKernelGGL(k_fin_collect<float>, grid, dim3(kBlock), 0, s, c, fins, slots);
-    else hipLaunchKernelGGL(k_fin_collect<double>, grid, dim3(kBlock), 0, s, c, fins, slots);
+    dim3 grid((nfins + kWaves - 1) / kWaves, (unsigned)nslots);
+    if (prec) hipLaunchKernelGGL(k_fin_collect<float>, grid, dim3(kBlock), 0, s, c, fins, nfins, slots);
+    else hipLaunchKernelGGL(k_fin_collect<double>, grid, dim3(kBlock), 0, s, c, fins, nfins, slots);
     return hipGetLastError();
 }
 
 hipError_t launch_distribute(const Ctx& c, int prec, const DWork* works, uint32_t nworks, const int32_t* slots,
                              int nslots, hipStream_t s) {
     if (!nworks || !nslots) return hipSuccess;
-    dim3 grid(nworks, (unsigned)nslots);
-    if (prec) hipLaunchKernelGGL(k_dist_gather<float>, grid, dim3(kBlock), 0, s, c, works, slots);
-    else hipLaunchKernelGGL(k_dist_gather<double>, grid, dim3(kBlock), 0, s, c, works, slots);
+    if (prec) launch_gather_t<float>(c, works, nworks, slots, nslots, s);
+    else launch_gather_t<double>(c, works, nworks, slots, nslots, s);
     return hipGetLastError();
 }
 
 hipError_t launch_fin_distribute(const Ctx& c, int prec, const DSepFin* fins, uint32_t nfins, const int32_t* slots,
                                  int nslots, hipStream_t s) {
     if (!nfins || !nslots) return hipSuccess;
-    dim3 grid(nfins, (unsigned)nslots);
-    if (prec) hipLaunchKernelGGL(k_fin_distribute<float>, grid, dim3(kBlock), 0, s, c, fins, slots);
-    else hipLaunchKernelGGL(k_fin_distribute<double>, grid, dim3(kBlock), 0, s, c, fins, slots);
+    dim3 grid((nfins + kWaves - 1) / kWaves, (unsigned)nslots);
+    if (prec) hipLaunchKernelGGL(k_fin_distribute<float>, grid, dim3(kBlock), 0, s, c, fins, nfins, slots);
+    else hipLaunchKernelGGL(k_fin_distribute<double>, grid, dim3(kBlock), 0, s, c, fins, nfins, slots);
     return hipGetLastError();
 }
 

@@ -164,6 +164,30 @@ std::string check_plan(const Tree& t, const Plan& p) {
         if ((uint64_t)ly.fin0 + ly.nfin > p.fins.size()) return "layer fins";
         for (uint32_t w = ly.group0; w < ly.group0 + ly.ngroup; w++) {
             const DWork& W = p.works[w];
+            if (W.npiece > 0) {
+                // packed: whole cliques staged in LDS and all their targets
+                if (W.npiece > (uint32_t)kMaxPieces || (uint64_t)W.piece0 + W.npiece > p.pieces.size()) return "packed pieces";
+                if (W.total == 0 || W.total > (uint32_t)kTileMax) return "packed tile";
+                uint32_t ofs = 0;
+                for (uint32_t k = 0; k < W.npiece; k++) {
+                    const DPiece& pc = p.pieces[W.piece0 + k];
+                    if (pc.clique >= nc || pc.begin != 0 || pc.count != p.cliques[pc.clique].size || pc.gofs != ofs)
+                        return "packed piece layout";
+                    ofs += pc.count;
+                }
+                if (ofs != W.total) return "packed total";
+                if (W.nwt == 0 || W.nwt > (uint32_t)kMaxPieces || (uint64_t)W.wt0 + W.nwt > p.wtargets.size()) return "packed targets";
+                uint32_t outs = 0;
+                for (uint32_t k = 0; k < W.nwt; k++) {
+                    const DWTarget& wt = p.wtargets[W.wt0 + k];
+                    if (wt.target >= p.targets.size() || wt.piece >= W.npiece || wt.out0 != outs) return "packed target record";
+                    const DTarget& tg = p.targets[wt.target];
+                    if (tg.clique != p.pieces[W.piece0 + wt.piece].clique || tg.part0 >= 0) return "packed target clique";
+                    outs += tg.G * tg.nPL;
+                }
+                if (outs != W.nout) return "packed outputs";
+                continue;
+            }
             if (W.target >= p.targets.size()) return "work target";
             const DTarget& tg = p.targets[W.target];
             if (tg.clique >= nc) return "target clique";
@@ -213,6 +237,13 @@ std::string check_plan(const Tree& t, const Plan& p) {
         }
     }
     if ((uint64_t)p.sep_stride < (uint64_t)p.sep_real) return "separator stride";
+    if (p.stage == 0 || p.stage > (uint32_t)kTileMax) return "stage size";
+    for (const DGroup& g : p.groups)
+        if (g.total > p.stage) return "group exceeds stage";
+    for (const DWork& w : p.works) {
+        const uint32_t n = w.npiece ? w.total : w.ng * w.nk * p.cliques[p.targets[w.target].clique].L;
+        if (n > p.stage) return "work exceeds stage";
+    }
     return "";
 }
 
@@ -437,6 +468,7 @@ void build_plan(const Tree& t, int tile, Plan& p) {
     for (int dd = 0; dd <= D; dd++) {
         Layer& ly = p.distribute[(size_t)dd];
         ly.group0 = (uint32_t)p.works.size();
+        int32_t open_w = -1;  // open packed workgroup of this layer
         std::vector<DSepFin> fins;
         for (int c = 0; c < nc; c++) {
             if (t.depth[(size_t)c] != dd) continue;
@@ -471,6 +503,27 @@ void build_plan(const Tree& t, int tile, Plan& p) {
             }
             for (int v : lay)
                 if (p.post_sep[(size_t)v] < 0) tgts.push_back({{v}, vsep_off[(size_t)v], -2});
+            const uint32_t dtile_c = std::min<uint32_t>((uint32_t)kTileMax, std::max(dtile_base, d.L));
+            const bool packed = d.size <= dtile_c;
+            if (packed) {
+                if (open_w >= 0) {
+                    const DWork& W = p.works[(size_t)open_w];
+                    if (W.total + d.size > dtile_c || W.npiece >= (uint32_t)kMaxPieces ||
+                        W.nwt + tgts.size() > (size_t)kMaxPieces)
+                        open_w = -1;
+                }
+                if (open_w < 0) {
+                    DWork W{};
+                    W.piece0 = (uint32_t)p.pieces.size();
+                    W.wt0 = (uint32_t)p.wtargets.size();
+                    p.works.push_back(W);
+                    open_w = (int32_t)p.works.size() - 1;
+                }
+                DWork& W = p.works[(size_t)open_w];
+                p.pieces.push_back({(uint32_t)c, 0u, d.size, W.total});
+                W.npiece++;
+                W.total += d.size;
+            }
             for (const Tgt& tg0 : tgts) {
                 // target strides (ascending variable order, last fastest)
                 std::vector<uint64_t> tstride((size_t)m, 0);
@@ -511,9 +564,14 @@ void build_plan(const Tree& t, int tile, Plan& p) {
                 T.part0 = -1;
                 T.nchunk = 0;
                 const uint32_t ti = (uint32_t)p.targets.size();
-                const uint32_t dtile = std::min<uint32_t>((uint32_t)kTileMax, std::max(dtile_base, d.L));
+                const uint32_t dtile = dtile_c;
                 const uint64_t group_entries = (uint64_t)T.NQ * d.L;
-                if (group_entries <= dtile) {
+                if (packed) {
+                    DWork& W = p.works[(size_t)open_w];
+                    p.wtargets.push_back({ti, W.npiece - 1, W.nout, 0u});
+                    W.nwt++;
+                    W.nout += T.G * T.nPL;
+                } else if (group_entries <= dtile) {
                     const uint32_t per = std::max<uint32_t>(1, (uint32_t)(dtile / group_entries));
                     for (uint32_t g0 = 0; g0 < T.G; g0 += per) {
                         DWork W{};
@@ -579,6 +637,12 @@ void build_plan(const Tree& t, int tile, Plan& p) {
         p.fins.insert(p.fins.end(), fins.begin(), fins.end());
     }
     p.n_parts = parts;
+    p.stage = (uint32_t)tile;
+    for (const DGroup& g : p.groups) p.stage = std::max(p.stage, g.total);
+    for (const DWork& w : p.works) {
+        const uint32_t n = w.npiece ? w.total : w.ng * w.nk * p.cliques[p.targets[w.target].clique].L;
+        p.stage = std::max(p.stage, n);
+    }
 }
 
 }  // namespace fbn

@@ -13,6 +13,7 @@ struct Layer {
 
 struct Plan {
     int tile = 2048;
+    uint32_t stage = 0;               // LDS entries per slot: largest collect tile or distribute block
     uint64_t T = 0;                   // prior / working-table entries
     uint32_t sep_total = 0;           // separator entries over all edges
     uint32_t sep_stride = 0;          // per slot: sep_total + 1 (root's virtual entry) rounded
@@ -28,6 +29,7 @@ struct Plan {
     std::vector<DSepFin> fins;
     std::vector<DTarget> targets;     // distribute marginalisations
     std::vector<DWork> works;         // distribute workgroups
+    std::vector<DWTarget> wtargets;   // targets of packed distribute workgroups
     std::vector<DMargVar> margvars;   // posterior variables per finalised separator
     std::vector<int> post_sep;        // per variable: edge whose separator gives its posterior, -1 virtual
     uint32_t sep_real = 0;            // entries of real separators + the root's virtual entry

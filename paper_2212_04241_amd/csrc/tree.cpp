@@ -266,33 +266,41 @@ std::string compile_tree(const Net& net, uint64_t max_entries, Tree& t, int& cod
             if (t.parent[c] >= 0) t.children[t.parent[c]].push_back(c);
     }
 
-    // ---- edges by ascending child id, separators ascending, layouts
+    // ---- edges by ascending child id; then layouts from the root down: the
+    // root ascending, a separator in the order its variables take in the
+    // parent's layout, a non-root clique [parent separator] ++ [rest ascending]
     t.pedge.assign(nc, -1);
     t.vars.assign(nc, {});
     t.size = csize;
+    std::vector<std::vector<int>> rest(nc);
     for (int c = 0; c < nc; c++) {
+        if (c == root) continue;
+        const int p = t.parent[c];
+        uint64_t ssz = 1;
+        for (int v : asc[c]) {
+            if (cliques[p].test(v)) ssz *= (uint64_t)net.card[v];
+            else rest[c].push_back(v);
+        }
+        t.pedge[c] = t.ne++;
+        t.e_parent.push_back(p);
+        t.e_child.push_back(c);
+        t.e_sep.push_back({});
+        t.e_size.push_back(ssz);
+    }
+    std::vector<int> topdown(nc);
+    std::iota(topdown.begin(), topdown.end(), 0);
+    std::stable_sort(topdown.begin(), topdown.end(), [&](int a, int b) { return t.depth[a] < t.depth[b]; });
+    for (int c : topdown) {
         if (c == root) {
             t.vars[c] = asc[c];
             continue;
         }
         const int p = t.parent[c];
-        std::vector<int> sep, rest;
-        uint64_t ssz = 1;
-        for (int v : asc[c]) {
-            if (cliques[p].test(v)) {
-                sep.push_back(v);
-                ssz *= (uint64_t)net.card[v];
-            } else {
-                rest.push_back(v);
-            }
-        }
-        t.pedge[c] = t.ne++;
-        t.e_parent.push_back(p);
-        t.e_child.push_back(c);
-        t.e_sep.push_back(sep);
-        t.e_size.push_back(ssz);
+        std::vector<int>& sep = t.e_sep[(size_t)t.pedge[c]];
+        for (int v : t.vars[p])
+            if (cliques[c].test(v)) sep.push_back(v);
         std::vector<int> lay = sep;
-        lay.insert(lay.end(), rest.begin(), rest.end());
+        lay.insert(lay.end(), rest[c].begin(), rest[c].end());
         t.vars[c] = lay;
     }
 

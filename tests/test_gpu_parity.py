@@ -136,6 +136,47 @@ def test_random_nets_fp32(seed):
     check_fp32(post, lp, st, ref, f"fp32 seed {seed}")
 
 
+@pytest.fixture(scope="module")
+def c3():
+    net = fbngen.make_net("C3", 0)
+    cases = fbngen.make_cases("C3", net)[:4]
+    ref, ojt = oracle_run(net, cases)
+    return net, cases, ref
+
+
+@pytest.mark.timeout(600)
+def test_c3_huge_clique_fp64(c3):
+    # ~1.3e7-entry clique: segments and gathers split across workgroups
+    net, cases, ref = c3
+    say("C3 fp64", len(cases[:2]))
+    post, lp, st, _ = gpu_run(net, cases[:2])
+    check_fp64(post, lp, st, ref[:2], "C3 fp64")
+
+
+@pytest.mark.timeout(600)
+def test_c3_huge_clique_fp32(c3):
+    net, cases, ref = c3
+    say("C3 fp32", len(cases))
+    post, lp, st, _ = gpu_run(net, cases, precision=fbn.FBN_FP32_RESCALED)
+    say("C3 fp32 worst abs error", check_fp32(post, lp, st, ref, "C3 fp32"))
+
+
+@pytest.mark.timeout(600)
+def test_c5_network_fp64_and_fp32():
+    net = fbngen.make_net("C5", 7)
+    rng = np.random.default_rng(7)
+    cases = []
+    for k in range(3):
+        seed = int(rng.integers(0, 2**62))
+        cases.append(fbngen.case_for_arrival(net, [0.02, 0.1, 0.2][k], seed))
+    say("C5 net 7", net.n)
+    ref, _ = oracle_run(net, cases)
+    post, lp, st, _ = gpu_run(net, cases)
+    check_fp64(post, lp, st, ref, "C5 fp64")
+    post, lp, st, _ = gpu_run(net, cases, precision=fbn.FBN_FP32_RESCALED)
+    say("C5 fp32 worst abs error", check_fp32(post, lp, st, ref, "C5 fp32"))
+
+
 # ------------------------------------------------------------------ edge cases
 
 def test_degenerate_networks():
