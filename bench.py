@@ -146,6 +146,9 @@ def main():
     ap.add_argument("--plain-queries", type=int, default=300)
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--fp32-only", action="store_true", help="time only the FP32 batched path (for profiling)")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="also run plain 512 MiB device copies (reference for byte counters)")
     args = ap.parse_args()
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
@@ -169,6 +172,21 @@ def main():
     qps32 = n * args.steps / dt32
     log(f"[bench] fp32 batched: {qps32:.1f} q/s, {1e3 * dt32 / args.steps:.3f} ms/step")
     jt32.free()
+    if args.copy_calibration:
+        # a plain device copy of known size, so that byte counters taken in
+        # the same run can be scaled (read 512 MiB, write 512 MiB, three times)
+        import torch
+        src = torch.ones(128 << 20, dtype=torch.float32, device="cuda")
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        log("[bench] copy calibration: 3 x 512 MiB device copies")
+    if args.fp32_only:
+        # profiling runs: the headline path alone
+        print(json.dumps({"value": round(qps32, 1), "unit": "queries/s", "ms_per_step": 1e3 * dt32 / args.steps,
+                          "kernel_ms_per_step": {k: v[0] / args.steps for k, v in prof32.items()}}), flush=True)
+        return
     # FP64 batched
     jt64, dt64, _, post64, lp64, st64 = time_batched(fbn, net, cases, fbn.FBN_FP64, max(1, args.steps // 2),
                                                      1, False)

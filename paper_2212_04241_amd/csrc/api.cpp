@@ -616,8 +616,9 @@ fbn_status fbn_build_jt(const fbn_net* net, const fbn_jt_options* opt_in, fbn_jt
             return fail(code ? code : FBN_E_INVALID_ARG, err);
         }
         // default tile: 8 KB of table per slot, so four slots share a workgroup
-        const int def_tile = opt.precision == FBN_FP32_RESCALED ? 2048 : 1024;
-        build_plan(jt->tree, opt.tile_entries ? opt.tile_entries : def_tile, jt->plan);
+        const int def_tile = opt.precision == FBN_FP32_RESCALED ? 1024 : 512;
+        const uint32_t max_stage = (uint32_t)kStageBytes / (opt.precision == FBN_FP32_RESCALED ? 4u : 8u);
+        build_plan(jt->tree, opt.tile_entries ? opt.tile_entries : def_tile, max_stage, jt->plan);
         const std::string bad = check_plan(jt->tree, jt->plan);
         if (!bad.empty()) {
             delete jt;
@@ -757,7 +758,7 @@ fbn_status fbn_calibrate(fbn_jt* jt, int32_t n, const int32_t* slots, double* lo
              })))
             return st;
         if ((st = timed(jt, 1, 2.0 * w * nb * (double)jt->coll_sep[h], [&] {
-                 return launch_fin_collect(c, prec, jt->d_fins + ly.fin0, ly.nfin, jt->d_slots, n, s);
+                 return launch_fin_collect(c, prec, jt->d_fins + ly.fin0, ly.nfin, ly.nbig, jt->d_slots, n, s);
              })))
             return st;
     }
@@ -769,7 +770,7 @@ fbn_status fbn_calibrate(fbn_jt* jt, int32_t n, const int32_t* slots, double* lo
              })))
             return st;
         if ((st = timed(jt, 3, 2.0 * w * nb * (double)jt->dist_sep[d], [&] {
-                 return launch_fin_distribute(c, prec, jt->d_fins + ly.fin0, ly.nfin, jt->d_slots, n, s);
+                 return launch_fin_distribute(c, prec, jt->d_fins + ly.fin0, ly.nfin, ly.nbig, jt->d_slots, n, s);
              })))
             return st;
     }

@@ -119,7 +119,8 @@ struct DMargVar {
     uint32_t out;        // offset of its first state in the per-slot marginal arrays
     uint32_t stride;     // stride of the variable in the separator layout
     uint32_t card;
-    uint32_t pad;
+    uint32_t smul, ssh;  // division by stride
+    uint32_t pad[3];
 };
 
 // Distribute-sweep marginalisation of clique C onto a target separator S
@@ -170,6 +171,6 @@ struct DHomeVar {        // for the posterior finaliser: one per variable
 
 constexpr int kBlock = 256;       // threads per workgroup
 constexpr int kTileMax = 4096;    // entries per workgroup tile
-constexpr int kMaxPieces = 64;    // runs per workgroup
+constexpr int kMaxPieces = 32;    // runs (and packed targets) per workgroup
 
 }  // namespace fbn

@@ -39,7 +39,7 @@ struct Ctx {
 
 // Bytes of LDS a layer workgroup stages; slots per workgroup times tile
 // times the entry width must fit.
-constexpr int kStageBytes = 32768;
+constexpr int kStageBytes = 16384;
 // Slots one workgroup carries for a tile of `tile` entries of width w.
 inline int slots_per_block(uint32_t tile, int w) {
     int b = kStageBytes / (int)(tile * (uint32_t)w);
@@ -49,11 +49,11 @@ inline int slots_per_block(uint32_t tile, int w) {
 // prec: 0 = float64 tables, 1 = float32 tables
 hipError_t launch_collect(const Ctx& c, int prec, const DGroup* groups, uint32_t ngroups,
                           const int32_t* slots, int nslots, hipStream_t s);
-hipError_t launch_fin_collect(const Ctx& c, int prec, const DSepFin* fins, uint32_t nfins,
+hipError_t launch_fin_collect(const Ctx& c, int prec, const DSepFin* fins, uint32_t nfins, uint32_t nbig,
                               const int32_t* slots, int nslots, hipStream_t s);
 hipError_t launch_distribute(const Ctx& c, int prec, const DWork* works, uint32_t nworks,
                              const int32_t* slots, int nslots, hipStream_t s);
-hipError_t launch_fin_distribute(const Ctx& c, int prec, const DSepFin* fins, uint32_t nfins,
+hipError_t launch_fin_distribute(const Ctx& c, int prec, const DSepFin* fins, uint32_t nfins, uint32_t nbig,
                                  const int32_t* slots, int nslots, hipStream_t s);
 hipError_t launch_marginals(const Ctx& c, const int32_t* slots, int nslots, hipStream_t s);
 hipError_t launch_gather(const Ctx& c, const int32_t* slots, int nslots, double* post_out,

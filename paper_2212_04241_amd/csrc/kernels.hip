@@ -71,11 +71,29 @@ __device__ __forceinline__ double block_sum(double v, double* scratch) {
 
 // ------------------------------------------------------------------ collect
 
+// What a collect workgroup needs about one of its runs, copied to LDS once.
+struct RunC {
+    uint64_t off;        // arena offset of the run's clique
+    uint32_t begin, count, gofs;
+    uint32_t L, Lmul, Lsh, hdig, ldig;
+    uint32_t seg, out0;  // segment length; separator entry of the run's first segment
+    uint32_t nchild, child0;
+    uint32_t seg0;       // segments of the tile before this run
+    uint32_t pad;
+};
+
+struct KidC {
+    uint32_t sep, mh, ml;
+};
+
 template <typename T, int B>
 __global__ __launch_bounds__(kBlock) void k_collect(Ctx c, const DGroup* __restrict__ groups,
                                                     const int32_t* __restrict__ slots, int nslots) {
     __shared__ __align__(16) unsigned char stage[kStageBytes];
-    __shared__ DPiece pcs[kMaxPieces];
+    __shared__ RunC runs[kMaxPieces];
+    __shared__ KidC kids[kMaxPieces][kMaxKids];
+    __shared__ DEvidence evs[kMaxPieces][B];
+    __shared__ uint32_t nseg_total;
     __shared__ double red[kWaves];
     T* vals = reinterpret_cast<T*>(stage);
     const DGroup g = groups[blockIdx.x];
@@ -85,107 +103,214 @@ __global__ __launch_bounds__(kBlock) void k_collect(Ctx c, const DGroup* __restr
         const int k = (int)blockIdx.y * B + b;
         sl[b] = k < nslots ? slots[k] : -1;
     }
-    for (uint32_t k = threadIdx.x; k < g.npiece; k += kBlock) pcs[k] = c.pc[g.piece0 + k];
+    // ---- run metadata into LDS
+    if (threadIdx.x < g.npiece) {
+        const DPiece pc = c.pc[g.piece0 + threadIdx.x];
+        const DClique q = c.cl[pc.clique];
+        RunC r;
+        r.off = q.off;
+        r.begin = pc.begin;
+        r.count = pc.count;
+        r.gofs = pc.gofs;
+        r.L = q.L;
+        r.Lmul = q.Lmul;
+        r.Lsh = q.Lsh;
+        r.hdig = q.hdig;
+        r.ldig = q.ldig;
+        r.seg = q.seg;
+        r.out0 = q.psep + pc.begin / q.seg;
+        r.nchild = q.nchild;
+        r.child0 = q.child0;
+        r.seg0 = 0;
+        r.pad = 0;
+        runs[threadIdx.x] = r;
+#pragma unroll
+        for (int b = 0; b < B; b++)
+            evs[threadIdx.x][b] = sl[b] >= 0 ? c.ev[(uint64_t)sl[b] * c.ev_stride + pc.clique] : DEvidence{0, 0};
+        for (uint32_t k = 0; k < q.nchild && k < (uint32_t)kMaxKids; k++) {
+            const DChild ch = c.ch[q.child0 + k];
+            kids[threadIdx.x][k] = KidC{ch.sep, ch.mh, ch.ml};
+        }
+    }
     __syncthreads();
+    if (threadIdx.x == 0) {
+        uint32_t s = 0;
+        for (uint32_t r = 0; r < g.npiece; r++) {
+            runs[r].seg0 = s;
+            s += runs[r].count / runs[r].seg;
+        }
+        nseg_total = s;
+    }
 
+    // ---- psi = prior x evidence x children's messages, per slot
     const T* __restrict__ prior = static_cast<const T*>(c.prior);
     const uint32_t* __restrict__ map = c.map;
-    uint32_t p = 0;
-    int cur = -1;
-    DClique q{};
-    DEvidence e[B];
+    T* psi_b[B];
+    const T* sepc_b[B];
+#pragma unroll
+    for (int b = 0; b < B; b++) {
+        const uint64_t s = sl[b] >= 0 ? (uint64_t)sl[b] : 0;
+        psi_b[b] = static_cast<T*>(c.psi) + s * c.psi_stride;
+        sepc_b[b] = static_cast<const T*>(c.sepc) + s * c.sep_stride;
+    }
+    // the current run's fields, reloaded from LDS only when the run changes
+    uint32_t p = 0, r_end = 0, r_base = 0, r_L = 1, r_Lmul = 0, r_Lsh = 0, r_hdig = 0, r_ldig = 0, nk = 0;
+    const T* r_prior = prior;
+    uint32_t kmh[kMaxKids], kml[kMaxKids], ksep[kMaxKids];
+    DEvidence ev[B];
     uint64_t anyev = 0;
+    bool first = true;
     for (uint32_t gi = threadIdx.x; gi < g.total; gi += kBlock) {
-        while (gi >= pcs[p].gofs + pcs[p].count) p++;
-        if ((int)p != cur) {
-            cur = (int)p;
-            q = c.cl[pcs[p].clique];
+        if (first || gi >= r_end) {
+            if (!first) p++;
+            while (gi >= runs[p].gofs + runs[p].count) p++;
+            first = false;
+            const RunC& r = runs[p];
+            r_end = r.gofs + r.count;
+            r_base = r.begin - r.gofs;     // entry = gi + r_base
+            r_L = r.L;
+            r_Lmul = r.Lmul;
+            r_Lsh = r.Lsh;
+            r_hdig = r.hdig;
+            r_ldig = r.ldig;
+            nk = r.nchild;
+            r_prior = prior + r.off;
+#pragma unroll
+            for (int k = 0; k < kMaxKids; k++)
+                if (k < (int)nk) {
+                    ksep[k] = kids[p][k].sep;
+                    kmh[k] = kids[p][k].mh;
+                    kml[k] = kids[p][k].ml;
+                }
             anyev = 0;
 #pragma unroll
             for (int b = 0; b < B; b++) {
-                e[b] = sl[b] >= 0 ? c.ev[(uint64_t)sl[b] * c.ev_stride + pcs[p].clique] : DEvidence{0, 0};
-                anyev |= e[b].mask;
+                ev[b] = evs[p][b];
+                anyev |= ev[b].mask;
             }
         }
-        const uint32_t i = pcs[p].begin + (gi - pcs[p].gofs);
-        const uint32_t hi = mdiv(i, q.Lmul, q.Lsh);
-        const uint32_t lo = i - hi * q.L;
-        const T pv = prior[q.off + i];
-        const uint64_t d = anyev ? (c.dig[q.hdig + hi] | c.dig[q.ldig + lo]) : 0;
+        const uint32_t i = gi + r_base;
+        const uint32_t hi = mdiv(i, r_Lmul, r_Lsh);
+        const uint32_t lo = i - hi * r_L;
+        const T pv = r_prior[i];
+        const uint64_t d = anyev ? (c.dig[r_hdig + hi] | c.dig[r_ldig + lo]) : 0;
         uint32_t jk[kMaxKids];
 #pragma unroll
         for (int k = 0; k < kMaxKids; k++)
-            if (k < (int)q.nchild) {
-                const DChild ch = c.ch[q.child0 + k];
-                jk[k] = ch.sep + map[ch.mh + hi] + map[ch.ml + lo];
-            }
+            if (k < (int)nk) jk[k] = ksep[k] + map[kmh[k] + hi] + map[kml[k] + lo];
+        const uint64_t toff = (uint64_t)(r_prior - prior) + i;
 #pragma unroll
         for (int b = 0; b < B; b++) {
             if (sl[b] < 0) continue;
-            const T* __restrict__ sepc = static_cast<const T*>(c.sepc) + (uint64_t)sl[b] * c.sep_stride;
-            T v = ((d ^ e[b].want) & e[b].mask) ? T(0) : pv;
+            T v = ((d ^ ev[b].want) & ev[b].mask) ? T(0) : pv;
 #pragma unroll
             for (int k = 0; k < kMaxKids; k++)
-                if (k < (int)q.nchild) v *= sepc[jk[k]];
-            for (uint32_t k = kMaxKids; k < q.nchild; k++) {
-                const DChild ch = c.ch[q.child0 + k];
-                v *= sepc[ch.sep + map[ch.mh + hi] + map[ch.ml + lo]];
+                if (k < (int)nk) v *= sepc_b[b][jk[k]];
+            for (uint32_t k = kMaxKids; k < nk; k++) {
+                const DChild ch = c.ch[runs[p].child0 + k];
+                v *= sepc_b[b][ch.sep + map[ch.mh + hi] + map[ch.ml + lo]];
             }
-            static_cast<T*>(c.psi)[(uint64_t)sl[b] * c.psi_stride + q.off + i] = v;
+            psi_b[b][toff] = v;
             vals[b * c.tile + gi] = v;
         }
     }
     __syncthreads();
 
-    // marginalise onto the parent separator: contiguous segments of q.seg
-    const int lane = threadIdx.x & (kWave - 1), wid = threadIdx.x / kWave;
+    // ---- marginalise onto the parent separators: every segment of the tile
+    // at once, tps lanes per segment, all slots together
+    if (g.part >= 0) {
 #pragma unroll
-    for (int b = 0; b < B; b++) {
-        if (sl[b] < 0) continue;
-        const T* v = vals + b * c.tile;
-        double* __restrict__ acc = c.acc + (uint64_t)sl[b] * c.sep_stride;
-        if (g.part >= 0) {
+        for (int b = 0; b < B; b++) {
+            if (sl[b] < 0) continue;
             double s = 0.0;
-            for (uint32_t k = threadIdx.x; k < g.total; k += kBlock) s += (double)v[k];
+            for (uint32_t k = threadIdx.x; k < g.total; k += kBlock) s += (double)vals[b * c.tile + k];
             s = block_sum(s, red);
             if (threadIdx.x == 0) c.part[(uint64_t)sl[b] * c.part_stride + (uint32_t)g.part] = s;
-            continue;
         }
-        for (uint32_t r = 0; r < g.npiece; r++) {
-            const DPiece pc = pcs[r];
-            const DClique qq = c.cl[pc.clique];
-            const uint32_t seg = qq.seg;
-            const uint32_t nseg = pc.count / seg;
-            const uint32_t out0 = qq.psep + pc.begin / seg;
-            if (seg >= 32) {
-                for (uint32_t s = (uint32_t)wid; s < nseg; s += kWaves) {
-                    double a = 0.0;
-                    for (uint32_t k = (uint32_t)lane; k < seg; k += kWave) a += (double)v[pc.gofs + s * seg + k];
-                    a = wave_sum(a);
-                    if (lane == 0) acc[out0 + s] = a;
-                }
-            } else {
-                for (uint32_t s = threadIdx.x; s < nseg; s += kBlock) {
-                    double a = 0.0;
-                    for (uint32_t k = 0; k < seg; k++) a += (double)v[pc.gofs + s * seg + k];
-                    acc[out0 + s] = a;
-                }
+        return;
+    }
+    const uint32_t ns = nseg_total;
+    uint32_t tps = 1;
+    while (tps < 64 && tps * 2 * ns <= (uint32_t)kBlock) tps *= 2;
+    const uint32_t sub = threadIdx.x & (tps - 1);
+    uint32_t q = 0;
+    for (uint32_t base = 0; base < ns * tps; base += kBlock) {
+        const uint32_t sidx = (base + threadIdx.x) / tps;
+        double a[B];
+#pragma unroll
+        for (int b = 0; b < B; b++) a[b] = 0.0;
+        uint32_t out = 0;
+        if (sidx < ns) {
+            while (q + 1 < g.npiece && sidx >= runs[q + 1].seg0) q++;
+            const uint32_t seg = runs[q].seg;
+            const uint32_t s = sidx - runs[q].seg0;
+            const uint32_t e0 = runs[q].gofs + s * seg;
+            out = runs[q].out0 + s;
+            for (uint32_t k = sub; k < seg; k += tps) {
+#pragma unroll
+                for (int b = 0; b < B; b++) a[b] += (double)vals[b * c.tile + e0 + k];
             }
+        }
+#pragma unroll
+        for (int b = 0; b < B; b++)
+            for (uint32_t o = tps / 2; o > 0; o >>= 1) a[b] += __shfl_xor(a[b], (int)o, kWave);
+        if (sidx < ns && sub == 0) {
+#pragma unroll
+            for (int b = 0; b < B; b++)
+                if (sl[b] >= 0) c.acc[(uint64_t)sl[b] * c.sep_stride + out] = a[b];
         }
     }
 }
 
-// After a collect layer, one wave per separator: finish the message (sum
-// partial sums where a segment spanned several tiles), rescale it by an
-// exact power of two so its largest entry lies in [0.5, 1), store it in
-// table precision and record the exponent.  The root's one-entry virtual
-// separator yields log P(e).
+// A separator finaliser runs as a team: a whole workgroup for a large
+// separator (the first nbig of a layer), one wave for a small one.
+struct Team {
+    uint32_t lane, size;
+    bool block;
+    double* red;
+    __device__ double sum(double v) const { return block ? block_sum(v, red) : wave_sum(v); }
+    __device__ double max(double v) const { return block ? block_max(v) : wave_max(v); }
+    __device__ double block_max(double v) const {
+        v = wave_max(v);
+        const int l = threadIdx.x & (kWave - 1), w = threadIdx.x / kWave;
+        __syncthreads();
+        if (l == 0) red[w] = v;
+        __syncthreads();
+        double s = red[0];
+        for (int k = 1; k < kWaves; k++) s = fmax(s, red[k]);
+        return s;
+    }
+    // make this team's global writes visible to the whole team
+    __device__ void sync() const {
+        if (block) __syncthreads();
+        else __threadfence_block();
+    }
+};
+
+__device__ __forceinline__ bool team_of(uint32_t nbig, uint32_t nfins, double* red, Team& t, uint32_t& fi) {
+    if (blockIdx.x < nbig) {
+        fi = blockIdx.x;
+        t = Team{threadIdx.x, (uint32_t)kBlock, true, red};
+        return true;
+    }
+    fi = nbig + (blockIdx.x - nbig) * kWaves + threadIdx.x / kWave;
+    t = Team{threadIdx.x & (kWave - 1), (uint32_t)kWave, false, red};
+    return fi < nfins;
+}
+
+// After a collect layer, per separator: finish the message (sum partial
+// sums where a segment spanned several tiles), rescale it by an exact power
+// of two so its largest entry lies in [0.5, 1), store it in table precision
+// and record the exponent.  The root's one-entry virtual separator yields
+// log P(e).
 template <typename T>
 __global__ __launch_bounds__(kBlock) void k_fin_collect(Ctx c, const DSepFin* __restrict__ fins, uint32_t nfins,
-                                                        const int32_t* __restrict__ slots) {
-    const uint32_t fi = blockIdx.x * kWaves + threadIdx.x / kWave;
-    if (fi >= nfins) return;
-    const uint32_t lane = threadIdx.x & (kWave - 1);
+                                                        uint32_t nbig, const int32_t* __restrict__ slots) {
+    __shared__ double red[kWaves];
+    Team tm;
+    uint32_t fi;
+    if (!team_of(nbig, nfins, red, tm, fi)) return;
+    const uint32_t lane = tm.lane;
     const DSepFin f = fins[fi];
     const int slot = slots[blockIdx.y];
     double* __restrict__ acc = c.acc + (uint64_t)slot * c.sep_stride;
@@ -193,7 +318,8 @@ __global__ __launch_bounds__(kBlock) void k_fin_collect(Ctx c, const DSepFin* __
     int32_t* kexp = c.kexp + (uint64_t)slot * c.kexp_stride;
 
     double mx = 0.0;
-    for (uint32_t m = lane; m < f.size; m += kWave) {
+#pragma unroll 4
+    for (uint32_t m = lane; m < f.size; m += tm.size) {
         double v;
         if (f.nchunk) {
             v = 0.0;
@@ -205,7 +331,7 @@ __global__ __launch_bounds__(kBlock) void k_fin_collect(Ctx c, const DSepFin* __
         }
         mx = fmax(mx, v);
     }
-    mx = wave_max(mx);
+    mx = tm.max(mx);
 
     if (f.edge < 0) {
         if (lane == 0) {
@@ -226,7 +352,8 @@ __global__ __launch_bounds__(kBlock) void k_fin_collect(Ctx c, const DSepFin* __
     else if (lane == 0) atomicOr(&c.flags[slot], c.fp32 ? 2 : 1);
     const double scale = ldexp(1.0, -k);
     T* __restrict__ sepc = static_cast<T*>(c.sepc) + (uint64_t)slot * c.sep_stride;
-    for (uint32_t m = lane; m < f.size; m += kWave) sepc[f.sep + m] = (T)(acc[f.sep + m] * scale);
+#pragma unroll 4
+    for (uint32_t m = lane; m < f.size; m += tm.size) sepc[f.sep + m] = (T)(acc[f.sep + m] * scale);
     if (lane == 0) kexp[f.edge] = k;
 }
 
@@ -240,12 +367,27 @@ __global__ __launch_bounds__(kBlock) void k_fin_collect(Ctx c, const DSepFin* __
 //   summed by a fixed set of lanes in a fixed order.
 //   Packed small cliques: each whole clique is staged once, and all of its
 //   targets are summed from LDS.
+// What a packed distribute workgroup needs about one of its runs (a whole
+// small clique) and about each of its targets, copied to LDS once.
+struct RunD {
+    uint64_t off;
+    uint32_t count, gofs;
+    uint32_t L, Lmul, Lsh;
+    int32_t pedge;
+    uint32_t psep, pmh, pml, pad;
+};
+
+struct TgtD {
+    DTarget t;
+    uint32_t out0, gofs, L, pad;
+};
+
 template <typename T, int B>
 __global__ __launch_bounds__(kBlock) void k_dist_gather(Ctx c, const DWork* __restrict__ works,
                                                         const int32_t* __restrict__ slots, int nslots) {
     __shared__ __align__(16) unsigned char stage[kStageBytes];
-    __shared__ DPiece pcs[kMaxPieces];
-    __shared__ DWTarget wts[kMaxPieces];
+    __shared__ RunD runs[kMaxPieces];
+    __shared__ TgtD tgts[kMaxPieces];
     T* vals = reinterpret_cast<T*>(stage);
     const DWork w = works[blockIdx.x];
     int sl[B];
@@ -263,8 +405,18 @@ __global__ __launch_bounds__(kBlock) void k_dist_gather(Ctx c, const DWork* __re
     DClique q{};
     uint32_t n;
     if (packed) {
-        for (uint32_t k = threadIdx.x; k < w.npiece; k += kBlock) pcs[k] = c.pc[w.piece0 + k];
-        for (uint32_t k = threadIdx.x; k < w.nwt; k += kBlock) wts[k] = c.wt[w.wt0 + k];
+        if (threadIdx.x < w.npiece) {
+            const DPiece pc = c.pc[w.piece0 + threadIdx.x];
+            const DClique cq = c.cl[pc.clique];
+            runs[threadIdx.x] = RunD{cq.off, pc.count, pc.gofs, cq.L, cq.Lmul, cq.Lsh, cq.pedge, cq.psep, cq.pmh,
+                                     cq.pml, 0u};
+        }
+        if (threadIdx.x >= 64 && threadIdx.x - 64 < w.nwt) {
+            const uint32_t k = threadIdx.x - 64;
+            const DWTarget wt = c.wt[w.wt0 + k];
+            const DPiece pc = c.pc[w.piece0 + wt.piece];
+            tgts[k] = TgtD{c.tg[wt.target], wt.out0, pc.gofs, c.cl[pc.clique].L, 0u};
+        }
         __syncthreads();
         n = w.total;
     } else {
@@ -272,34 +424,63 @@ __global__ __launch_bounds__(kBlock) void k_dist_gather(Ctx c, const DWork* __re
         q = c.cl[tg.clique];
         n = w.ng * w.nk * q.L;
     }
-    uint32_t p = 0;
-    int cur = -1;
+    const T* psi_b[B];
+    const T* sepd_b[B];
+#pragma unroll
+    for (int b = 0; b < B; b++) {
+        const uint64_t s = sl[b] >= 0 ? (uint64_t)sl[b] : 0;
+        psi_b[b] = static_cast<const T*>(c.psi) + s * c.psi_stride;
+        sepd_b[b] = static_cast<const T*>(c.sepd) + s * c.sep_stride;
+    }
+    // packed: the current run's fields, reloaded only when the run changes
+    uint32_t p = 0, r_end = 0, r_gofs = 0, r_L = 1, r_Lmul = 0, r_Lsh = 0, r_psep = 0, r_pmh = 0, r_pml = 0;
+    uint64_t r_off = 0;
+    int32_t r_pedge = -1;
+    bool first = true;
     for (uint32_t gi = threadIdx.x; gi < n; gi += kBlock) {
-        uint64_t ent;   // entry index within the clique
-        uint32_t row, l;
+        uint64_t off;
+        uint32_t row, l, ent;
+        int32_t pedge;
+        uint32_t pr = 0;
         if (packed) {
-            while (gi >= pcs[p].gofs + pcs[p].count) p++;
-            if ((int)p != cur) {
-                cur = (int)p;
-                q = c.cl[pcs[p].clique];
+            if (first || gi >= r_end) {
+                if (!first) p++;
+                while (gi >= runs[p].gofs + runs[p].count) p++;
+                first = false;
+                const RunD& r = runs[p];
+                r_end = r.gofs + r.count;
+                r_gofs = r.gofs;
+                r_L = r.L;
+                r_Lmul = r.Lmul;
+                r_Lsh = r.Lsh;
+                r_off = r.off;
+                r_pedge = r.pedge;
+                r_psep = r.psep;
+                r_pmh = r.pmh;
+                r_pml = r.pml;
             }
-            ent = gi - pcs[p].gofs;
-            row = mdiv((uint32_t)ent, q.Lmul, q.Lsh);
-            l = (uint32_t)ent - row * q.L;
+            ent = gi - r_gofs;
+            row = mdiv(ent, r_Lmul, r_Lsh);
+            l = ent - row * r_L;
+            off = r_off;
+            pedge = r_pedge;
+            if (pedge >= 0) pr = r_psep + map[r_pmh + row] + map[r_pml + l];
         } else {
             const uint32_t ri = mdiv(gi, q.Lmul, q.Lsh);
             l = gi - ri * q.L;
             const uint32_t gg = mdiv(ri, w.nkmul, w.nksh);
             const uint32_t k = ri - gg * w.nk;
             row = map[tg.rg + w.g0 + gg] + map[tg.rq + w.k0 + k];
-            ent = (uint64_t)row * q.L + l;
+            ent = row * q.L + l;
+            off = q.off;
+            pedge = q.pedge;
+            if (pedge >= 0) pr = q.psep + map[q.pmh + row] + map[q.pml + l];
         }
-        const uint32_t pr = q.pedge >= 0 ? q.psep + map[q.pmh + row] + map[q.pml + l] : 0u;
 #pragma unroll
         for (int b = 0; b < B; b++) {
             if (sl[b] < 0) continue;
-            T v = static_cast<const T*>(c.psi)[(uint64_t)sl[b] * c.psi_stride + q.off + ent];
-            if (q.pedge >= 0) v *= static_cast<const T*>(c.sepd)[(uint64_t)sl[b] * c.sep_stride + pr];
+            T v = psi_b[b][off + ent];
+            if (pedge >= 0) v *= sepd_b[b][pr];
             vals[b * c.tile + gi] = v;
         }
     }
@@ -323,13 +504,11 @@ __global__ __launch_bounds__(kBlock) void k_dist_gather(Ctx c, const DWork* __re
             DTarget t2 = tg;
             uint32_t L = q.L, g, t, nk, rowbase;
             if (packed) {
-                while (a + 1 < w.nwt && o >= wts[a + 1].out0) a++;
-                const DWTarget wt = wts[a];
-                t2 = c.tg[wt.target];
-                const DPiece pc = pcs[wt.piece];
-                L = c.cl[pc.clique].L;
-                gofs = pc.gofs;
-                const uint32_t oo = o - wt.out0;
+                while (a + 1 < w.nwt && o >= tgts[a + 1].out0) a++;
+                t2 = tgts[a].t;
+                L = tgts[a].L;
+                gofs = tgts[a].gofs;
+                const uint32_t oo = o - tgts[a].out0;
                 g = oo / t2.nPL;
                 t = oo - g * t2.nPL;
                 nk = t2.NQ;
@@ -370,32 +549,33 @@ __global__ __launch_bounds__(kBlock) void k_dist_gather(Ctx c, const DWork* __re
     }
 }
 
-// After a distribute layer, one wave per separator (real or one-variable
-// virtual): finish the new separator table S* (summing partials), read the
-// posterior marginals of the variables assigned to it, and for a real
-// separator form the new/old ratio S*/S (0/0 = 0) rescaled by an exact
-// power of two.
+// After a distribute layer, per separator (real or one-variable virtual):
+// finish the new separator table S* (summing partials), read the posterior
+// marginals of the variables assigned to it, and for a real separator form
+// the new/old ratio S*/S (0/0 = 0) rescaled by an exact power of two.
 template <typename T>
 __global__ __launch_bounds__(kBlock) void k_fin_distribute(Ctx c, const DSepFin* __restrict__ fins, uint32_t nfins,
-                                                           const int32_t* __restrict__ slots) {
-    const uint32_t fi = blockIdx.x * kWaves + threadIdx.x / kWave;
-    if (fi >= nfins) return;
-    const uint32_t lane = threadIdx.x & (kWave - 1);
+                                                           uint32_t nbig, const int32_t* __restrict__ slots) {
+    __shared__ double red[kWaves];
+    Team tm;
+    uint32_t fi;
+    if (!team_of(nbig, nfins, red, tm, fi)) return;
+    const uint32_t lane = tm.lane;
     const DSepFin f = fins[fi];
     const int slot = slots[blockIdx.y];
     double* __restrict__ acc = c.acc + (uint64_t)slot * c.sep_stride;
     const double* __restrict__ part = c.part + (uint64_t)slot * c.part_stride;
     if (f.nchunk) {
-        for (uint32_t m = lane; m < f.size; m += kWave) {
+    #pragma unroll 4
+    for (uint32_t m = lane; m < f.size; m += tm.size) {
             double v = 0.0;
             const double* pp = part + f.part0 + (uint64_t)m * f.nchunk;
             for (uint32_t k = 0; k < f.nchunk; k++) v += pp[k];
             acc[f.sep + m] = v;
         }
-        // other lanes of this wave read these sums below
-        __threadfence_block();
+        tm.sync();  // other lanes of the team read these sums below
     }
-    // posteriors: each state of each assigned variable is a wave-wide sum
+    // posteriors: each state of each assigned variable is a team-wide sum
     // over the separator entries carrying that state
     double* __restrict__ marg = c.marg + (uint64_t)slot * c.marg_stride;
     for (uint32_t a = 0; a < f.nmv; a++) {
@@ -403,11 +583,12 @@ __global__ __launch_bounds__(kBlock) void k_fin_distribute(Ctx c, const DSepFin*
         const uint32_t per = f.size / mv.card;
         for (uint32_t x = 0; x < mv.card; x++) {
             double s = 0.0;
-            for (uint32_t e = lane; e < per; e += kWave) {
-                const uint32_t o = e / mv.stride;
+#pragma unroll 4
+            for (uint32_t e = lane; e < per; e += tm.size) {
+                const uint32_t o = mdiv(e, mv.smul, mv.ssh);
                 s += acc[f.sep + (o * mv.card + x) * mv.stride + (e - o * mv.stride)];
             }
-            s = wave_sum(s);
+            s = tm.sum(s);
             if (lane == 0) marg[mv.out + x] = s;
         }
     }
@@ -415,15 +596,17 @@ __global__ __launch_bounds__(kBlock) void k_fin_distribute(Ctx c, const DSepFin*
     const T* __restrict__ sepc = static_cast<const T*>(c.sepc) + (uint64_t)slot * c.sep_stride;
     T* __restrict__ sepd = static_cast<T*>(c.sepd) + (uint64_t)slot * c.sep_stride;
     double mx = 0.0;
-    for (uint32_t m = lane; m < f.size; m += kWave) {
+#pragma unroll 4
+    for (uint32_t m = lane; m < f.size; m += tm.size) {
         const double den = (double)sepc[f.sep + m];
         mx = fmax(mx, den == 0.0 ? 0.0 : acc[f.sep + m] / den);
     }
-    mx = wave_max(mx);
+    mx = tm.max(mx);
     int k = 0;
     if (mx > 0.0) frexp(mx, &k);
     const double scale = ldexp(1.0, -k);
-    for (uint32_t m = lane; m < f.size; m += kWave) {
+#pragma unroll 4
+    for (uint32_t m = lane; m < f.size; m += tm.size) {
         const double den = (double)sepc[f.sep + m];
         sepd[f.sep + m] = (T)((den == 0.0 ? 0.0 : acc[f.sep + m] / den) * scale);
     }
@@ -519,12 +702,12 @@ hipError_t launch_collect(const Ctx& c, int prec, const DGroup* groups, uint32_t
     return hipGetLastError();
 }
 
-hipError_t launch_fin_collect(const Ctx& c, int prec, const DSepFin* fins, uint32_t nfins, const int32_t* slots,
-                              int nslots, hipStream_t s) {
+hipError_t launch_fin_collect(const Ctx& c, int prec, const DSepFin* fins, uint32_t nfins, uint32_t nbig,
+                              const int32_t* slots, int nslots, hipStream_t s) {
     if (!nfins || !nslots) return hipSuccess;
-    dim3 grid((nfins + kWaves - 1) / kWaves, (unsigned)nslots);
-    if (prec) hipLaunchKernelGGL(k_fin_collect<float>, grid, dim3(kBlock), 0, s, c, fins, nfins, slots);
-    else hipLaunchKernelGGL(k_fin_collect<double>, grid, dim3(kBlock), 0, s, c, fins, nfins, slots);
+    dim3 grid(nbig + (nfins - nbig + kWaves - 1) / kWaves, (unsigned)nslots);
+    if (prec) hipLaunchKernelGGL(k_fin_collect<float>, grid, dim3(kBlock), 0, s, c, fins, nfins, nbig, slots);
+    else hipLaunchKernelGGL(k_fin_collect<double>, grid, dim3(kBlock), 0, s, c, fins, nfins, nbig, slots);
     return hipGetLastError();
 }
 
@@ -536,12 +719,12 @@ hipError_t launch_distribute(const Ctx& c, int prec, const DWork* works, uint32_
     return hipGetLastError();
 }
 
-hipError_t launch_fin_distribute(const Ctx& c, int prec, const DSepFin* fins, uint32_t nfins, const int32_t* slots,
-                                 int nslots, hipStream_t s) {
+hipError_t launch_fin_distribute(const Ctx& c, int prec, const DSepFin* fins, uint32_t nfins, uint32_t nbig,
+                                 const int32_t* slots, int nslots, hipStream_t s) {
     if (!nfins || !nslots) return hipSuccess;
-    dim3 grid((nfins + kWaves - 1) / kWaves, (unsigned)nslots);
-    if (prec) hipLaunchKernelGGL(k_fin_distribute<float>, grid, dim3(kBlock), 0, s, c, fins, nfins, slots);
-    else hipLaunchKernelGGL(k_fin_distribute<double>, grid, dim3(kBlock), 0, s, c, fins, nfins, slots);
+    dim3 grid(nbig + (nfins - nbig + kWaves - 1) / kWaves, (unsigned)nslots);
+    if (prec) hipLaunchKernelGGL(k_fin_distribute<float>, grid, dim3(kBlock), 0, s, c, fins, nfins, nbig, slots);
+    else hipLaunchKernelGGL(k_fin_distribute<double>, grid, dim3(kBlock), 0, s, c, fins, nfins, nbig, slots);
     return hipGetLastError();
 }
 

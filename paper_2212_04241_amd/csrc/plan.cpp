@@ -70,6 +70,7 @@ struct Packer {
         g.total += count;
     }
     void add_part(uint32_t clique, uint32_t begin, uint32_t count, int32_t part) {
+        open = -1;  // runs of one group must stay contiguous in the run list
         DGroup g{};
         g.piece0 = (uint32_t)p.pieces.size();
         g.npiece = 1;
@@ -234,10 +235,12 @@ std::string check_plan(const Tree& t, const Plan& p) {
             const DMargVar& m = p.margvars[F.mv0 + k];
             if ((uint64_t)m.out + m.card > p.marg_total || m.card == 0 || m.stride == 0) return "posterior var range";
             if ((uint64_t)m.stride * m.card > F.size || F.size % ((uint64_t)m.stride * m.card)) return "posterior var stride";
+            for (uint32_t x : {0u, m.stride - 1, m.stride, F.size / m.card - 1})
+                if (mdiv_host(x, m.smul, m.ssh) != x / m.stride) return "posterior var magic";
         }
     }
     if ((uint64_t)p.sep_stride < (uint64_t)p.sep_real) return "separator stride";
-    if (p.stage == 0 || p.stage > (uint32_t)kTileMax) return "stage size";
+    if (p.stage == 0 || p.stage > (uint32_t)kTileMax || p.stage > p.max_stage) return "stage size";
     for (const DGroup& g : p.groups)
         if (g.total > p.stage) return "group exceeds stage";
     for (const DWork& w : p.works) {
@@ -247,10 +250,12 @@ std::string check_plan(const Tree& t, const Plan& p) {
     return "";
 }
 
-void build_plan(const Tree& t, int tile, Plan& p) {
+void build_plan(const Tree& t, int tile, uint32_t max_stage, Plan& p) {
     p = Plan();
+    max_stage = std::min<uint32_t>(std::max<uint32_t>(max_stage, 64), (uint32_t)kTileMax);
+    p.max_stage = max_stage;
     if (tile <= 0) tile = 2048;
-    tile = std::min(tile, kTileMax);
+    tile = std::min(tile, (int)max_stage);
     p.tile = tile;
     const int nc = t.nc;
 
@@ -313,11 +318,12 @@ void build_plan(const Tree& t, int tile, Plan& p) {
         // split point: smallest suffix product >= 64, or the whole clique
         int q = m;
         uint64_t L = 1;
-        while (q > 0 && L < 64) {
+        // (at most max_stage entries, so that one row fits the LDS stage)
+        while (q > 0 && L < 64 && L * (uint64_t)card_at[(size_t)q - 1] <= max_stage) {
             q--;
             L *= (uint64_t)card_at[(size_t)q];
         }
-        if (L > (uint64_t)kTileMax) throw std::runtime_error("a variable's cardinality is too large for the tile");
+        if (L > (uint64_t)max_stage) throw std::runtime_error("a variable's cardinality is too large for the tile");
         splitq[(size_t)c] = q;
         const uint64_t rows = size / L;
         d.L = (uint32_t)L;
@@ -456,8 +462,11 @@ void build_plan(const Tree& t, int tile, Plan& p) {
             fins.push_back(f);
         }
         ly.ngroup = (uint32_t)p.groups.size() - ly.group0;
+        // large separators first: each gets a workgroup, the rest a wave
+        std::stable_partition(fins.begin(), fins.end(), [](const DSepFin& f) { return f.size > kBigSeparator; });
         ly.fin0 = (uint32_t)p.fins.size();
         ly.nfin = (uint32_t)fins.size();
+        ly.nbig = (uint32_t)std::count_if(fins.begin(), fins.end(), [](const DSepFin& f) { return f.size > kBigSeparator; });
         p.fins.insert(p.fins.end(), fins.begin(), fins.end());
     }
 
@@ -503,8 +512,8 @@ void build_plan(const Tree& t, int tile, Plan& p) {
             }
             for (int v : lay)
                 if (p.post_sep[(size_t)v] < 0) tgts.push_back({{v}, vsep_off[(size_t)v], -2});
-            const uint32_t dtile_c = std::min<uint32_t>((uint32_t)kTileMax, std::max(dtile_base, d.L));
-            const bool packed = d.size <= dtile_c;
+            const uint32_t dtile_c = std::min<uint32_t>(max_stage, std::max(dtile_base, d.L));
+            const bool packed = d.size <= dtile_c && tgts.size() <= (size_t)kMaxPieces;
             if (packed) {
                 if (open_w >= 0) {
                     const DWork& W = p.works[(size_t)open_w];
@@ -620,20 +629,33 @@ void build_plan(const Tree& t, int tile, Plan& p) {
                     }
                     for (size_t a = 0; a < tg0.vars.size(); a++) {
                         const int v = tg0.vars[a];
-                        if (p.post_sep[(size_t)v] == tg0.edge)
-                            p.margvars.push_back({marg_off[(size_t)v], (uint32_t)vs[a], (uint32_t)t.card[(size_t)v], 0});
+                        if (p.post_sep[(size_t)v] != tg0.edge) continue;
+                        DMargVar mv{};
+                        mv.out = marg_off[(size_t)v];
+                        mv.stride = (uint32_t)vs[a];
+                        mv.card = (uint32_t)t.card[(size_t)v];
+                        magic_u32(mv.stride, mv.smul, mv.ssh);
+                        p.margvars.push_back(mv);
                     }
                 } else {
                     const int v = tg0.vars[0];
-                    p.margvars.push_back({marg_off[(size_t)v], 1u, (uint32_t)t.card[(size_t)v], 0});
+                    DMargVar mv{};
+                    mv.out = marg_off[(size_t)v];
+                    mv.stride = 1u;
+                    mv.card = (uint32_t)t.card[(size_t)v];
+                    magic_u32(1u, mv.smul, mv.ssh);
+                    p.margvars.push_back(mv);
                 }
                 f.nmv = (uint32_t)p.margvars.size() - f.mv0;
                 fins.push_back(f);
             }
         }
         ly.ngroup = (uint32_t)p.works.size() - ly.group0;
+        // large separators first: each gets a workgroup, the rest a wave
+        std::stable_partition(fins.begin(), fins.end(), [](const DSepFin& f) { return f.size > kBigSeparator; });
         ly.fin0 = (uint32_t)p.fins.size();
         ly.nfin = (uint32_t)fins.size();
+        ly.nbig = (uint32_t)std::count_if(fins.begin(), fins.end(), [](const DSepFin& f) { return f.size > kBigSeparator; });
         p.fins.insert(p.fins.end(), fins.begin(), fins.end());
     }
     p.n_parts = parts;

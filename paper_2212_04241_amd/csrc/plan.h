@@ -9,11 +9,15 @@ namespace fbn {
 struct Layer {
     uint32_t group0 = 0, ngroup = 0;  // collect: into Plan::groups; distribute: into Plan::works
     uint32_t fin0 = 0, nfin = 0;      // into Plan::fins (separators finalised after it)
+    uint32_t nbig = 0;                // the first nbig fins get a workgroup each, the rest a wave
 };
+
+constexpr uint32_t kBigSeparator = 1024;  // entries above which a separator gets a workgroup
 
 struct Plan {
     int tile = 2048;
     uint32_t stage = 0;               // LDS entries per slot: largest collect tile or distribute block
+    uint32_t max_stage = 0;           // bound on stage
     uint64_t T = 0;                   // prior / working-table entries
     uint32_t sep_total = 0;           // separator entries over all edges
     uint32_t sep_stride = 0;          // per slot: sep_total + 1 (root's virtual entry) rounded
@@ -44,7 +48,9 @@ struct Plan {
     std::vector<uint32_t> dig_shift0; // start of each clique's entries in dig_shift
 };
 
-void build_plan(const Tree& t, int tile, Plan& p);
+// max_stage: entries one workgroup can stage in LDS for one slot (bounds
+// every tile, every distribute block and the row length L).
+void build_plan(const Tree& t, int tile, uint32_t max_stage, Plan& p);
 
 // Checks, on the host, every bound the kernels rely on: tile and run sizes,
 // run alignment to separator segments, table offsets and every value of the

@@ -154,3 +154,12 @@ def test_plan_bounds_check_passes_for_any_tile(key, tile):
 def test_plan_bounds_check_random(seed, n, tile):
     net = fbngen.random_small_net(seed, n, max_card=6, p_max=3, window=5)
     _host_jt(net, tile_entries=tile, max_clique_entries=1 << 24)
+
+
+@pytest.mark.parametrize("precision", [0, 1])
+@pytest.mark.parametrize("key,j", [("C3", 0), ("C5", 7), ("C5", 0)])
+def test_plan_bounds_check_large_workloads(key, j, precision):
+    # mixes full-segment and partial-sum runs in one layer, and rows near the
+    # LDS stage limit; the build runs the plan checker
+    net = fbngen.make_net(key, j)
+    _host_jt(net, precision=precision)
