@@ -66,10 +66,15 @@ def time_batched(fbn, net, cases, precision, steps, warmup, profile):
     return jt, dt, prof, post, lp, st
 
 
-def time_plain(fbn, net, cases, n_queries):
-    """One query per calibration, waiting for each result (a per-query engine)."""
+def time_plain(fbn, net, cases, n_queries, graph=True):
+    """One query per calibration, waiting for each result (a per-query
+    engine); the layer sequence is replayed as one captured graph."""
+    import torch
     m = min(n_queries, len(cases))
-    jt = fbn.JT(fbn.net_from_spec(net), precision=fbn.FBN_FP64, max_slots=m)
+    stream = torch.cuda.Stream()
+    jt = fbn.JT(fbn.net_from_spec(net), precision=fbn.FBN_FP64, max_slots=m, stream=stream.cuda_stream)
+    if graph:
+        fbn.set_graph_mode(jt, True)
     slots = list(range(m))
     fbn.set_evidence_batch(jt, slots, cases[:m])
     marg = int(np.sum(net.card))
@@ -196,7 +201,10 @@ def main():
     # FP64 plain, one query per calibration
     jtp, qps_plain, lat, postp, lpp, stp = time_plain(fbn, net, cases, args.plain_queries)
     jtp.free()
-    log(f"[bench] fp64 plain: {qps_plain:.1f} q/s, p50 {1e3 * np.median(lat):.3f} ms")
+    log(f"[bench] fp64 plain (graph replay): {qps_plain:.1f} q/s, p50 {1e3 * np.median(lat):.3f} ms")
+    jte, qps_plain_eager, lat_e, _, _, _ = time_plain(fbn, net, cases, args.plain_queries, graph=False)
+    jte.free()
+    log(f"[bench] fp64 plain (eager launches): {qps_plain_eager:.1f} q/s")
     qps_io = time_with_host_io(fbn, net, cases, fbn.FBN_FP32_RESCALED, max(1, args.steps // 4))
     log(f"[bench] fp32 batched with host i/o: {qps_io:.1f} q/s")
 
@@ -236,7 +244,9 @@ def main():
             "fp64_plain_per_query": {"queries_per_s": round(qps_plain, 1),
                                      "p50_ms": round(1e3 * float(np.median(lat)), 4),
                                      "p99_ms": round(1e3 * float(np.percentile(lat, 99)), 4),
-                                     "queries": int(len(lat))},
+                                     "queries": int(len(lat)), "launch": "hipGraph replay",
+                                     "eager_queries_per_s": round(qps_plain_eager, 1),
+                                     "eager_p50_ms": round(1e3 * float(np.median(lat_e)), 4)},
             "fp32_batched_with_host_io": {"queries_per_s": round(qps_io, 1)},
             "fp32_vs_fp64_plain": round(qps32 / qps_plain, 2),
         },

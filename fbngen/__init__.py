@@ -223,7 +223,7 @@ CONFIGS = {
     "C3": Config("C3", 3, 1, 500, 0.2, 20_000_000, 5_000_000,
                  "110 variables, hub of 63 states parenting 60 others (+<=2 extra parents), "
                  "cards in {2..63}, Dirichlet(0.2); 500 cases observing 10 variables"),
-    "C4": Config("C4", 4, 256, 64, 1.0, 4_000_000, None,
+    "C4": Config("C4", 4, 256, 64, 1.0, 32_768, None,
                  "256 networks of U[50,500] variables, cards {2..6}, <=3 parents from the previous 30, "
                  "Dirichlet(1); 64 cases each observing 4% of the variables"),
     "C5": Config("C5", 5, 8, 4096, 1.0, 4_000_000, None,

@@ -114,8 +114,14 @@ void fbn_free_net(fbn_net* net);
  * potentials, device upload.  opt may be NULL (defaults). */
 fbn_status fbn_build_jt(const fbn_net* net, const fbn_jt_options* opt, fbn_jt** out);
 void fbn_free_jt(fbn_jt* jt);  /* synchronises its stream first */
-/* Replace the stream used by later calls. */
+/* Replace the stream used by later calls (drops captured graphs). */
 fbn_status fbn_set_stream(fbn_jt* jt, void* stream);
+/* Graph mode (Section 2's one task per layer, with the whole sequence of
+ * layer launches of one calibration captured once as a HIP graph per batch
+ * size and replayed): on = 1 enables it, 0 returns to eager launches.
+ * Needs a non-NULL stream (FBN_E_STATE otherwise).  Results are bitwise
+ * identical to eager launches.  Kernel timing (below) disables replay. */
+fbn_status fbn_set_graph_mode(fbn_jt* jt, int32_t on);
 
 /* --- evidence: the reduction operation (Section 2) -------------------------
  * Hard evidence for one slot: distinct variables, 0 <= state < card.  n_obs = 0

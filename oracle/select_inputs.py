@@ -88,6 +88,11 @@ def select_repair(key, j, cap, rejection_attempts):
     return _record(jt, {"attempt": 0, "card_mode": "uniform", "drop": drop, "path": "repair"})
 
 
+def _repair_job(args):
+    key, j, cap = args
+    return j, select_repair(key, j, cap, 3)
+
+
 def main(keys):
     data = {}
     if os.path.exists(OUT):
@@ -97,6 +102,17 @@ def main(keys):
         cfg = fbngen.CONFIGS[key]
         t0 = time.time()
         res = {}
+        if key == "C4":
+            # many independent networks: one process per core
+            from multiprocessing import Pool
+            with Pool(max(1, min(7, (os.cpu_count() or 2) - 1))) as pool:
+                for j, r in pool.imap_unordered(_repair_job, [(key, j, cfg.cap) for j in range(cfg.n_nets)]):
+                    res[str(j)] = r
+                    print(key, j, {k: v for k, v in r.items() if k != "drop"}, f"{time.time() - t0:.1f}s", flush=True)
+            data[key] = {k: res[k] for k in sorted(res, key=int)}
+            with open(OUT, "w") as f:
+                json.dump(data, f, indent=1, sort_keys=True)
+            continue
         for j in range(cfg.n_nets):
             if key == "C1":
                 res[str(j)] = select_range(key, j, None, 4096, ["uniform"], 1000)

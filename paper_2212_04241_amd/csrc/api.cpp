@@ -10,6 +10,7 @@
 #include <cstdlib>
 #include <cstring>
 #include <fstream>
+#include <map>
 #include <new>
 #include <sstream>
 #include <string>
@@ -224,6 +225,9 @@ struct fbn_jt {
     std::vector<std::vector<std::pair<int, int>>> occ;
     Ctx ctx{};
     uint64_t device_bytes = 0, slot_bytes = 0;
+    // graph mode: one captured launch sequence per batch size
+    bool use_graph = false;
+    std::map<int, hipGraphExec_t> graphs;
     // kernel timing
     struct Rec {
         hipEvent_t a, b;
@@ -268,6 +272,8 @@ void release(fbn_jt* jt) {
             }
         }
         if (jt->staged) hipEventDestroy(jt->staged);
+        for (auto& kv : jt->graphs) hipGraphExecDestroy(kv.second);
+        jt->graphs.clear();
         for (auto& r : jt->recs) {
             hipEventDestroy(r.a);
             hipEventDestroy(r.b);
@@ -486,6 +492,8 @@ fbn_status fetch(fbn_jt* jt, int32_t n, double* post, double* logpe, int32_t* fl
 
 }  // namespace
 
+static fbn_status enqueue_calibration(fbn_jt* jt, int32_t n);
+
 // ====================================================================== ABI
 
 extern "C" {
@@ -685,8 +693,11 @@ fbn_status fbn_set_stream(fbn_jt* jt, void* stream) {
     fbn_status st = wait_staged(jt);
     if (st) return st;
     HIP_OK(hipStreamSynchronize(jt->stream));
+    for (auto& kv : jt->graphs) hipGraphExecDestroy(kv.second);
+    jt->graphs.clear();
     jt->stream = static_cast<hipStream_t>(stream);
     jt->opt.stream = stream;
+    if (!jt->stream) jt->use_graph = false;
     return FBN_OK;
 }
 
@@ -743,6 +754,49 @@ fbn_status fbn_calibrate(fbn_jt* jt, int32_t n, const int32_t* slots, double* lo
     if (n == 0) return FBN_OK;
     HIP_OK(hipSetDevice(jt->device));
     if ((st = stage_slots(jt, n, slots))) return st;
+    if (jt->use_graph && !jt->prof) {
+        // one graph launch replays the whole layer sequence for n slots
+        auto it = jt->graphs.find(n);
+        if (it == jt->graphs.end()) {
+            hipGraph_t g = nullptr;
+            hipGraphExec_t ge = nullptr;
+            HIP_OK(hipStreamBeginCapture(jt->stream, hipStreamCaptureModeThreadLocal));
+            st = enqueue_calibration(jt, n);
+            hipError_t ec = hipStreamEndCapture(jt->stream, &g);
+            if (st) {
+                if (g) hipGraphDestroy(g);
+                return st;
+            }
+            if (ec != hipSuccess) return fail(FBN_E_DEVICE, std::string("graph capture: ") + hipGetErrorString(ec));
+            ec = hipGraphInstantiate(&ge, g, nullptr, nullptr, 0);
+            hipGraphDestroy(g);
+            if (ec != hipSuccess) return fail(FBN_E_DEVICE, std::string("graph instantiate: ") + hipGetErrorString(ec));
+            it = jt->graphs.emplace(n, ge).first;
+        }
+        HIP_OK(hipGraphLaunch(it->second, jt->stream));
+    } else if ((st = enqueue_calibration(jt, n))) {
+        return st;
+    }
+    if (log_pe || per_slot) {
+        std::vector<double> lp((size_t)n);
+        std::vector<int32_t> fl((size_t)n);
+        if ((st = fetch(jt, n, nullptr, lp.data(), fl.data()))) return st;
+        HIP_OK(hipStreamSynchronize(jt->stream));
+        for (int32_t i = 0; i < n; i++) {
+            if (log_pe) log_pe[i] = lp[(size_t)i];
+            if (per_slot) per_slot[i] = status_of_flag(fl[(size_t)i]);
+        }
+    }
+    return FBN_OK;
+}
+
+}  // extern "C"
+
+// The launch sequence of one calibration of the n slots staged in d_slots:
+// collect layers leaves to root, then distribute layers root to leaves, then
+// the posteriors.
+static fbn_status enqueue_calibration(fbn_jt* jt, int32_t n) {
+    fbn_status st = FBN_OK;
     const Ctx& c = jt->ctx;
     const Plan& p = jt->plan;
     const int prec = jt->opt.precision == FBN_FP32_RESCALED ? 1 : 0;
@@ -776,16 +830,16 @@ fbn_status fbn_calibrate(fbn_jt* jt, int32_t n, const int32_t* slots, double* lo
     }
     if ((st = timed(jt, 4, 16.0 * nb * (double)c.marg_stride, [&] { return launch_marginals(c, jt->d_slots, n, s); })))
         return st;
-    if (log_pe || per_slot) {
-        std::vector<double> lp((size_t)n);
-        std::vector<int32_t> fl((size_t)n);
-        if ((st = fetch(jt, n, nullptr, lp.data(), fl.data()))) return st;
-        HIP_OK(hipStreamSynchronize(s));
-        for (int32_t i = 0; i < n; i++) {
-            if (log_pe) log_pe[i] = lp[(size_t)i];
-            if (per_slot) per_slot[i] = status_of_flag(fl[(size_t)i]);
-        }
-    }
+    return FBN_OK;
+}
+
+extern "C" {
+
+fbn_status fbn_set_graph_mode(fbn_jt* jt, int32_t on) {
+    if (!jt) return fail(FBN_E_INVALID_ARG, "null jt");
+    if (jt->opt.host_only) return fail(FBN_E_STATE, "host-only jt");
+    if (on && !jt->stream) return fail(FBN_E_STATE, "graph mode needs a stream");
+    jt->use_graph = on != 0;
     return FBN_OK;
 }
 

@@ -80,6 +80,7 @@ def lib():
         "fbn_build_jt": (C.c_int32, [C.c_void_p, P(fbn_jt_options), vpp]),
         "fbn_free_jt": (None, [C.c_void_p]),
         "fbn_set_stream": (C.c_int32, [C.c_void_p, C.c_void_p]),
+        "fbn_set_graph_mode": (C.c_int32, [C.c_void_p, C.c_int32]),
         "fbn_set_evidence": (C.c_int32, [C.c_void_p, C.c_int32, C.c_int32, i32p, i32p]),
         "fbn_set_evidence_batch": (C.c_int32, [C.c_void_p, C.c_int32, i32p, i32p, i32p, i32p]),
         "fbn_calibrate": (C.c_int32, [C.c_void_p, C.c_int32, i32p, f64p, i32p]),
@@ -218,6 +219,11 @@ def build_jt(net: Net, **kw) -> JT:
 
 def set_stream(jt: JT, stream) -> None:
     _check(lib().fbn_set_stream(jt._h, C.c_void_p(stream) if stream else None), "fbn_set_stream")
+
+
+def set_graph_mode(jt: JT, on: bool = True) -> None:
+    """Replay each calibration as one captured HIP graph (needs a stream)."""
+    _check(lib().fbn_set_graph_mode(jt._h, 1 if on else 0), "fbn_set_graph_mode")
 
 
 def set_evidence(jt: JT, slot: int, vars_, states) -> None:

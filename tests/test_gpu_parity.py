@@ -267,6 +267,42 @@ def test_query_marginals_subset_and_errors():
         fbn.calibrate(jt, [2])
 
 
+@pytest.mark.parametrize("prec", [fbn.FBN_FP64, fbn.FBN_FP32_RESCALED])
+def test_graph_replay_equals_eager(prec):
+    # the captured layer sequence, replayed several times with new evidence,
+    # eager work and synchronisation in between, gives bitwise the eager result
+    import torch
+    net = fbngen.make_net("C2", 0)
+    cases = fbngen.make_cases("C2", net)[:24]
+    say("graph replay", prec)
+    marg = int(np.sum(net.card))
+    eager = fbn.JT(fbn.net_from_spec(net), precision=prec, max_slots=8)
+    s = torch.cuda.Stream()
+    graph = fbn.JT(fbn.net_from_spec(net), precision=prec, max_slots=8, stream=s.cuda_stream)
+    fbn.set_graph_mode(graph, True)
+    slots = list(range(8))
+    for rep in range(3):
+        batch = cases[8 * rep: 8 * rep + 8]
+        fbn.set_evidence_batch(eager, slots, batch)
+        fbn.set_evidence_batch(graph, slots, batch)
+        fbn.calibrate(eager, slots)
+        pe, le, se = fbn.query_all(eager, slots, marg)
+        fbn.calibrate(graph, slots)
+        pg, lg, sg = fbn.query_all(graph, slots, marg)
+        torch.cuda.synchronize()
+        assert np.array_equal(pe, pg) and np.array_equal(le, lg) and np.array_equal(se, sg), rep
+        # a different batch size captures its own graph
+        fbn.set_evidence(graph, 0, *cases[rep])
+        fbn.set_evidence(eager, 0, *cases[rep])
+        lg1, _ = fbn.calibrate(graph, [0], want_results=True)
+        le1, _ = fbn.calibrate(eager, [0], want_results=True)
+        assert np.array_equal(lg1, le1)
+    ref, _ = oracle_run(net, cases[16:24])
+    (check_fp64 if prec == fbn.FBN_FP64 else check_fp32)(pg, lg, sg, ref, "graph")
+    del graph
+    torch.cuda.synchronize()
+
+
 def test_torch_stream_and_allocator():
     import torch
     net = fbngen.make_net("C1", 0)
