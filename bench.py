@@ -8,7 +8,11 @@ A step is one calibration (collect + distribute + posteriors, every layer
 kernel) of every evidence case of the workload, with the network and the
 evidence already resident in device memory; posteriors stay on the device.
 
-Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload C2]
+With --workload C4 the 256 networks form one forest junction tree and a
+step calibrates 64 slots, each holding one case of every network (16384
+queries).
+
+Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload C2|C4]
 """
 from __future__ import annotations
 
@@ -31,12 +35,49 @@ def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
-def workload_config(key, net, jt_stats, n_cases):
+class Workload:
+    """The networks and evidence of one preset.  A slot is one evidence case
+    of the junction tree; with several networks (C4) the tree is a forest of
+    all of them and one slot carries one case of every network, so a slot
+    answers len(nets) queries."""
+
+    def __init__(self, key):
+        import fbngen
+        self.key = key
+        cfg = fbngen.CONFIGS[key]
+        if key == "C4":
+            self.nets = [fbngen.make_net(key, j) for j in range(cfg.n_nets)]
+            self.cases = [fbngen.make_cases(key, n, j) for j, n in enumerate(self.nets)]
+            off = fbngen.forest_offsets(self.nets)
+            self.slot_cases = [fbngen.forest_case(off, self.cases, s) for s in range(cfg.n_cases)]
+        else:
+            self.nets = [fbngen.make_net(key, 0)]
+            self.cases = [fbngen.make_cases(key, self.nets[0])]
+            self.slot_cases = self.cases[0]
+        self.per_slot = len(self.nets)
+        self.marg_off = np.concatenate([[0], np.cumsum([int(np.sum(n.card)) for n in self.nets])]).astype(int)
+        self.marg = int(self.marg_off[-1])
+
+    def handles(self, fbn):
+        h = [fbn.net_from_spec(n) for n in self.nets]
+        return h if len(h) > 1 else h[0]
+
+    def sample(self, k):
+        """(network, case index) pairs of the accuracy and host samples."""
+        if len(self.nets) == 1:
+            return [(0, i) for i in range(min(k, len(self.cases[0])))]
+        per = max(1, k // 8)
+        return [(j, i) for j in range(min(8, len(self.nets))) for i in range(min(per, len(self.cases[j])))]
+
+
+def workload_config(key, W, jt_stats, n_slots):
     import fbngen
     return {
         "workload": f"{key}: {fbngen.CONFIGS[key].description}",
-        "queries_per_step": n_cases,
-        "variables": net.n,
+        "queries_per_step": n_slots * W.per_slot,
+        "networks": len(W.nets),
+        "slots": n_slots,
+        "variables": jt_stats["n_vars"],
         "cliques": jt_stats["n_cliques"],
         "table_entries_T": jt_stats["T"],
         "max_clique_entries": jt_stats["max_clique"],
@@ -46,9 +87,10 @@ def workload_config(key, net, jt_stats, n_cases):
     }
 
 
-def time_batched(fbn, net, cases, precision, steps, warmup, profile):
+def time_batched(fbn, W, precision, steps, warmup, profile):
+    cases = W.slot_cases
     n = len(cases)
-    jt = fbn.JT(fbn.net_from_spec(net), precision=precision, max_slots=n)
+    jt = fbn.JT(W.handles(fbn), precision=precision, max_slots=n)
     slots = list(range(n))
     fbn.set_evidence_batch(jt, slots, cases)
     for _ in range(warmup):
@@ -62,41 +104,49 @@ def time_batched(fbn, net, cases, precision, steps, warmup, profile):
     prof = fbn.jt_profile_read(jt)      # synchronises the stream
     dt = time.perf_counter() - t0
     fbn.jt_profile_enable(jt, False)
-    post, lp, st = fbn.query_all(jt, slots, int(np.sum(net.card)))
+    post, lp, st = fbn.query_all(jt, slots, W.marg)
     return jt, dt, prof, post, lp, st
 
 
-def time_plain(fbn, net, cases, n_queries, graph=True):
-    """One query per calibration, waiting for each result (a per-query
-    engine); the layer sequence is replayed as one captured graph."""
+def time_plain(fbn, W, n_queries, graph=True):
+    """One query per calibration on the query's own network, waiting for
+    each result (a per-query engine); with graph, the layer sequence is
+    replayed as one captured graph.  Returns q/s, latencies and, per
+    network used, (case indices, post, log_pe, status)."""
     import torch
-    m = min(n_queries, len(cases))
+    groups = {}
+    for j, i in W.sample(n_queries):
+        groups.setdefault(j, []).append(i)
     stream = torch.cuda.Stream()
-    jt = fbn.JT(fbn.net_from_spec(net), precision=fbn.FBN_FP64, max_slots=m, stream=stream.cuda_stream)
-    if graph:
-        fbn.set_graph_mode(jt, True)
-    slots = list(range(m))
-    fbn.set_evidence_batch(jt, slots, cases[:m])
-    marg = int(np.sum(net.card))
-    for s in slots[:3]:                 # warm-up (uploads evidence)
-        fbn.calibrate(jt, [s], want_results=True)
-    lat = []
-    t0 = time.perf_counter()
-    for s in slots:
-        a = time.perf_counter()
-        fbn.calibrate(jt, [s], want_results=True)
-        lat.append(time.perf_counter() - a)
-    dt = time.perf_counter() - t0
-    post, lp, st = fbn.query_all(jt, slots, marg)
-    return jt, m / dt, np.array(lat), post, lp, st
+    lat, res, dt = [], {}, 0.0
+    for j, idx in groups.items():
+        net = W.nets[j]
+        jt = fbn.JT(fbn.net_from_spec(net), precision=fbn.FBN_FP64, max_slots=len(idx), stream=stream.cuda_stream)
+        if graph:
+            fbn.set_graph_mode(jt, True)
+        slots = list(range(len(idx)))
+        fbn.set_evidence_batch(jt, slots, [W.cases[j][i] for i in idx])
+        for s in slots[:3]:             # warm-up (uploads evidence)
+            fbn.calibrate(jt, [s], want_results=True)
+        t0 = time.perf_counter()
+        for s in slots:
+            a = time.perf_counter()
+            fbn.calibrate(jt, [s], want_results=True)
+            lat.append(time.perf_counter() - a)
+        dt += time.perf_counter() - t0
+        post, lp, st = fbn.query_all(jt, slots, int(np.sum(net.card)))
+        res[j] = (idx, post, lp, st)
+        jt.free()
+    return len(lat) / dt, np.array(lat), res
 
 
-def time_with_host_io(fbn, net, cases, precision, steps):
+def time_with_host_io(fbn, W, precision, steps):
     """Same batch, counting evidence upload and posterior download (PCIe)."""
+    cases = W.slot_cases
     n = len(cases)
-    jt = fbn.JT(fbn.net_from_spec(net), precision=precision, max_slots=n)
+    jt = fbn.JT(W.handles(fbn), precision=precision, max_slots=n)
     slots = list(range(n))
-    marg = int(np.sum(net.card))
+    marg = W.marg
     fbn.set_evidence_batch(jt, slots, cases)
     fbn.calibrate(jt, slots)
     fbn.query_all(jt, slots, marg)
@@ -105,41 +155,62 @@ def time_with_host_io(fbn, net, cases, precision, steps):
         fbn.set_evidence_batch(jt, slots, cases)
         fbn.calibrate(jt, slots)
         fbn.query_all(jt, slots, marg)
-    return n * steps / (time.perf_counter() - t0)
+    return n * W.per_slot * steps / (time.perf_counter() - t0)
 
 
-def cpu_baseline(net, cases, seconds):
+def cpu_baseline(W, seconds):
     import oracle
-    ojt = oracle.compile_net(net)
+    sample = W.sample(200 if len(W.nets) == 1 else 512)
+    ojts = {j: oracle.compile_net(W.nets[j]) for j in sorted({j for j, _ in sample})}
     threads = max(1, min(16, os.cpu_count() or 1))
     done = 0
     t0 = time.perf_counter()
-    sample = cases[: max(1, min(len(cases), 200))]
 
     def run(k):
-        v, s = sample[k % len(sample)]
-        ojt.query(v, s)
+        j, i = sample[k % len(sample)]
+        ojts[j].query(*W.cases[j][i])
         return 1
 
     with ThreadPoolExecutor(threads) as ex:
         while time.perf_counter() - t0 < seconds:
             done += sum(ex.map(run, range(done, done + 4 * threads)))
     dt = time.perf_counter() - t0
+    what = (f"the first {len(sample)} cases" if len(W.nets) == 1 else
+            f"{len(sample)} (network, case) queries: the first {len(sample) // len(ojts)} cases of the first "
+            f"{len(ojts)} networks")
     return {"value": done / dt, "unit": "queries/s", "cores": threads, "kind": "oracle",
-            "sample": f"{done} oracle queries cycling over the first {len(sample)} cases, {dt:.1f} s, "
-                      f"{threads} threads (one query per thread at a time)"}, ojt
+            "sample": f"{done} oracle queries cycling over {what}, {dt:.1f} s, "
+                      f"{threads} threads (one query per thread at a time)"}, ojts
 
 
-def accuracy(ojt, cases, post, lp, k, fp32):
+def accuracy(W, ojts, get, pairs, fp32):
+    """get(j, i) -> (posterior slice of network j, case i; its log P(e) or
+    None where the path only reports a sum over networks)."""
+    import oracle
     worst_abs = worst_rel = worst_lp = 0.0
-    for i in range(min(k, len(cases))):
-        olp, op = ojt.query(*cases[i])
-        err = np.abs(post[i] - op)
+    for j, i in pairs:
+        if j not in ojts:
+            ojts[j] = oracle.compile_net(W.nets[j])
+        olp, op = ojts[j].query(*W.cases[j][i])
+        post, lp = get(j, i)
+        err = np.abs(post - op)
         worst_abs = max(worst_abs, float(err.max()))
         worst_rel = max(worst_rel, float(np.max(err / np.maximum(np.abs(op), 1e-300))))
-        worst_lp = max(worst_lp, abs(float(lp[i]) - olp))
-    return {"cases_checked": min(k, len(cases)), "max_abs_err": worst_abs,
+        if lp is not None:
+            worst_lp = max(worst_lp, abs(float(lp) - olp))
+    return {"queries_checked": len(pairs), "max_abs_err": worst_abs,
             "max_rel_err": None if fp32 else worst_rel, "max_logpe_err": worst_lp}
+
+
+def forest_logpe_err(W, ojts, lp, slot):
+    """|log P(e) of a forest slot - sum over networks of the oracle's|."""
+    import oracle
+    tot = 0.0
+    for j in range(len(W.nets)):
+        if j not in ojts:
+            ojts[j] = oracle.compile_net(W.nets[j])
+        tot += ojts[j].query(*W.cases[j][slot])[0]
+    return abs(float(lp[slot]) - tot)
 
 
 def main():
@@ -161,20 +232,20 @@ def main():
                                    "described in the design notes but not built", "n_gpus": args.gpus}))
         sys.exit(2)
 
-    import fbngen
     from paper_2212_04241_amd import fbn
 
     key = args.workload
-    net = fbngen.make_net(key, 0)
-    cases = fbngen.make_cases(key, net)
-    n = len(cases)
-    log(f"[bench] {key}: {net.n} variables, {n} cases")
+    W = Workload(key)
+    n = len(W.slot_cases)
+    q = n * W.per_slot
+    log(f"[bench] {key}: {len(W.nets)} network(s), {sum(x.n for x in W.nets)} variables, {n} slots, "
+        f"{q} queries per step")
 
     # FP32 batched (the headline path), kernel timing by HIP events
-    jt32, dt32, prof32, post32, lp32, st32 = time_batched(fbn, net, cases, fbn.FBN_FP32_RESCALED,
+    jt32, dt32, prof32, post32, lp32, st32 = time_batched(fbn, W, fbn.FBN_FP32_RESCALED,
                                                           args.steps, args.warmup, True)
     stats = jt32.stats
-    qps32 = n * args.steps / dt32
+    qps32 = q * args.steps / dt32
     log(f"[bench] fp32 batched: {qps32:.1f} q/s, {1e3 * dt32 / args.steps:.3f} ms/step")
     jt32.free()
     if args.copy_calibration:
@@ -193,19 +264,17 @@ def main():
                           "kernel_ms_per_step": {k: v[0] / args.steps for k, v in prof32.items()}}), flush=True)
         return
     # FP64 batched
-    jt64, dt64, _, post64, lp64, st64 = time_batched(fbn, net, cases, fbn.FBN_FP64, max(1, args.steps // 2),
-                                                     1, False)
-    qps64b = n * max(1, args.steps // 2) / dt64
+    steps64 = max(1, args.steps // 2)
+    jt64, dt64, _, post64, lp64, st64 = time_batched(fbn, W, fbn.FBN_FP64, steps64, 1, False)
+    qps64b = q * steps64 / dt64
     jt64.free()
     log(f"[bench] fp64 batched: {qps64b:.1f} q/s")
     # FP64 plain, one query per calibration
-    jtp, qps_plain, lat, postp, lpp, stp = time_plain(fbn, net, cases, args.plain_queries)
-    jtp.free()
+    qps_plain, lat, plain = time_plain(fbn, W, args.plain_queries)
     log(f"[bench] fp64 plain (graph replay): {qps_plain:.1f} q/s, p50 {1e3 * np.median(lat):.3f} ms")
-    jte, qps_plain_eager, lat_e, _, _, _ = time_plain(fbn, net, cases, args.plain_queries, graph=False)
-    jte.free()
+    qps_plain_eager, lat_e, _ = time_plain(fbn, W, args.plain_queries, graph=False)
     log(f"[bench] fp64 plain (eager launches): {qps_plain_eager:.1f} q/s")
-    qps_io = time_with_host_io(fbn, net, cases, fbn.FBN_FP32_RESCALED, max(1, args.steps // 4))
+    qps_io = time_with_host_io(fbn, W, fbn.FBN_FP32_RESCALED, max(1, args.steps // 4))
     log(f"[bench] fp32 batched with host i/o: {qps_io:.1f} q/s")
 
     # roofline of the dominant kernel over the timed region
@@ -219,6 +288,7 @@ def main():
                 "avg_launch_us": round(1e3 * ms / max(launches, 1), 3),
                 "bytes_per_launch": byts / max(launches, 1)}
 
+    T = stats["T"]
     out = {
         "metric": "evidence queries/sec and table-op HBM GB/s, FP32-served vs plain FP64, 1 GPU",
         "value": round(qps32, 1),
@@ -232,15 +302,15 @@ def main():
         "vs_baseline": None,
         "dtype": "f32",
         "data": "synthetic",
-        "config": workload_config(key, net, stats, n),
+        "config": workload_config(key, W, stats, n),
         "roofline": roofline,
         "paths": {
             "fp32_batched": {"queries_per_s": round(qps32, 1),
-                             "useful_GBps": round(qps32 * 3 * stats["T"] * 4 / 1e9, 1),
+                             "useful_GBps": round(n * args.steps / dt32 * 3 * T * 4 / 1e9, 1),
                              "kernel_ms_per_step": {k: round(v[0] / args.steps, 4) for k, v in prof32.items()},
                              "kernel_share": round(kern_total_ms / (1e3 * dt32), 3)},
             "fp64_batched": {"queries_per_s": round(qps64b, 1),
-                             "useful_GBps": round(qps64b * 3 * stats["T"] * 8 / 1e9, 1)},
+                             "useful_GBps": round(n * steps64 / dt64 * 3 * T * 8 / 1e9, 1)},
             "fp64_plain_per_query": {"queries_per_s": round(qps_plain, 1),
                                      "p50_ms": round(1e3 * float(np.median(lat)), 4),
                                      "p99_ms": round(1e3 * float(np.percentile(lat, 99)), 4),
@@ -252,14 +322,33 @@ def main():
         },
     }
     if not args.no_cpu_baseline:
-        cb, ojt = cpu_baseline(net, cases, args.cpu_seconds)
+        cb, ojts = cpu_baseline(W, args.cpu_seconds)
         out["cpu_baseline"] = cb
+        pairs = W.sample(20 if len(W.nets) == 1 else 64)
+        forest = len(W.nets) > 1
+        mo = W.marg_off
+
+        def batched(post, lp):
+            # slot i carries case i of every network
+            return lambda j, i: (post[i, mo[j]:mo[j + 1]], None if forest else lp[i])
+
+        def plain_get(j, i):
+            idx, post, lp, _ = plain[j]
+            k = idx.index(i)
+            return post[k], lp[k]
+
+        plain_pairs = [(j, i) for j, i in pairs if j in plain and i in plain[j][0]]
         out["accuracy"] = {
-            "fp32_batched": accuracy(ojt, cases, post32, lp32, 20, True),
-            "fp64_batched": accuracy(ojt, cases, post64, lp64, 20, False),
-            "fp64_plain": accuracy(ojt, cases, postp, lpp, 20, False),
+            "fp32_batched": accuracy(W, ojts, batched(post32, lp32), pairs, True),
+            "fp64_batched": accuracy(W, ojts, batched(post64, lp64), pairs, False),
+            "fp64_plain": accuracy(W, ojts, plain_get, plain_pairs, False),
         }
-        out["status_nonzero"] = int(np.count_nonzero(st32)) + int(np.count_nonzero(st64)) + int(np.count_nonzero(stp))
+        if forest:
+            out["accuracy"]["fp32_batched"]["max_logpe_err"] = forest_logpe_err(W, ojts, lp32, 0)
+            out["accuracy"]["fp64_batched"]["max_logpe_err"] = forest_logpe_err(W, ojts, lp64, 0)
+            out["accuracy"]["logpe_note"] = "forest slots: log P(e) of slot 0 against the sum over all networks"
+        out["status_nonzero"] = (int(np.count_nonzero(st32)) + int(np.count_nonzero(st64)) +
+                                 sum(int(np.count_nonzero(r[3])) for r in plain.values()))
     print(json.dumps(out), flush=True)
 
 

@@ -353,6 +353,23 @@ def make_cases(key: str, net: Net, j: int = 0, n_cases: int | None = None):
     return cases
 
 
+def forest_offsets(nets) -> np.ndarray:
+    """Variable-id offset of each network in a forest built from `nets` in
+    order: network k's variables follow those of networks 0..k-1."""
+    return np.concatenate([[0], np.cumsum([n.n for n in nets])]).astype(np.int64)
+
+
+def forest_case(offsets, cases_per_net, s: int):
+    """Evidence of one forest slot: case s of every network, ids offset."""
+    vs, st = [], []
+    for k, cases in enumerate(cases_per_net):
+        v, x = cases[s]
+        vs.append(np.asarray(v, np.int64) + int(offsets[k]))
+        st.append(np.asarray(x, np.int64))
+    return (np.concatenate(vs).astype(np.int32) if vs else np.zeros(0, np.int32),
+            np.concatenate(st).astype(np.int32) if st else np.zeros(0, np.int32))
+
+
 def make_arrivals(key: str = "C5", n_queries: int = 4096, n_nets: int = 8):
     """Served-load trace: unit-rate Poisson inter-arrival gaps (scale by 1/lambda
     at replay), each query picking a network uniformly and an observed

@@ -83,13 +83,15 @@ typedef struct {
 } fbn_jt_options;
 
 typedef struct {
-    int32_t n_vars, n_cliques, n_edges, root, H, D; /* H: root height, D: max depth */
+    int32_t n_vars, n_cliques, n_edges, root, H, D; /* root: first root; H: max height, D: max depth */
     uint64_t T;            /* sum of clique table entries                         */
     uint64_t K;            /* sum over edges of the parent table size (map length) */
     uint64_t max_clique;   /* largest clique table                                */
     uint64_t sep_total;    /* sum of separator table entries                      */
     uint64_t device_bytes; /* device memory held by the jt                        */
     uint64_t slot_bytes;   /* of which per evidence slot                          */
+    int32_t n_trees;       /* networks (roots) in the jt: 1 unless built as a forest */
+    int32_t reserved;
 } fbn_jt_stats_t;
 
 /* Fill opt with defaults: FP64, 1 slot, 2^31-1 max entries, device build. */
@@ -113,6 +115,17 @@ void fbn_free_net(fbn_net* net);
  * root of minimum eccentricity (fewest layers), per-edge index maps, prior
  * potentials, device upload.  opt may be NULL (defaults). */
 fbn_status fbn_build_jt(const fbn_net* net, const fbn_jt_options* opt, fbn_jt** out);
+/* Several independent networks in one jt: each is compiled exactly as by
+ * fbn_build_jt (its own tree and root), and the trees form one forest whose
+ * layers are aligned by height in the collect sweep and by depth in the
+ * distribute sweep, so one launch per layer serves every network (the
+ * paper's layer-wise parallelism of Section 2 taken across networks).
+ * Variables, cliques and edges of network k follow those of networks
+ * 0..k-1 (ids offset by their counts); one slot carries evidence for all
+ * networks at once, and its log P(e) is the sum over the networks.
+ * nets[n_nets] are borrowed for the call.  A network that fails to compile
+ * fails the whole call (its index is named in fbn_last_error()). */
+fbn_status fbn_build_forest(const fbn_net* const* nets, int32_t n_nets, const fbn_jt_options* opt, fbn_jt** out);
 void fbn_free_jt(fbn_jt* jt);  /* synchronises its stream first */
 /* Replace the stream used by later calls (drops captured graphs). */
 fbn_status fbn_set_stream(fbn_jt* jt, void* stream);

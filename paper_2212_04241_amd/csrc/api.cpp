@@ -414,6 +414,8 @@ fbn_status setup_device(fbn_jt* jt) {
     c.nvars = jt->tree.n;
     c.ne = jt->tree.ne;
     c.kappa_total = p.kappa_total;
+    c.sep_total = p.sep_total;
+    c.nroots = p.n_roots;
     c.fp32 = f32 ? 1 : 0;
     c.tile = p.stage;
     HIP_OK(hipStreamSynchronize(jt->stream));
@@ -603,8 +605,7 @@ fbn_status fbn_net_from_arrays(int32_t n, const int32_t* card, const int32_t* np
 
 void fbn_free_net(fbn_net* net) { delete net; }
 
-fbn_status fbn_build_jt(const fbn_net* net, const fbn_jt_options* opt_in, fbn_jt** out) {
-    if (!net || !out) return fail(FBN_E_INVALID_ARG, "null argument");
+static fbn_status build_jt_impl(const std::vector<const fbn_net*>& nets, const fbn_jt_options* opt_in, fbn_jt** out) {
     *out = nullptr;
     fbn_jt_options opt;
     if (opt_in) opt = *opt_in;
@@ -617,11 +618,30 @@ fbn_status fbn_build_jt(const fbn_net* net, const fbn_jt_options* opt_in, fbn_jt
     try {
         jt = new fbn_jt();
         jt->opt = opt;
-        int code = 0;
-        std::string err = compile_tree(net->net, opt.max_clique_entries, jt->tree, code);
-        if (!err.empty()) {
-            delete jt;
-            return fail(code ? code : FBN_E_INVALID_ARG, err);
+        if (nets.size() == 1) {
+            int code = 0;
+            std::string err = compile_tree(nets[0]->net, opt.max_clique_entries, jt->tree, code);
+            if (!err.empty()) {
+                delete jt;
+                return fail(code ? code : FBN_E_INVALID_ARG, err);
+            }
+        } else {
+            std::vector<Tree> parts(nets.size());
+            uint64_t nv = 0;
+            for (size_t k = 0; k < nets.size(); k++) {
+                int code = 0;
+                std::string err = compile_tree(nets[k]->net, opt.max_clique_entries, parts[k], code);
+                if (!err.empty()) {
+                    delete jt;
+                    return fail(code ? code : FBN_E_INVALID_ARG, "network " + std::to_string(k) + ": " + err);
+                }
+                nv += (uint64_t)parts[k].n;
+            }
+            if (nv > 0x7fffffffull) {
+                delete jt;
+                return fail(FBN_E_TOO_LARGE, "too many variables in the forest");
+            }
+            jt->tree = merge_forest(parts);
         }
         // default tile: 8 KB of table per slot, so four slots share a workgroup
         const int def_tile = opt.precision == FBN_FP32_RESCALED ? 1024 : 512;
@@ -679,6 +699,22 @@ fbn_status fbn_build_jt(const fbn_net* net, const fbn_jt_options* opt_in, fbn_jt
         }
         return fail(FBN_E_TOO_LARGE, e.what());
     }
+}
+
+fbn_status fbn_build_jt(const fbn_net* net, const fbn_jt_options* opt_in, fbn_jt** out) {
+    if (!net || !out) return fail(FBN_E_INVALID_ARG, "null argument");
+    return build_jt_impl({net}, opt_in, out);
+}
+
+fbn_status fbn_build_forest(const fbn_net* const* nets, int32_t n_nets, const fbn_jt_options* opt_in, fbn_jt** out) {
+    if (!nets || !out || n_nets < 1) return fail(FBN_E_INVALID_ARG, "null argument or no networks");
+    *out = nullptr;
+    std::vector<const fbn_net*> v((size_t)n_nets);
+    for (int32_t k = 0; k < n_nets; k++) {
+        if (!nets[k]) return fail(FBN_E_INVALID_ARG, "null network");
+        v[(size_t)k] = nets[k];
+    }
+    return build_jt_impl(v, opt_in, out);
 }
 
 void fbn_free_jt(fbn_jt* jt) {
@@ -911,8 +947,9 @@ fbn_status fbn_jt_stats(const fbn_jt* jt, fbn_jt_stats_t* out) {
     out->n_cliques = t.nc;
     out->n_edges = t.ne;
     out->root = t.root;
-    out->H = t.height[(size_t)t.root];
+    out->n_trees = (int32_t)t.roots.size();
     for (int c = 0; c < t.nc; c++) {
+        out->H = std::max(out->H, t.height[(size_t)c]);
         out->D = std::max(out->D, t.depth[(size_t)c]);
         out->T += t.size[(size_t)c];
         out->max_clique = std::max(out->max_clique, t.size[(size_t)c]);

@@ -28,7 +28,8 @@ struct Tree {
     int nc = 0;                                  // cliques
     std::vector<std::vector<int>> vars;          // table layout order
     std::vector<uint64_t> size;                  // entries per clique
-    int root = 0;
+    int root = 0;                                // first root
+    std::vector<int> roots;                      // one per network of a forest
     std::vector<int> parent, pedge, height, depth;
     std::vector<std::vector<int>> children;      // ascending id
     int ne = 0;                                  // edges, by ascending child id
@@ -42,6 +43,11 @@ struct Tree {
 // Returns an empty string on success, else the error text.  code receives
 // an fbn_status value.
 std::string compile_tree(const Net& net, uint64_t max_entries, Tree& out, int& code);
+
+// Several independent networks as one forest: variables, cliques and edges
+// of network k follow those of networks 0..k-1 (ids offset), each network
+// keeps its own tree and root.
+Tree merge_forest(const std::vector<Tree>& parts);
 
 // ---------------------------------------------------------------- plan records
 

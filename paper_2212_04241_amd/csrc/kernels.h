@@ -34,6 +34,7 @@ struct Ctx {
     uint64_t psi_stride;
     uint32_t sep_stride, part_stride, kexp_stride, marg_stride, ev_stride;
     int32_t nvars, ne, kappa_total, fp32;
+    uint32_t sep_total, nroots;  // the roots' one-entry separators follow sep_total
     uint32_t tile;         // LDS entries reserved per slot in a workgroup
 };
 

@@ -301,8 +301,8 @@ __device__ __forceinline__ bool team_of(uint32_t nbig, uint32_t nfins, double* r
 // After a collect layer, per separator: finish the message (sum partial
 // sums where a segment spanned several tiles), rescale it by an exact power
 // of two so its largest entry lies in [0.5, 1), store it in table precision
-// and record the exponent.  The root's one-entry virtual separator yields
-// log P(e).
+// and record the exponent.  A root's one-entry virtual separator holds its
+// tree's share of P(e); zero there means the evidence is impossible.
 template <typename T>
 __global__ __launch_bounds__(kBlock) void k_fin_collect(Ctx c, const DSepFin* __restrict__ fins, uint32_t nfins,
                                                         uint32_t nbig, const int32_t* __restrict__ slots) {
@@ -334,17 +334,7 @@ __global__ __launch_bounds__(kBlock) void k_fin_collect(Ctx c, const DSepFin* __
     mx = tm.max(mx);
 
     if (f.edge < 0) {
-        if (lane == 0) {
-            const double z = acc[f.sep];
-            long long ks = c.kappa_total;
-            for (int e = 0; e < c.ne; e++) ks += kexp[e];
-            if (z > 0.0) {
-                c.logpe[slot] = log(z) + 0.69314718055994530942 * (double)ks;
-            } else {
-                c.logpe[slot] = -INFINITY;
-                atomicOr(&c.flags[slot], c.fp32 ? 2 : 1);
-            }
-        }
+        if (lane == 0 && !(acc[f.sep] > 0.0)) atomicOr(&c.flags[slot], c.fp32 ? 2 : 1);
         return;
     }
     int k = 0;
@@ -612,11 +602,40 @@ __global__ __launch_bounds__(kBlock) void k_fin_distribute(Ctx c, const DSepFin*
     }
 }
 
-// Posteriors: normalise each variable's marginal.
+// Posteriors: normalise each variable's marginal.  log P(e): the log of the
+// product of the roots' sums (one per tree of the forest) plus the
+// rescaling exponents of the priors and of every collect message.
 __global__ __launch_bounds__(kBlock) void k_marginals(Ctx c, const int32_t* __restrict__ slots) {
+    __shared__ double s_log[kBlock];
+    __shared__ long long s_exp[kBlock];
     const int slot = slots[blockIdx.x];
     const double* marg = c.marg + (uint64_t)slot * c.marg_stride;
     double* post = c.post + (uint64_t)slot * c.marg_stride;
+    {
+        const double* acc = c.acc + (uint64_t)slot * c.sep_stride;
+        const int32_t* kexp = c.kexp + (uint64_t)slot * c.kexp_stride;
+        double lg = 0.0;
+        long long ks = 0;
+        for (uint32_t r = threadIdx.x; r < c.nroots; r += kBlock) {
+            const double z = acc[c.sep_total + r];
+            lg += z > 0.0 ? log(z) : -INFINITY;
+        }
+        for (int e = threadIdx.x; e < c.ne; e += kBlock) ks += kexp[e];
+        s_log[threadIdx.x] = lg;
+        s_exp[threadIdx.x] = ks;
+        __syncthreads();
+        for (int h = kBlock / 2; h > 0; h >>= 1) {
+            if ((int)threadIdx.x < h) {
+                s_log[threadIdx.x] += s_log[threadIdx.x + h];
+                s_exp[threadIdx.x] += s_exp[threadIdx.x + h];
+            }
+            __syncthreads();
+        }
+        if (threadIdx.x == 0) {
+            const double l = s_log[0];
+            c.logpe[slot] = l > -INFINITY ? l + 0.69314718055994530942 * (double)(s_exp[0] + c.kappa_total) : -INFINITY;
+        }
+    }
     bool empty = false;
     for (int v = threadIdx.x; v < c.nvars; v += kBlock) {
         const DHomeVar h = c.hv[v];

@@ -117,7 +117,8 @@ std::string check_plan(const Tree& t, const Plan& p) {
         for (uint32_t x : {0u, d.size - 1, d.size / 2, d.L, d.L - 1})
             if (x < d.size && mdiv_host(x, d.Lmul, d.Lsh) != x / d.L) return "magic division";
         if ((uint64_t)d.hdig + rows > p.digits.size() || (uint64_t)d.ldig + d.L > p.digits.size()) return "digit tables";
-        const uint32_t psize = (int)c == t.root ? 1u : (uint32_t)t.e_size[(size_t)t.pedge[c]];
+        const bool is_root = t.pedge[c] < 0;
+        const uint32_t psize = is_root ? 1u : (uint32_t)t.e_size[(size_t)t.pedge[c]];
         if (d.seg == 0 || d.size != d.seg * psize) return "segment";
         if ((uint64_t)d.psep + psize > p.sep_real) return "parent separator offset";
         auto check_map = [&](uint32_t mh, uint32_t ml, uint32_t limit) -> bool {
@@ -127,7 +128,9 @@ std::string check_plan(const Tree& t, const Plan& p) {
             for (uint32_t l = 0; l < d.L; l++) mx_l = std::max<uint64_t>(mx_l, p.maps[ml + l]);
             return mx_h + mx_l < limit;
         };
-        if ((int)c != t.root && !check_map(d.pmh, d.pml, psize)) return "parent map range";
+        if (is_root != (d.pedge < 0) || (is_root && (d.psep < p.sep_total || d.psep >= p.sep_real)))
+            return "root separator";
+        if (!is_root && !check_map(d.pmh, d.pml, psize)) return "parent map range";
         if ((uint64_t)d.child0 + d.nchild > p.children.size() || d.nchild != t.children[c].size()) return "children";
         for (uint32_t k = 0; k < d.nchild; k++) {
             const DChild& r = p.children[d.child0 + k];
@@ -259,8 +262,9 @@ void build_plan(const Tree& t, int tile, uint32_t max_stage, Plan& p) {
     p.tile = tile;
     const int nc = t.nc;
 
-    // ---- separator arena: real edges in id order, the root's virtual
-    // entry, then one-variable virtual separators for private variables
+    // ---- separator arena: real edges in id order, one virtual entry per
+    // root (a forest of several networks has several), then one-variable
+    // virtual separators for private variables
     p.sep_off.resize((size_t)t.ne);
     uint64_t so = 0;
     for (int e = 0; e < t.ne; e++) {
@@ -268,7 +272,12 @@ void build_plan(const Tree& t, int tile, uint32_t max_stage, Plan& p) {
         so += t.e_size[(size_t)e];
     }
     p.sep_total = (uint32_t)so;
-    so += 1;
+    std::vector<uint32_t> root_sep((size_t)nc, 0);
+    p.n_roots = 0;
+    for (int c = 0; c < nc; c++)
+        if (t.pedge[(size_t)c] < 0) root_sep[(size_t)c] = p.sep_total + p.n_roots++;
+    if (p.n_roots == 0) throw std::runtime_error("tree without a root");
+    so += p.n_roots;
     p.sep_real = (uint32_t)so;
 
     // posterior source: smallest real separator containing the variable
@@ -364,9 +373,9 @@ void build_plan(const Tree& t, int tile, uint32_t max_stage, Plan& p) {
         }
         (void)rows;
         // parent map (prefix of the layout) and segment length
-        if (c == t.root) {
+        if (t.pedge[(size_t)c] < 0) {
             d.pedge = -1;
-            d.psep = p.sep_total;
+            d.psep = root_sep[(size_t)c];
             d.seg = (uint32_t)size;
             d.pmh = d.pml = 0;
         } else {

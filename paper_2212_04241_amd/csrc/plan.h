@@ -20,7 +20,8 @@ struct Plan {
     uint32_t max_stage = 0;           // bound on stage
     uint64_t T = 0;                   // prior / working-table entries
     uint32_t sep_total = 0;           // separator entries over all edges
-    uint32_t sep_stride = 0;          // per slot: sep_total + 1 (root's virtual entry) rounded
+    uint32_t n_roots = 0;             // trees of the forest; virtual entries follow sep_total
+    uint32_t sep_stride = 0;          // per slot: separators, root entries, virtual separators, rounded
     uint32_t n_parts = 0;             // partial sums per slot
     uint32_t marg_total = 0;          // sum of cardinalities
     int kappa_total = 0;              // sum of clique prior exponents

@@ -237,6 +237,7 @@ std::string compile_tree(const Net& net, uint64_t max_entries, Tree& t, int& cod
     int root = path[(size_t)diam / 2];
     if (diam % 2 == 1) root = std::min(root, path[(size_t)diam / 2 + 1]);
     t.root = root;
+    t.roots.assign(1, root);
 
     // ---- depth, parent, height, children
     t.parent.assign(nc, -1);
@@ -365,6 +366,50 @@ std::string compile_tree(const Net& net, uint64_t max_entries, Tree& t, int& cod
         for (int k = 0; k < m; k++) pos[lay[k]] = -1;
     }
     return "";
+}
+
+Tree merge_forest(const std::vector<Tree>& parts) {
+    Tree f;
+    int v0 = 0, c0 = 0, e0 = 0;
+    for (const Tree& t : parts) {
+        f.card.insert(f.card.end(), t.card.begin(), t.card.end());
+        for (int v : t.elim_order) f.elim_order.push_back(v + v0);
+        for (int c = 0; c < t.nc; c++) {
+            std::vector<int> lay = t.vars[(size_t)c];
+            for (int& v : lay) v += v0;
+            f.vars.push_back(std::move(lay));
+            f.size.push_back(t.size[(size_t)c]);
+            f.parent.push_back(t.parent[(size_t)c] < 0 ? -1 : t.parent[(size_t)c] + c0);
+            f.pedge.push_back(t.pedge[(size_t)c] < 0 ? -1 : t.pedge[(size_t)c] + e0);
+            f.height.push_back(t.height[(size_t)c]);
+            f.depth.push_back(t.depth[(size_t)c]);
+            std::vector<int> ch = t.children[(size_t)c];
+            for (int& d : ch) d += c0;
+            f.children.push_back(std::move(ch));
+            f.prior.push_back(t.prior[(size_t)c]);
+        }
+        for (int r : t.roots) f.roots.push_back(r + c0);
+        for (int e = 0; e < t.ne; e++) {
+            f.e_parent.push_back(t.e_parent[(size_t)e] + c0);
+            f.e_child.push_back(t.e_child[(size_t)e] + c0);
+            std::vector<int> sv = t.e_sep[(size_t)e];
+            for (int& v : sv) v += v0;
+            f.e_sep.push_back(std::move(sv));
+            f.e_size.push_back(t.e_size[(size_t)e]);
+        }
+        for (int v = 0; v < t.n; v++) {
+            f.cpt_home.push_back(t.cpt_home[(size_t)v] + c0);
+            f.var_home.push_back(t.var_home[(size_t)v] + c0);
+        }
+        v0 += t.n;
+        c0 += t.nc;
+        e0 += t.ne;
+    }
+    f.n = v0;
+    f.nc = c0;
+    f.ne = e0;
+    f.root = f.roots.empty() ? 0 : f.roots[0];
+    return f;
 }
 
 }  // namespace fbn

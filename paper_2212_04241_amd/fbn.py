@@ -38,7 +38,7 @@ class fbn_jt_stats_t(C.Structure):
     _fields_ = [("n_vars", C.c_int32), ("n_cliques", C.c_int32), ("n_edges", C.c_int32), ("root", C.c_int32),
                 ("H", C.c_int32), ("D", C.c_int32), ("T", C.c_uint64), ("K", C.c_uint64),
                 ("max_clique", C.c_uint64), ("sep_total", C.c_uint64), ("device_bytes", C.c_uint64),
-                ("slot_bytes", C.c_uint64)]
+                ("slot_bytes", C.c_uint64), ("n_trees", C.c_int32), ("reserved", C.c_int32)]
 
 
 class FbnError(RuntimeError):
@@ -78,6 +78,7 @@ def lib():
         "fbn_net_from_arrays": (C.c_int32, [C.c_int32, i32p, i32p, i32p, f64p, vpp]),
         "fbn_free_net": (None, [C.c_void_p]),
         "fbn_build_jt": (C.c_int32, [C.c_void_p, P(fbn_jt_options), vpp]),
+        "fbn_build_forest": (C.c_int32, [P(C.c_void_p), C.c_int32, P(fbn_jt_options), vpp]),
         "fbn_free_jt": (None, [C.c_void_p]),
         "fbn_set_stream": (C.c_int32, [C.c_void_p, C.c_void_p]),
         "fbn_set_graph_mode": (C.c_int32, [C.c_void_p, C.c_int32]),
@@ -174,9 +175,10 @@ def _torch_allocator(device: int):
 
 
 class JT:
-    """An fbn_jt handle with its options and stats."""
+    """An fbn_jt handle with its options and stats.  `net` is one Net, or a
+    list of Nets for a forest (fbn_build_forest)."""
 
-    def __init__(self, net: Net, precision: int = FBN_FP64, max_slots: int = 1, max_clique_entries: int = 0,
+    def __init__(self, net, precision: int = FBN_FP64, max_slots: int = 1, max_clique_entries: int = 0,
                  host_only: bool = False, tile_entries: int = 0, stream=None, torch_allocator: bool = False):
         L = lib()
         opt = fbn_jt_options()
@@ -194,7 +196,11 @@ class JT:
             self._cb = _torch_allocator(torch.cuda.current_device())
             opt.allocator = fbn_allocator(self._cb[0], self._cb[1], None)
         h = C.c_void_p()
-        _check(L.fbn_build_jt(net._h, C.byref(opt), C.byref(h)), "fbn_build_jt")
+        if isinstance(net, (list, tuple)):
+            arr = (C.c_void_p * len(net))(*[x._h for x in net])
+            _check(L.fbn_build_forest(arr, len(net), C.byref(opt), C.byref(h)), "fbn_build_forest")
+        else:
+            _check(L.fbn_build_jt(net._h, C.byref(opt), C.byref(h)), "fbn_build_jt")
         self._h = h
         self.precision = precision
         self.max_slots = max_slots
@@ -215,6 +221,11 @@ class JT:
 
 def build_jt(net: Net, **kw) -> JT:
     return JT(net, **kw)
+
+
+def build_forest(nets, **kw) -> JT:
+    """One jt over several independent networks (ids offset per network)."""
+    return JT(list(nets), **kw)
 
 
 def set_stream(jt: JT, stream) -> None:

@@ -163,3 +163,71 @@ def test_plan_bounds_check_large_workloads(key, j, precision):
     # LDS stage limit; the build runs the plan checker
     net = fbngen.make_net(key, j)
     _host_jt(net, precision=precision)
+
+
+# ---------------------------------------------------------------- forests
+
+def _forest_parts():
+    nets = [fbngen.make_net("C1", 0)]
+    nets += [fbngen.random_small_net(seed, n, max_card=4, window=8) for seed, n in ((3, 9), (11, 1), (29, 17))]
+    with open(os.path.join(ROOT, "tests", "golden", "micro", "disconnected.fbn")) as f:
+        nets.append(fbngen.net_from_text(f.read()))
+    return nets
+
+
+def test_forest_is_the_offset_union_of_the_parts():
+    # each network of a forest keeps the tree the oracle compiles for it
+    # alone, with variable, clique and edge ids offset by the earlier parts
+    nets = _forest_parts()
+    ljt = fbn.JT([fbn.net_from_spec(n) for n in nets], host_only=True)
+    card = np.concatenate([n.card for n in nets])
+    s = ljt.stats
+    v0 = c0 = e0 = 0
+    H = D = 0
+    for net in nets:
+        ojt = oracle.compile_net(net)
+        assert s["n_trees"] == len(nets)
+        for c in range(ojt.n_cliques):
+            lv, lh, ld = fbn.jt_clique(ljt, c0 + c)
+            ov, oh, od = ojt.clique(c)
+            assert np.array_equal(lv, np.asarray(ov) + v0) and (lh, ld) == (oh, od), c
+            H, D = max(H, oh), max(D, od)
+        for e in range(ojt.n_edges):
+            lp, lc, ls = fbn.jt_edge(ljt, e0 + e)
+            op, oc, os_ = ojt.edge(e)
+            assert (lp, lc) == (op + c0, oc + c0) and np.array_equal(ls, np.asarray(os_) + v0), e
+            assert np.array_equal(fbn.jt_index_map(ljt, e0 + e, card), ojt.index_map(e)), e
+        v0 += net.n
+        c0 += ojt.n_cliques
+        e0 += ojt.n_edges
+    la, lb = fbn.jt_homes(ljt)
+    assert len(la) == v0
+    assert (s["n_vars"], s["n_cliques"], s["n_edges"], s["H"], s["D"]) == (v0, c0, e0, H, D)
+
+
+def test_forest_offsets_and_cases():
+    nets = _forest_parts()
+    off = fbngen.forest_offsets(nets)
+    assert off[0] == 0 and off[-1] == sum(n.n for n in nets)
+    cases = [[(np.array([0], np.int32), np.array([1], np.int32))] for _ in nets]
+    v, s = fbngen.forest_case(off, cases, 0)
+    assert np.array_equal(v, off[:-1]) and np.all(s == 1)
+
+
+def test_forest_rejects_bad_input():
+    with pytest.raises(fbn.FbnError):
+        fbn.JT([], host_only=True)
+    big = fbngen.make_net("C2", 0, with_cpts=True)
+    with pytest.raises(fbn.FbnError) as ei:
+        fbn.JT([fbn.net_from_spec(fbngen.make_net("C1", 0)), fbn.net_from_spec(big)], host_only=True,
+               max_clique_entries=4096)
+    assert ei.value.code == fbn.FBN_E_TOO_LARGE and "network 1" in str(ei.value)
+
+
+@pytest.mark.parametrize("precision", [fbn.FBN_FP32_RESCALED, fbn.FBN_FP64])
+def test_plan_bounds_check_c4_forest(precision):
+    # the 256-network batch: its plan passes every kernel bound check at
+    # build time (a failing check would raise here)
+    nets = [fbngen.make_net("C4", j) for j in range(256)]
+    jt = fbn.JT([fbn.net_from_spec(n) for n in nets], host_only=True, precision=precision)
+    assert jt.stats["n_trees"] == 256 and jt.stats["n_vars"] == sum(n.n for n in nets)
