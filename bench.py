@@ -10,9 +10,11 @@ evidence already resident in device memory; posteriors stay on the device.
 
 With --workload C4 the 256 networks form one forest junction tree and a
 step calibrates 64 slots, each holding one case of every network (16384
-queries).
+queries).  With --workload C5 eight trees stay resident and serve a Poisson
+trace of queries with continuous batching; a step is one closed-loop replay
+of the trace, and latency percentiles come with it.
 
-Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload C2|C4]
+Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload C2|C4|C5]
 """
 from __future__ import annotations
 
@@ -213,6 +215,157 @@ def forest_logpe_err(W, ojts, lp, slot):
     return abs(float(lp[slot]) - tot)
 
 
+def bench_served(args, fbn):
+    """The served workload: eight resident networks, a Poisson trace of
+    evidence queries, continuous batching with footprint admission (FP32),
+    against the plain per-query FP64 engine on the same trace.  Load points:
+    closed loop (every query available at once) for both; open loop at 0.8 x
+    the plain engine's saturation rate for both; open loop at 0.8 x the
+    served saturation rate for the served path."""
+    import fbngen
+    import oracle
+    from paper_2212_04241_amd.serve import Server, serve_plain, trace_queries
+    nets = [fbngen.make_net("C5", j) for j in range(8)]
+    times, which, fracs, seeds = fbngen.make_arrivals("C5")
+    n = min(args.trace, len(times))
+    cases = [fbngen.case_for_arrival(nets[int(which[i])], float(fracs[i]), int(seeds[i])) for i in range(n)]
+    queries = trace_queries(times[:n], which[:n], cases)
+    log(f"[bench] C5: 8 networks, {n} trace queries")
+    t0 = time.perf_counter()
+    srv = Server(nets, budget_bytes=int(args.budget_gb * (1 << 30)), max_batch=args.max_batch)
+    log(f"[bench] server up in {time.perf_counter() - t0:.1f} s: {srv.slots} slots per tree, "
+        f"{srv.device_bytes / 2**30:.2f} GiB resident, plan {srv.planned_bytes / 2**30:.2f} GiB of "
+        f"{args.budget_gb} GiB")
+    keep = list(range(min(200, n)))
+    for _ in range(args.warmup):
+        srv.run(queries[: min(n, 256)])
+    # (i) closed loop, served: `steps` replays of the trace
+    tot_q = tot_t = 0.0
+    sat = None
+    for _ in range(args.steps):
+        r = srv.run(queries, None, keep=keep if sat is None else None)
+        sat = sat or r
+        tot_q += n
+        tot_t += r.wall
+    qps_served = tot_q / tot_t
+    log(f"[bench] served closed loop: {qps_served:.1f} q/s ({args.steps} x {n} queries), "
+        f"p50 {1e3 * sat.percentile(50):.2f} ms")
+    # dominant kernel: one profiled (eager) full batch per tree
+    prof = {}
+    for k, jt in enumerate(srv.jts):
+        qs = [q for q in queries if q.net == k][: srv.slots]
+        if not qs:
+            continue
+        sl = list(range(len(qs)))
+        fbn.set_evidence_batch(jt, sl, [(q.vars, q.states) for q in qs])
+        fbn.jt_profile_read(jt)
+        fbn.jt_profile_enable(jt, True)
+        fbn.calibrate(jt, sl)
+        for kind, (ms, launches, byts) in fbn.jt_profile_read(jt).items():
+            a = prof.setdefault(kind, [0.0, 0, 0.0])
+            a[0] += ms
+            a[1] += launches
+            a[2] += byts
+        fbn.jt_profile_enable(jt, False)
+    # plain FP64 engine, closed loop over a prefix
+    plain_sat = serve_plain(nets, queries, None, limit=args.plain_queries, keep=keep)
+    log(f"[bench] plain fp64 closed loop: {plain_sat.qps:.1f} q/s over {len(plain_sat.latency)} queries")
+    # (ii) open loop at 0.8 x plain saturation, both paths
+    lam2 = 0.8 * plain_sat.qps
+    srv_2 = srv.run(queries, lam2)
+    plain_2 = serve_plain(nets, queries, lam2, limit=args.plain_queries)
+    # (iii) open loop at 0.8 x served saturation
+    lam3 = 0.8 * qps_served
+    srv_3 = srv.run(queries, lam3)
+    log(f"[bench] open loop {lam2:.0f}/s: served p50 {1e3 * srv_2.percentile(50):.2f} ms p99 "
+        f"{1e3 * srv_2.percentile(99):.2f}; plain p50 {1e3 * plain_2.percentile(50):.2f} p99 "
+        f"{1e3 * plain_2.percentile(99):.2f}; open loop {lam3:.0f}/s: served p50 {1e3 * srv_3.percentile(50):.2f} "
+        f"p99 {1e3 * srv_3.percentile(99):.2f}")
+    slots, resident = srv.slots, srv.device_bytes
+    status_nonzero = int(np.count_nonzero(sat.status)) + int(np.count_nonzero(plain_sat.status))
+    fallbacks = int(np.count_nonzero(sat.precision == fbn.FBN_FP64))
+    srv.close()
+
+    kind = max(prof, key=lambda k: prof[k][0])
+    ms, launches, byts = prof[kind]
+    achieved = byts / (ms * 1e-3) / 1e9 if ms > 0 else 0.0
+    roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None, "kernel": f"k_{kind}<float>",
+                "launches": launches, "avg_launch_us": round(1e3 * ms / max(launches, 1), 3),
+                "bytes_per_launch": byts / max(launches, 1),
+                "measured_on": "one full batch per resident tree, eager launches, HIP events"}
+
+    def lat(r):
+        return {"queries_per_s": round(r.qps, 1), "p50_ms": round(1e3 * r.percentile(50), 3),
+                "p99_ms": round(1e3 * r.percentile(99), 3), "queries": int(len(r.latency))}
+
+    out = {
+        "metric": "evidence queries/sec and table-op HBM GB/s, FP32-served vs plain FP64, 1 GPU",
+        "value": round(qps_served, 1),
+        "unit": "queries/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(1e3 * tot_t / args.steps, 3),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": f"C5: {fbngen.CONFIGS['C5'].description}", "networks": 8,
+                   "trace_queries": n, "budget_GiB": args.budget_gb, "slots_per_tree": slots,
+                   "resident_GiB": round(resident / 2**30, 3), "max_batch": args.max_batch,
+                   "step": "one closed-loop replay of the trace"},
+        "roofline": roofline,
+        "paths": {
+            "served_fp32_closed_loop": lat(sat) | {"batches": sat.batches, "fp64_fallbacks": fallbacks},
+            "plain_fp64_closed_loop": lat(plain_sat),
+            "open_loop_at_0.8x_plain": {"rate_per_s": round(lam2, 1), "served": lat(srv_2), "plain": lat(plain_2)},
+            "open_loop_at_0.8x_served": {"rate_per_s": round(lam3, 1), "served": lat(srv_3),
+                                         "plain": "unstable at this rate (above its saturation)"},
+            "served_vs_plain": round(qps_served / max(plain_sat.qps, 1e-9), 2),
+        },
+        "status_nonzero": status_nonzero,
+    }
+    if not args.no_cpu_baseline:
+        sample = keep
+        threads = max(1, min(16, os.cpu_count() or 1))
+        t1 = time.perf_counter()
+        used = sorted({queries[i].net for i in sample})
+        with ThreadPoolExecutor(len(used)) as ex:
+            ojts = dict(zip(used, ex.map(lambda k: oracle.compile_net(nets[k]), used)))
+        log(f"[bench] oracle compiled in {time.perf_counter() - t1:.1f} s")
+        done = 0
+        results = {}
+        t0 = time.perf_counter()
+
+        def run(k):
+            i = sample[k % len(sample)]
+            q = queries[i]
+            lp, post = ojts[q.net].query(q.vars, q.states)
+            if k < len(sample):
+                results[i] = (lp, post)
+            return 1
+
+        with ThreadPoolExecutor(threads) as ex:
+            while time.perf_counter() - t0 < args.cpu_seconds:
+                done += sum(ex.map(run, range(done, done + threads)))
+        dt = time.perf_counter() - t0
+        out["cpu_baseline"] = {"value": done / dt, "unit": "queries/s", "cores": threads, "kind": "oracle",
+                               "sample": f"{done} oracle queries over the first {len(sample)} trace queries, "
+                                         f"{dt:.1f} s, {threads} threads (one query per thread at a time)"}
+        e32 = e64 = l32 = l64 = 0.0
+        for i, (olp, op) in results.items():
+            e32 = max(e32, float(np.max(np.abs(sat.post[i] - op))))
+            e64 = max(e64, float(np.max(np.abs(plain_sat.post[i] - op))))
+            l32 = max(l32, abs(sat.log_pe[i] - olp))
+            l64 = max(l64, abs(plain_sat.log_pe[i] - olp))
+        out["accuracy"] = {"queries_checked": len(results),
+                           "served_fp32": {"max_abs_err": e32, "max_logpe_err": l32},
+                           "plain_fp64": {"max_abs_err": e64, "max_logpe_err": l64}}
+    print(json.dumps(out), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -225,6 +378,9 @@ def main():
     ap.add_argument("--fp32-only", action="store_true", help="time only the FP32 batched path (for profiling)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run plain 512 MiB device copies (reference for byte counters)")
+    ap.add_argument("--trace", type=int, default=4096, help="C5: trace queries")
+    ap.add_argument("--budget-gb", type=float, default=32.0, help="C5: device-memory budget, GiB")
+    ap.add_argument("--max-batch", type=int, default=32, help="C5: slots per resident tree at most")
     args = ap.parse_args()
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
@@ -235,6 +391,8 @@ def main():
     from paper_2212_04241_amd import fbn
 
     key = args.workload
+    if key == "C5":
+        return bench_served(args, fbn)
     W = Workload(key)
     n = len(W.slot_cases)
     q = n * W.per_slot

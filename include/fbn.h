@@ -88,8 +88,8 @@ typedef struct {
     uint64_t K;            /* sum over edges of the parent table size (map length) */
     uint64_t max_clique;   /* largest clique table                                */
     uint64_t sep_total;    /* sum of separator table entries                      */
-    uint64_t device_bytes; /* device memory held by the jt                        */
-    uint64_t slot_bytes;   /* of which per evidence slot                          */
+    uint64_t device_bytes; /* device memory held by the jt (host_only: the bytes a */
+    uint64_t slot_bytes;   /* device build would hold); of which per evidence slot */
     int32_t n_trees;       /* networks (roots) in the jt: 1 unless built as a forest */
     int32_t reserved;
 } fbn_jt_stats_t;

@@ -195,6 +195,7 @@ struct fbn_jt {
     DHomeVar* d_hv = nullptr;
     DGroup* d_groups = nullptr;
     DSepFin* d_fins = nullptr;
+    DFinBlk* d_finblks = nullptr;
     uint64_t* d_dig = nullptr;
     uint32_t* d_map = nullptr;
     void* d_prior = nullptr;
@@ -210,6 +211,8 @@ struct fbn_jt {
     double* d_logpe = nullptr;
     int32_t* d_flags = nullptr;
     DEvidence* d_ev = nullptr;
+    double* d_bmax = nullptr;
+    double* d_bmarg = nullptr;
     int32_t* d_slots = nullptr;
     double* d_out_post = nullptr;
     double* d_out_logpe = nullptr;
@@ -310,6 +313,50 @@ fbn_status wait_staged(fbn_jt* jt) {
     return FBN_OK;
 }
 
+// Per-slot strides and the bytes one slot adds to each per-slot buffer, in
+// allocation order.
+constexpr int kSlotBuffers = 17;
+
+struct SlotLayout {
+    uint64_t psi_stride;
+    uint32_t part_stride, kexp_stride, marg_stride, ev_stride, bmax_stride, bmarg_stride;
+    size_t unit[kSlotBuffers];
+};
+
+SlotLayout slot_layout(const fbn_jt* jt) {
+    const Plan& p = jt->plan;
+    const size_t w = jt->opt.precision == FBN_FP32_RESCALED ? 4 : 8;
+    SlotLayout L{};
+    L.psi_stride = (p.T + 63) / 64 * 64;
+    L.part_stride = (p.n_parts + 63) / 64 * 64 + 64;
+    L.kexp_stride = (uint32_t)((jt->tree.ne + 1 + 63) / 64 * 64);
+    L.marg_stride = p.marg_total;
+    L.ev_stride = (uint32_t)jt->tree.nc;
+    L.bmax_stride = (uint32_t)std::max<size_t>(p.finblks.size(), 1);
+    L.bmarg_stride = std::max<uint32_t>(p.n_bmarg, 1);
+    const size_t u[kSlotBuffers] = {w * L.psi_stride, w * p.sep_stride, w * p.sep_stride, 8ull * p.sep_stride,
+                                    8ull * L.part_stride, 4ull * L.kexp_stride, 8ull * L.marg_stride,
+                                    8ull * L.marg_stride, 8, 4, sizeof(DEvidence) * L.ev_stride, 4,
+                                    8ull * L.marg_stride, 8, 4, 8ull * L.bmax_stride, 8ull * L.bmarg_stride};
+    std::copy(u, u + kSlotBuffers, L.unit);
+    return L;
+}
+
+// Device bytes a jt holds (the plan, the prior and max_slots slots), as
+// setup_device allocates them; slot_bytes receives the per-slot share.
+uint64_t footprint(const fbn_jt* jt, uint64_t& slot_bytes) {
+    const Plan& p = jt->plan;
+    auto b = [](const auto& v) { return (uint64_t)sizeof(v[0]) * std::max<uint64_t>(v.size(), 1); };
+    uint64_t fixed = b(p.cliques) + b(p.children) + b(p.targets) + b(p.margvars) + b(p.works) + b(p.wtargets) +
+                     b(p.pieces) + b(p.homevars) + b(p.groups) + b(p.fins) + b(p.finblks) + b(p.digits) +
+                     b(p.maps);
+    fixed += (jt->opt.precision == FBN_FP32_RESCALED ? 4ull : 8ull) * std::max<uint64_t>(p.T, 1);
+    const SlotLayout L = slot_layout(jt);
+    slot_bytes = 0;
+    for (size_t u : L.unit) slot_bytes += u;
+    return fixed + slot_bytes * (uint64_t)jt->opt.max_slots;
+}
+
 fbn_status setup_device(fbn_jt* jt) {
     Plan& p = jt->plan;
     const int S = jt->opt.max_slots;
@@ -329,6 +376,7 @@ fbn_status setup_device(fbn_jt* jt) {
     if ((st = upload(jt, p.homevars, jt->d_hv))) return st;
     if ((st = upload(jt, p.groups, jt->d_groups))) return st;
     if ((st = upload(jt, p.fins, jt->d_fins))) return st;
+    if ((st = upload(jt, p.finblks, jt->d_finblks))) return st;
     if ((st = upload(jt, p.digits, jt->d_dig))) return st;
     if ((st = upload(jt, p.maps, jt->d_map))) return st;
     // prior in table precision (float32: each entry rounded once, to nearest)
@@ -342,36 +390,21 @@ fbn_status setup_device(fbn_jt* jt) {
         HIP_OK(hipMemcpy(jt->d_prior, p.prior.data(), 8 * p.prior.size(), hipMemcpyHostToDevice));
     }
     // per-slot state
-    const uint64_t psi_stride = (p.T + 63) / 64 * 64;
-    const uint32_t part_stride = (p.n_parts + 63) / 64 * 64 + 64;
-    const uint32_t kexp_stride = (uint32_t)((jt->tree.ne + 1 + 63) / 64 * 64);
-    const uint32_t marg_stride = p.marg_total;
-    const uint32_t ev_stride = (uint32_t)jt->tree.nc;
+    const SlotLayout SL = slot_layout(jt);
+    const uint64_t psi_stride = SL.psi_stride;
+    const uint32_t part_stride = SL.part_stride, kexp_stride = SL.kexp_stride, marg_stride = SL.marg_stride,
+                   ev_stride = SL.ev_stride;
     const uint64_t before = jt->device_bytes;
-    struct Req {
-        void** dst;
-        size_t bytes;
-    } reqs[] = {
-        {&jt->d_psi, w * psi_stride * (size_t)S},
-        {&jt->d_sepc, w * p.sep_stride * (size_t)S},
-        {&jt->d_sepd, w * p.sep_stride * (size_t)S},
-        {(void**)&jt->d_acc, 8ull * p.sep_stride * (size_t)S},
-        {(void**)&jt->d_part, 8ull * part_stride * (size_t)S},
-        {(void**)&jt->d_kexp, 4ull * kexp_stride * (size_t)S},
-        {(void**)&jt->d_marg, 8ull * marg_stride * (size_t)S},
-        {(void**)&jt->d_post, 8ull * marg_stride * (size_t)S},
-        {(void**)&jt->d_logpe, 8ull * (size_t)S},
-        {(void**)&jt->d_flags, 4ull * (size_t)S},
-        {(void**)&jt->d_ev, sizeof(DEvidence) * ev_stride * (size_t)S},
-        {(void**)&jt->d_slots, 4ull * (size_t)S},
-        {(void**)&jt->d_out_post, 8ull * marg_stride * (size_t)S},
-        {(void**)&jt->d_out_logpe, 8ull * (size_t)S},
-        {(void**)&jt->d_out_flags, 4ull * (size_t)S},
-    };
-    for (auto& r : reqs) {
-        *r.dst = dev_alloc(jt, r.bytes);
-        if (!*r.dst) return fail(FBN_E_NOMEM_DEVICE, "device allocation failed");
-        HIP_OK(launch_zero(*r.dst, r.bytes, jt->stream));
+    void** dsts[kSlotBuffers] = {&jt->d_psi, &jt->d_sepc, &jt->d_sepd, (void**)&jt->d_acc, (void**)&jt->d_part,
+                                 (void**)&jt->d_kexp, (void**)&jt->d_marg, (void**)&jt->d_post,
+                                 (void**)&jt->d_logpe, (void**)&jt->d_flags, (void**)&jt->d_ev,
+                                 (void**)&jt->d_slots, (void**)&jt->d_out_post, (void**)&jt->d_out_logpe,
+                                 (void**)&jt->d_out_flags, (void**)&jt->d_bmax, (void**)&jt->d_bmarg};
+    for (int k = 0; k < kSlotBuffers; k++) {
+        const size_t bytes = SL.unit[k] * (size_t)S;
+        *dsts[k] = dev_alloc(jt, bytes);
+        if (!*dsts[k]) return fail(FBN_E_NOMEM_DEVICE, "device allocation failed");
+        HIP_OK(launch_zero(*dsts[k], bytes, jt->stream));
     }
     jt->slot_bytes = (jt->device_bytes - before) / (uint64_t)S;
     // host staging
@@ -405,6 +438,10 @@ fbn_status setup_device(fbn_jt* jt) {
     c.logpe = jt->d_logpe;
     c.flags = jt->d_flags;
     c.ev = jt->d_ev;
+    c.bmax = jt->d_bmax;
+    c.bmarg = jt->d_bmarg;
+    c.bmax_stride = SL.bmax_stride;
+    c.bmarg_stride = SL.bmarg_stride;
     c.psi_stride = psi_stride;
     c.sep_stride = p.sep_stride;
     c.part_stride = part_stride;
@@ -674,7 +711,9 @@ static fbn_status build_jt_impl(const std::vector<const fbn_net*>& nets, const f
             for (size_t k = 0; k < jt->tree.vars[(size_t)c].size(); k++)
                 jt->occ[(size_t)jt->tree.vars[(size_t)c][k]].push_back({c, (int)k});
         jt->dirty.assign((size_t)opt.max_slots, 0);
-        if (!opt.host_only) {
+        if (opt.host_only) {
+            jt->device_bytes = footprint(jt, jt->slot_bytes);
+        } else {
             fbn_status st = setup_device(jt);
             if (st) {
                 std::string keep = g_err;
@@ -840,6 +879,30 @@ static fbn_status enqueue_calibration(fbn_jt* jt, int32_t n) {
     // clear the per-slot flags of this batch
     HIP_OK(launch_begin(c, jt->d_slots, n, s));
     const double w = prec ? 4.0 : 8.0, nb = (double)n;
+    // a layer's finalisers: small separators one wave each, large ones in
+    // blocks over two launches; the layer's bytes are booked on its first
+    auto finalise = [&](const Layer& ly, bool dist, int kind, double bytes) -> fbn_status {
+        fbn_status r;
+        if (ly.nfin > ly.nbig) {
+            const DSepFin* f = jt->d_fins + ly.fin0 + ly.nbig;
+            const uint32_t nf = ly.nfin - ly.nbig;
+            if ((r = timed(jt, kind, bytes, [&] {
+                     return dist ? launch_fin_distribute(c, prec, f, nf, 0, jt->d_slots, n, s)
+                                 : launch_fin_collect(c, prec, f, nf, 0, jt->d_slots, n, s);
+                 })))
+                return r;
+            bytes = 0.0;
+        }
+        for (int ph = 0; ph < 2 && ly.nfb; ph++) {
+            if ((r = timed(jt, kind, bytes, [&] {
+                     return launch_fin_blocks(c, prec, dist, ph, jt->d_fins, jt->d_finblks + ly.fb0, ly.nfb,
+                                              jt->d_slots, n, s);
+                 })))
+                return r;
+            bytes = 0.0;
+        }
+        return FBN_OK;
+    };
     for (size_t h = 0; h < p.collect.size(); h++) {
         const Layer& ly = p.collect[h];
         // reads the prior, writes the working table
@@ -847,10 +910,7 @@ static fbn_status enqueue_calibration(fbn_jt* jt, int32_t n) {
                  return launch_collect(c, prec, jt->d_groups + ly.group0, ly.ngroup, jt->d_slots, n, s);
              })))
             return st;
-        if ((st = timed(jt, 1, 2.0 * w * nb * (double)jt->coll_sep[h], [&] {
-                 return launch_fin_collect(c, prec, jt->d_fins + ly.fin0, ly.nfin, ly.nbig, jt->d_slots, n, s);
-             })))
-            return st;
+        if ((st = finalise(ly, false, 1, 2.0 * w * nb * (double)jt->coll_sep[h]))) return st;
     }
     for (size_t d = 0; d < p.distribute.size(); d++) {
         const Layer& ly = p.distribute[d];
@@ -859,10 +919,7 @@ static fbn_status enqueue_calibration(fbn_jt* jt, int32_t n) {
                  return launch_distribute(c, prec, jt->d_works + ly.group0, ly.ngroup, jt->d_slots, n, s);
              })))
             return st;
-        if ((st = timed(jt, 3, 2.0 * w * nb * (double)jt->dist_sep[d], [&] {
-                 return launch_fin_distribute(c, prec, jt->d_fins + ly.fin0, ly.nfin, ly.nbig, jt->d_slots, n, s);
-             })))
-            return st;
+        if ((st = finalise(ly, true, 3, 2.0 * w * nb * (double)jt->dist_sep[d]))) return st;
     }
     if ((st = timed(jt, 4, 16.0 * nb * (double)c.marg_stride, [&] { return launch_marginals(c, jt->d_slots, n, s); })))
         return st;

@@ -120,6 +120,18 @@ struct DSepFin {
     uint32_t pad;
 };
 
+// One block of a large separator's finalisation: entries [begin, begin+count)
+// of fin `fin`.  The fin's blocks are [blk0, blk0+nblk) in Plan::finblks (so
+// this block's maximum lands at slot scratch index id), and their partial
+// posterior sums sit at mbase + j*mw (block j), mw = sum of the posterior
+// variables' cardinalities.
+struct DFinBlk {
+    uint32_t fin;
+    uint32_t begin, count;
+    uint32_t id, blk0, nblk;
+    uint32_t mbase, mw;
+};
+
 // A variable whose posterior is the marginal of a calibrated separator.
 struct DMargVar {
     uint32_t out;        // offset of its first state in the per-slot marginal arrays
@@ -178,5 +190,6 @@ struct DHomeVar {        // for the posterior finaliser: one per variable
 constexpr int kBlock = 256;       // threads per workgroup
 constexpr int kTileMax = 4096;    // entries per workgroup tile
 constexpr int kMaxPieces = 32;    // runs (and packed targets) per workgroup
+constexpr uint32_t kFinBlock = 4096;  // separator entries per finaliser block at most
 
 }  // namespace fbn

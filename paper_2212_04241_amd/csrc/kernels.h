@@ -31,8 +31,10 @@ struct Ctx {
     double* logpe;         // per slot
     int32_t* flags;        // per slot: bit 0 zero evidence, bit 1 FP32 underflow
     const DEvidence* ev;   // ev_stride per slot
+    double* bmax;          // per slot: maximum of each large-separator block (bmax_stride)
+    double* bmarg;         // per slot: partial posterior sums of those blocks (bmarg_stride)
     uint64_t psi_stride;
-    uint32_t sep_stride, part_stride, kexp_stride, marg_stride, ev_stride;
+    uint32_t sep_stride, part_stride, kexp_stride, marg_stride, ev_stride, bmax_stride, bmarg_stride;
     int32_t nvars, ne, kappa_total, fp32;
     uint32_t sep_total, nroots;  // the roots' one-entry separators follow sep_total
     uint32_t tile;         // LDS entries reserved per slot in a workgroup
@@ -52,6 +54,10 @@ hipError_t launch_collect(const Ctx& c, int prec, const DGroup* groups, uint32_t
                           const int32_t* slots, int nslots, hipStream_t s);
 hipError_t launch_fin_collect(const Ctx& c, int prec, const DSepFin* fins, uint32_t nfins, uint32_t nbig,
                               const int32_t* slots, int nslots, hipStream_t s);
+// Large separators in blocks: phase 0 then phase 1, for the collect
+// (distribute = false) or distribute sweep.
+hipError_t launch_fin_blocks(const Ctx& c, int prec, bool distribute, int phase, const DSepFin* fins,
+                             const DFinBlk* blks, uint32_t nblks, const int32_t* slots, int nslots, hipStream_t s);
 hipError_t launch_distribute(const Ctx& c, int prec, const DWork* works, uint32_t nworks,
                              const int32_t* slots, int nslots, hipStream_t s);
 hipError_t launch_fin_distribute(const Ctx& c, int prec, const DSepFin* fins, uint32_t nfins, uint32_t nbig,

@@ -602,6 +602,172 @@ __global__ __launch_bounds__(kBlock) void k_fin_distribute(Ctx c, const DSepFin*
     }
 }
 
+// ------------------------------------------------- large separator finalisers
+
+// A separator larger than one workgroup's share is finalised in blocks of at
+// most kFinBlock entries, in two launches.  Phase one finishes each block's
+// entries (partial sums), records the block's maximum and, in the
+// distribute sweep, the block's partial posterior sums.  Phase two takes the
+// separator's maximum over its blocks and writes the rescaled message
+// (collect) or ratio (distribute); the separator's first block also adds the
+// posterior sums of all blocks, in block order.  Every sum has a fixed
+// order, as in the one-team finalisers.
+
+__device__ __forceinline__ double block_max_all(double v, double* scratch) {
+    v = wave_max(v);
+    const int lane = threadIdx.x & (kWave - 1), w = threadIdx.x / kWave;
+    __syncthreads();
+    if (lane == 0) scratch[w] = v;
+    __syncthreads();
+    double s = scratch[0];
+#pragma unroll
+    for (int k = 1; k < kWaves; k++) s = fmax(s, scratch[k]);
+    return s;
+}
+
+// Finish entry m of a separator: the sum of its partials, or the layer
+// kernel's whole sum.
+__device__ __forceinline__ double finish_entry(const DSepFin& f, double* acc, const double* part, uint32_t m) {
+    if (!f.nchunk) return acc[m];
+    const double* pp = part + (uint64_t)m * f.nchunk;
+    double v = 0.0;
+    for (uint32_t k = 0; k < f.nchunk; k++) v += pp[k];
+    acc[m] = v;
+    return v;
+}
+
+// Separator maximum over the blocks of b's separator.
+__device__ __forceinline__ double fin_max(const Ctx& c, const DFinBlk& b, int slot, double* red) {
+    const double* bm = c.bmax + (uint64_t)slot * c.bmax_stride + b.blk0;
+    double mx = 0.0;
+    for (uint32_t k = threadIdx.x; k < b.nblk; k += kBlock) mx = fmax(mx, bm[k]);
+    return block_max_all(mx, red);
+}
+
+__global__ __launch_bounds__(kBlock) void k_fin_collect_a(Ctx c, const DSepFin* __restrict__ fins,
+                                                          const DFinBlk* __restrict__ blks,
+                                                          const int32_t* __restrict__ slots) {
+    __shared__ double red[kWaves];
+    const DFinBlk b = blks[blockIdx.x];
+    const DSepFin f = fins[b.fin];
+    const int slot = slots[blockIdx.y];
+    double* __restrict__ acc = c.acc + (uint64_t)slot * c.sep_stride + f.sep;
+    const double* __restrict__ part = c.part + (uint64_t)slot * c.part_stride + f.part0;
+    double mx = 0.0;
+#pragma unroll 4
+    for (uint32_t m = b.begin + threadIdx.x; m < b.begin + b.count; m += kBlock)
+        mx = fmax(mx, finish_entry(f, acc, part, m));
+    mx = block_max_all(mx, red);
+    if (threadIdx.x == 0) c.bmax[(uint64_t)slot * c.bmax_stride + b.id] = mx;
+}
+
+template <typename T>
+__global__ __launch_bounds__(kBlock) void k_fin_collect_b(Ctx c, const DSepFin* __restrict__ fins,
+                                                          const DFinBlk* __restrict__ blks,
+                                                          const int32_t* __restrict__ slots) {
+    __shared__ double red[kWaves];
+    const DFinBlk b = blks[blockIdx.x];
+    const DSepFin f = fins[b.fin];
+    const int slot = slots[blockIdx.y];
+    const double mx = fin_max(c, b, slot, red);
+    int k = 0;
+    if (mx > 0.0) frexp(mx, &k);
+    else if (b.begin == 0 && threadIdx.x == 0) atomicOr(&c.flags[slot], c.fp32 ? 2 : 1);
+    const double scale = ldexp(1.0, -k);
+    const double* __restrict__ acc = c.acc + (uint64_t)slot * c.sep_stride + f.sep;
+    T* __restrict__ sepc = static_cast<T*>(c.sepc) + (uint64_t)slot * c.sep_stride + f.sep;
+#pragma unroll 4
+    for (uint32_t m = b.begin + threadIdx.x; m < b.begin + b.count; m += kBlock) sepc[m] = (T)(acc[m] * scale);
+    if (b.begin == 0 && threadIdx.x == 0) c.kexp[(uint64_t)slot * c.kexp_stride + f.edge] = k;
+}
+
+// Entries m < n of a separator whose digit of a variable (stride, card) is x:
+// whole periods of stride * card entries hold stride each.
+__device__ __forceinline__ uint32_t digit_below(uint32_t n, uint32_t stride, uint32_t card, uint32_t x) {
+    const uint32_t span = stride * card;
+    const uint32_t r = n % span;
+    const uint32_t lo = x * stride;
+    return (n / span) * stride + (r > lo ? min(r - lo, stride) : 0u);
+}
+
+template <typename T>
+__global__ __launch_bounds__(kBlock) void k_fin_distribute_a(Ctx c, const DSepFin* __restrict__ fins,
+                                                             const DFinBlk* __restrict__ blks,
+                                                             const int32_t* __restrict__ slots) {
+    __shared__ double red[kWaves];
+    __shared__ double vals[kFinBlock];
+    const DFinBlk b = blks[blockIdx.x];
+    const DSepFin f = fins[b.fin];
+    const int slot = slots[blockIdx.y];
+    double* __restrict__ acc = c.acc + (uint64_t)slot * c.sep_stride + f.sep;
+    const double* __restrict__ part = c.part + (uint64_t)slot * c.part_stride + f.part0;
+    const T* __restrict__ sepc = static_cast<const T*>(c.sepc) + (uint64_t)slot * c.sep_stride + f.sep;
+    double mx = 0.0;
+#pragma unroll 4
+    for (uint32_t m = b.begin + threadIdx.x; m < b.begin + b.count; m += kBlock) {
+        const double v = finish_entry(f, acc, part, m);
+        vals[m - b.begin] = v;
+        const double den = (double)sepc[m];
+        mx = fmax(mx, den == 0.0 ? 0.0 : v / den);
+    }
+    mx = block_max_all(mx, red);  // (its barriers also publish vals)
+    if (threadIdx.x == 0) c.bmax[(uint64_t)slot * c.bmax_stride + b.id] = mx;
+    // this block's share of each posterior sum: the entries with digit x
+    // are m = (o * card + x) * stride + r, enumerated by e = o * stride + r
+    double* __restrict__ bm = c.bmarg + (uint64_t)slot * c.bmarg_stride + b.mbase + (b.id - b.blk0) * b.mw;
+    uint32_t vo = 0;
+    for (uint32_t a = 0; a < f.nmv; a++) {
+        const DMargVar mv = c.mv[f.mv0 + a];
+        for (uint32_t x = 0; x < mv.card; x++) {
+            const uint32_t e0 = digit_below(b.begin, mv.stride, mv.card, x);
+            const uint32_t e1 = digit_below(b.begin + b.count, mv.stride, mv.card, x);
+            double s = 0.0;
+            for (uint32_t e = e0 + threadIdx.x; e < e1; e += kBlock) {
+                const uint32_t o = mdiv(e, mv.smul, mv.ssh);
+                s += vals[(o * mv.card + x) * mv.stride + (e - o * mv.stride) - b.begin];
+            }
+            s = block_sum(s, red);
+            if (threadIdx.x == 0) bm[vo + x] = s;
+        }
+        vo += mv.card;
+    }
+}
+
+template <typename T>
+__global__ __launch_bounds__(kBlock) void k_fin_distribute_b(Ctx c, const DSepFin* __restrict__ fins,
+                                                             const DFinBlk* __restrict__ blks,
+                                                             const int32_t* __restrict__ slots) {
+    __shared__ double red[kWaves];
+    const DFinBlk b = blks[blockIdx.x];
+    const DSepFin f = fins[b.fin];
+    const int slot = slots[blockIdx.y];
+    const double mx = fin_max(c, b, slot, red);
+    int k = 0;
+    if (mx > 0.0) frexp(mx, &k);
+    const double scale = ldexp(1.0, -k);
+    const double* __restrict__ acc = c.acc + (uint64_t)slot * c.sep_stride + f.sep;
+    const T* __restrict__ sepc = static_cast<const T*>(c.sepc) + (uint64_t)slot * c.sep_stride + f.sep;
+    T* __restrict__ sepd = static_cast<T*>(c.sepd) + (uint64_t)slot * c.sep_stride + f.sep;
+#pragma unroll 4
+    for (uint32_t m = b.begin + threadIdx.x; m < b.begin + b.count; m += kBlock) {
+        const double den = (double)sepc[m];
+        sepd[m] = (T)((den == 0.0 ? 0.0 : acc[m] / den) * scale);
+    }
+    if (b.begin != 0) return;
+    const double* __restrict__ bm = c.bmarg + (uint64_t)slot * c.bmarg_stride + b.mbase;
+    double* __restrict__ marg = c.marg + (uint64_t)slot * c.marg_stride;
+    uint32_t vo = 0;
+    for (uint32_t a = 0; a < f.nmv; a++) {
+        const DMargVar mv = c.mv[f.mv0 + a];
+        for (uint32_t x = threadIdx.x; x < mv.card; x += kBlock) {
+            double s = 0.0;
+            for (uint32_t j = 0; j < b.nblk; j++) s += bm[(uint64_t)j * b.mw + vo + x];
+            marg[mv.out + x] = s;
+        }
+        vo += mv.card;
+    }
+}
+
 // Posteriors: normalise each variable's marginal.  log P(e): the log of the
 // product of the roots' sums (one per tree of the forest) plus the
 // rescaling exponents of the priors and of every collect message.
@@ -727,6 +893,25 @@ hipError_t launch_fin_collect(const Ctx& c, int prec, const DSepFin* fins, uint3
     dim3 grid(nbig + (nfins - nbig + kWaves - 1) / kWaves, (unsigned)nslots);
     if (prec) hipLaunchKernelGGL(k_fin_collect<float>, grid, dim3(kBlock), 0, s, c, fins, nfins, nbig, slots);
     else hipLaunchKernelGGL(k_fin_collect<double>, grid, dim3(kBlock), 0, s, c, fins, nfins, nbig, slots);
+    return hipGetLastError();
+}
+
+hipError_t launch_fin_blocks(const Ctx& c, int prec, bool distribute, int phase, const DSepFin* fins,
+                             const DFinBlk* blks, uint32_t nblks, const int32_t* slots, int nslots, hipStream_t s) {
+    if (!nblks || !nslots) return hipSuccess;
+    const dim3 grid(nblks, (unsigned)nslots), block(kBlock);
+    if (!distribute && phase == 0) {
+        hipLaunchKernelGGL(k_fin_collect_a, grid, block, 0, s, c, fins, blks, slots);
+    } else if (!distribute) {
+        if (prec) hipLaunchKernelGGL(k_fin_collect_b<float>, grid, block, 0, s, c, fins, blks, slots);
+        else hipLaunchKernelGGL(k_fin_collect_b<double>, grid, block, 0, s, c, fins, blks, slots);
+    } else if (phase == 0) {
+        if (prec) hipLaunchKernelGGL(k_fin_distribute_a<float>, grid, block, 0, s, c, fins, blks, slots);
+        else hipLaunchKernelGGL(k_fin_distribute_a<double>, grid, block, 0, s, c, fins, blks, slots);
+    } else {
+        if (prec) hipLaunchKernelGGL(k_fin_distribute_b<float>, grid, block, 0, s, c, fins, blks, slots);
+        else hipLaunchKernelGGL(k_fin_distribute_b<double>, grid, block, 0, s, c, fins, blks, slots);
+    }
     return hipGetLastError();
 }
 

@@ -102,6 +102,35 @@ uint32_t enumerate(const std::vector<int>& pos, const std::vector<int>& card_at,
     return start;
 }
 
+bool is_big(const DSepFin& f) { return f.size > kBigSeparator && f.edge >= 0; }
+
+// Partition a layer's finalisers large-first and split each large one into
+// near-equal blocks of at most kFinBlock entries.
+void finish_layer(Plan& p, Layer& ly, std::vector<DSepFin>& fins) {
+    std::stable_partition(fins.begin(), fins.end(), is_big);
+    ly.fin0 = (uint32_t)p.fins.size();
+    ly.nfin = (uint32_t)fins.size();
+    ly.nbig = (uint32_t)std::count_if(fins.begin(), fins.end(), is_big);
+    p.fins.insert(p.fins.end(), fins.begin(), fins.end());
+    ly.fb0 = (uint32_t)p.finblks.size();
+    for (uint32_t f = ly.fin0; f < ly.fin0 + ly.nbig; f++) {
+        const DSepFin F = p.fins[f];
+        const uint32_t nblk = (F.size + kFinBlock - 1) / kFinBlock;
+        uint32_t mw = 0;
+        for (uint32_t k = 0; k < F.nmv; k++) mw += p.margvars[F.mv0 + k].card;
+        const uint32_t blk0 = (uint32_t)p.finblks.size();
+        const uint32_t mbase = p.n_bmarg;
+        if ((uint64_t)p.n_bmarg + (uint64_t)mw * nblk > 0x7fffffffull) throw std::runtime_error("finaliser scratch");
+        p.n_bmarg += mw * nblk;
+        for (uint32_t j = 0; j < nblk; j++) {
+            const uint32_t b = (uint32_t)((uint64_t)j * F.size / nblk);
+            const uint32_t e = (uint32_t)((uint64_t)(j + 1) * F.size / nblk);
+            p.finblks.push_back({f, b, e - b, blk0 + j, blk0, nblk, mbase, mw});
+        }
+    }
+    ly.nfb = (uint32_t)p.finblks.size() - ly.fb0;
+}
+
 }  // namespace
 
 std::string check_plan(const Tree& t, const Plan& p) {
@@ -229,6 +258,30 @@ std::string check_plan(const Tree& t, const Plan& p) {
         if ((uint64_t)tg.sep + sz > p.sep_stride) return "target separator offset";
         if (tg.part0 >= 0 && (uint64_t)tg.part0 + sz * tg.nchunk > p.n_parts) return "target partials";
     }
+    // finaliser blocks: each large fin of a layer covered by its blocks in order
+    for (const std::vector<Layer>* sweep : {&p.collect, &p.distribute})
+        for (const Layer& ly : *sweep) {
+            if (ly.nbig > ly.nfin || (uint64_t)ly.fb0 + ly.nfb > p.finblks.size()) return "layer fin blocks";
+            uint32_t b = ly.fb0;
+            for (uint32_t f = ly.fin0; f < ly.fin0 + ly.nfin; f++) {
+                const DSepFin& F = p.fins[f];
+                if ((f < ly.fin0 + ly.nbig) != is_big(F)) return "large fin partition";
+                if (f >= ly.fin0 + ly.nbig) continue;
+                uint32_t mw = 0;
+                for (uint32_t k = 0; k < F.nmv; k++) mw += p.margvars[F.mv0 + k].card;
+                uint32_t end = 0;
+                const uint32_t blk0 = b;
+                for (; b < ly.fb0 + ly.nfb && p.finblks[b].fin == f; b++) {
+                    const DFinBlk& B = p.finblks[b];
+                    if (B.id != b || B.blk0 != blk0 || B.begin != end || B.count == 0 || B.count > kFinBlock)
+                        return "fin block layout";
+                    if (B.mw != mw || (uint64_t)B.mbase + (uint64_t)B.nblk * mw > p.n_bmarg) return "fin block scratch";
+                    end += B.count;
+                }
+                if (end != F.size || b - blk0 != p.finblks[blk0].nblk) return "fin block cover";
+            }
+            if (b != ly.fb0 + ly.nfb) return "fin block count";
+        }
     for (const DSepFin& F : p.fins) {
         if ((uint64_t)F.sep + F.size > p.sep_stride) return "fin range";
         if (F.nchunk && (uint64_t)F.part0 + (uint64_t)F.size * F.nchunk > p.n_parts) return "fin partials";
@@ -471,12 +524,7 @@ void build_plan(const Tree& t, int tile, uint32_t max_stage, Plan& p) {
             fins.push_back(f);
         }
         ly.ngroup = (uint32_t)p.groups.size() - ly.group0;
-        // large separators first: each gets a workgroup, the rest a wave
-        std::stable_partition(fins.begin(), fins.end(), [](const DSepFin& f) { return f.size > kBigSeparator; });
-        ly.fin0 = (uint32_t)p.fins.size();
-        ly.nfin = (uint32_t)fins.size();
-        ly.nbig = (uint32_t)std::count_if(fins.begin(), fins.end(), [](const DSepFin& f) { return f.size > kBigSeparator; });
-        p.fins.insert(p.fins.end(), fins.begin(), fins.end());
+        finish_layer(p, ly, fins);
     }
 
     // ---- distribute layers (depth): marginalise each clique onto each child
@@ -660,12 +708,7 @@ void build_plan(const Tree& t, int tile, uint32_t max_stage, Plan& p) {
             }
         }
         ly.ngroup = (uint32_t)p.works.size() - ly.group0;
-        // large separators first: each gets a workgroup, the rest a wave
-        std::stable_partition(fins.begin(), fins.end(), [](const DSepFin& f) { return f.size > kBigSeparator; });
-        ly.fin0 = (uint32_t)p.fins.size();
-        ly.nfin = (uint32_t)fins.size();
-        ly.nbig = (uint32_t)std::count_if(fins.begin(), fins.end(), [](const DSepFin& f) { return f.size > kBigSeparator; });
-        p.fins.insert(p.fins.end(), fins.begin(), fins.end());
+        finish_layer(p, ly, fins);
     }
     p.n_parts = parts;
     p.stage = (uint32_t)tile;

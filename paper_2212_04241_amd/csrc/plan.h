@@ -9,10 +9,11 @@ namespace fbn {
 struct Layer {
     uint32_t group0 = 0, ngroup = 0;  // collect: into Plan::groups; distribute: into Plan::works
     uint32_t fin0 = 0, nfin = 0;      // into Plan::fins (separators finalised after it)
-    uint32_t nbig = 0;                // the first nbig fins get a workgroup each, the rest a wave
+    uint32_t nbig = 0;                // the first nbig fins are large: split over Plan::finblks
+    uint32_t fb0 = 0, nfb = 0;        // their blocks, into Plan::finblks
 };
 
-constexpr uint32_t kBigSeparator = 1024;  // entries above which a separator gets a workgroup
+constexpr uint32_t kBigSeparator = 1024;  // entries above which a separator is split into blocks
 
 struct Plan {
     int tile = 2048;
@@ -32,6 +33,8 @@ struct Plan {
     std::vector<DPiece> pieces;
     std::vector<DGroup> groups;
     std::vector<DSepFin> fins;
+    std::vector<DFinBlk> finblks;     // blocks of the large separators, layer by layer
+    uint32_t n_bmarg = 0;             // per slot: partial posterior sums of the blocks
     std::vector<DTarget> targets;     // distribute marginalisations
     std::vector<DWork> works;         // distribute workgroups
     std::vector<DWTarget> wtargets;   // targets of packed distribute workgroups

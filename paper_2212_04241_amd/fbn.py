@@ -297,9 +297,14 @@ def query_all(jt: JT, slots, marg_total: int):
 def fetch_async(jt: JT, slots, post_out, log_pe_out, flags_out) -> None:
     """Enqueue result copies into caller-owned (ideally pinned) host arrays."""
     sl, psl = _i32(slots)
-    _check(lib().fbn_fetch_async(jt._h, sl.size, psl, C.c_void_p(post_out.ctypes.data) if post_out is not None else None,
-                                 C.c_void_p(log_pe_out.ctypes.data) if log_pe_out is not None else None,
-                                 C.c_void_p(flags_out.ctypes.data) if flags_out is not None else None),
+    P = C.POINTER
+    for a, dt in ((post_out, np.float64), (log_pe_out, np.float64), (flags_out, np.int32)):
+        if a is not None and (a.dtype != dt or not a.flags.c_contiguous or a.shape[0] < sl.size):
+            raise ValueError("fetch_async: output arrays must be C-contiguous float64/float64/int32 with a row per slot")
+    _check(lib().fbn_fetch_async(jt._h, sl.size, psl,
+                                 post_out.ctypes.data_as(P(C.c_double)) if post_out is not None else None,
+                                 log_pe_out.ctypes.data_as(P(C.c_double)) if log_pe_out is not None else None,
+                                 flags_out.ctypes.data_as(P(C.c_int32)) if flags_out is not None else None),
            "fbn_fetch_async")
 
 
