@@ -31,10 +31,69 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0   # MI355X HBM3E, published
+PROFILES = os.path.join(ROOT, "profiles")
+# the sources a kernel's byte counters depend on: counters taken before a
+# change to any of them no longer describe the kernel
+KERNEL_SOURCES = ["paper_2212_04241_amd/csrc/kernels.hip", "paper_2212_04241_amd/csrc/kernels.h",
+                  "paper_2212_04241_amd/csrc/plan.cpp", "paper_2212_04241_amd/csrc/plan.h",
+                  "paper_2212_04241_amd/csrc/fbn_internal.h"]
 
 
 def log(*a):
     print(*a, file=sys.stderr, flush=True)
+
+
+def sources_sha256():
+    import hashlib
+    h = hashlib.sha256()
+    for f in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()
+
+
+# kernel behind each timed launch kind
+KIND_KERNEL = {"collect": "k_collect", "collect_finalise": "k_fin_collect", "distribute": "k_dist_gather",
+               "distribute_finalise": "k_fin_distribute", "posteriors": "k_marginals"}
+
+
+def counted_traffic(workload, kind):
+    """HBM bytes per launch of the dominant kernel from the committed
+    FETCH_SIZE / WRITE_SIZE summary (copy-scaled), or None when there is no
+    summary for this workload and kernel or the kernel sources changed since
+    the counters were taken."""
+    path = os.path.join(PROFILES, f"{KIND_KERNEL[kind]}_{workload}_counters.txt")
+    if not os.path.exists(path):
+        return None
+    kv = {}
+    with open(path) as f:
+        for line in f:
+            if ":" in line and not line.startswith("#"):
+                k, v = line.split(":", 1)
+                kv[k.strip()] = v.strip()
+    if kv.get("source_sha256") != sources_sha256():
+        return None
+    try:
+        return float(kv["traffic_bytes_per_launch"])
+    except (KeyError, ValueError):
+        return None
+
+
+def roofline_of(prof, workload, note=None):
+    """Roofline object for the kernel kind with the most time in `prof`
+    (kind -> (ms, launches, algorithmic bytes)), measured by HIP events."""
+    kind = max(prof, key=lambda k: prof[k][0])
+    ms, launches, byts = prof[kind]
+    achieved = byts / (ms * 1e-3) / 1e9 if ms > 0 else 0.0
+    r = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+         "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": counted_traffic(workload, kind),
+         "kernel": f"{KIND_KERNEL[kind]}<float>", "launches": launches,
+         "avg_launch_us": round(1e3 * ms / max(launches, 1), 3),
+         "bytes_per_launch": byts / max(launches, 1),
+         "traffic_unit": "HBM bytes per launch (FETCH_SIZE + WRITE_SIZE, copy-scaled)"}
+    if note:
+        r["measured_on"] = note
+    return r
 
 
 class Workload:
@@ -286,14 +345,8 @@ def bench_served(args, fbn):
     fallbacks = int(np.count_nonzero(sat.precision == fbn.FBN_FP64))
     srv.close()
 
-    kind = max(prof, key=lambda k: prof[k][0])
-    ms, launches, byts = prof[kind]
-    achieved = byts / (ms * 1e-3) / 1e9 if ms > 0 else 0.0
-    roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None, "kernel": f"k_{kind}<float>",
-                "launches": launches, "avg_launch_us": round(1e3 * ms / max(launches, 1), 3),
-                "bytes_per_launch": byts / max(launches, 1),
-                "measured_on": "one full batch per resident tree, eager launches, HIP events"}
+    roofline = roofline_of({k: tuple(v) for k, v in prof.items()}, "C5",
+                           "one full batch per resident tree, eager launches, HIP events")
 
     def lat(r):
         return {"queries_per_s": round(r.qps, 1), "p50_ms": round(1e3 * r.percentile(50), 3),
@@ -318,7 +371,9 @@ def bench_served(args, fbn):
                    "step": "one closed-loop replay of the trace"},
         "roofline": roofline,
         "paths": {
-            "served_fp32_closed_loop": lat(sat) | {"batches": sat.batches, "fp64_fallbacks": fallbacks},
+            "served_fp32_closed_loop": lat(sat) | {"batches": sat.batches, "fp64_fallbacks": fallbacks,
+                                                   "kernel_ms_one_batch_per_tree":
+                                                       {k: round(v[0], 3) for k, v in prof.items()}},
             "plain_fp64_closed_loop": lat(plain_sat),
             "open_loop_at_0.8x_plain": {"rate_per_s": round(lam2, 1), "served": lat(srv_2), "plain": lat(plain_2)},
             "open_loop_at_0.8x_served": {"rate_per_s": round(lam3, 1), "served": lat(srv_3),
@@ -416,10 +471,13 @@ def main():
             dst.copy_(src)
         torch.cuda.synchronize()
         log("[bench] copy calibration: 3 x 512 MiB device copies")
+    roofline = roofline_of(prof32, key)
     if args.fp32_only:
         # profiling runs: the headline path alone
         print(json.dumps({"value": round(qps32, 1), "unit": "queries/s", "ms_per_step": 1e3 * dt32 / args.steps,
-                          "kernel_ms_per_step": {k: v[0] / args.steps for k, v in prof32.items()}}), flush=True)
+                          "roofline": roofline,
+                          "kernel_ms_per_step": {k: v[0] / args.steps for k, v in prof32.items()},
+                          "kernel_launches": {k: v[1] for k, v in prof32.items()}}), flush=True)
         return
     # FP64 batched
     steps64 = max(1, args.steps // 2)
@@ -435,16 +493,7 @@ def main():
     qps_io = time_with_host_io(fbn, W, fbn.FBN_FP32_RESCALED, max(1, args.steps // 4))
     log(f"[bench] fp32 batched with host i/o: {qps_io:.1f} q/s")
 
-    # roofline of the dominant kernel over the timed region
-    kind = max(prof32, key=lambda k: prof32[k][0])
-    ms, launches, byts = prof32[kind]
-    achieved = byts / (ms * 1e-3) / 1e9 if ms > 0 else 0.0
     kern_total_ms = sum(v[0] for v in prof32.values())
-    roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
-                "kernel": f"k_{kind}<float>", "launches": launches,
-                "avg_launch_us": round(1e3 * ms / max(launches, 1), 3),
-                "bytes_per_launch": byts / max(launches, 1)}
 
     T = stats["T"]
     out = {
