@@ -439,8 +439,8 @@ def main():
     args = ap.parse_args()
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
-        print(json.dumps({"error": "this benchmark runs on exactly one GPU; multi-GPU sharding is "
-                                   "described in the design notes but not built", "n_gpus": args.gpus}))
+        print(json.dumps({"error": "this benchmark runs on exactly one GPU; sharding the path across "
+                                   "GPUs is not built", "n_gpus": args.gpus}))
         sys.exit(2)
 
     from paper_2212_04241_amd import fbn

@@ -16,7 +16,7 @@
  *     reduction (entering evidence), marginalisation onto a separator and
  *     extension by the new/old separator ratio.
  * The paper gives no formulas; every step below follows the textbook
- * construction, with the tie-breaks listed in the design notes:
+ * construction, with these fixed tie-breaks:
  *   moralise -> min-fill elimination (key: fill, table weight, id)
  *   -> maximal elimination cliques (id = elimination rank)
  *   -> Kruskal maximum-weight spanning tree over all clique pairs

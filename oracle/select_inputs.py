@@ -7,7 +7,8 @@ Acceptance rules (clique sizes are min-fill elimination cliques, in entries):
   C2  largest clique in [1e4, 1e6] (the stated range); first attempt.
   C3  largest clique in [5e6, 2e7]; up to 1000 attempts with cardinalities
       uniform on {2..63}, then attempts with P(r) proportional to 1/r.
-  C4, C5  largest clique <= 4e6.  A few attempts by rejection, then a
+  C4, C5  largest clique <= 32768 (C4: the batch of small networks) and
+      <= 4e6 (C5).  A few attempts by rejection, then a
       deterministic repair of attempt 0: while min-fill meets a clique above
       the cap, drop the DAG arc u->v inside that clique with the largest
       (position of v, position of u) -- or, if the clique holds no arc, the

@@ -29,10 +29,11 @@ def hipcc() -> str:
 def flags(src: str) -> list:
     f = ["-O3", "-std=c++17", "-fPIC", "-Wall", f"--offload-arch={ARCH}",
          "-I", os.path.join(ROOT, "include"), "-I", CSRC,
-         # packed fp32 instructions stay off (see the design notes)
+         # packed fp32 instructions stay off: some of their forms have given
+         # wrong results on this hardware without any error
          "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops"]
     if src.endswith(".hip"):
-        f += ["-x", "hip", "-munsafe-fp-atomics"]
+        f += ["-x", "hip"]
     return f
 
 
