@@ -52,17 +52,19 @@ def sources_sha256():
     return h.hexdigest()
 
 
-# kernel behind each timed launch kind
+# kernel behind each timed launch kind, per-slot and slot-interleaved layouts
 KIND_KERNEL = {"collect": "k_collect", "collect_finalise": "k_fin_collect", "distribute": "k_dist_gather",
                "distribute_finalise": "k_fin_distribute", "posteriors": "k_marginals"}
+KIND_KERNEL_IL = {"collect": "k_collect_i", "collect_finalise": "k_fin_collect_i", "distribute": "k_dist_i",
+                  "distribute_finalise": "k_fin_distribute_i", "posteriors": "k_marginals_i"}
 
 
-def counted_traffic(workload, kind):
+def counted_traffic(workload, kernel):
     """HBM bytes per launch of the dominant kernel from the committed
     FETCH_SIZE / WRITE_SIZE summary (copy-scaled), or None when there is no
     summary for this workload and kernel or the kernel sources changed since
     the counters were taken."""
-    path = os.path.join(PROFILES, f"{KIND_KERNEL[kind]}_{workload}_counters.txt")
+    path = os.path.join(PROFILES, f"{kernel}_{workload}_counters.txt")
     if not os.path.exists(path):
         return None
     kv = {}
@@ -79,15 +81,16 @@ def counted_traffic(workload, kind):
         return None
 
 
-def roofline_of(prof, workload, note=None):
+def roofline_of(prof, workload, note=None, interleaved=False):
     """Roofline object for the kernel kind with the most time in `prof`
     (kind -> (ms, launches, algorithmic bytes)), measured by HIP events."""
     kind = max(prof, key=lambda k: prof[k][0])
     ms, launches, byts = prof[kind]
     achieved = byts / (ms * 1e-3) / 1e9 if ms > 0 else 0.0
+    kernel = (KIND_KERNEL_IL if interleaved else KIND_KERNEL)[kind]
     r = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-         "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": counted_traffic(workload, kind),
-         "kernel": f"{KIND_KERNEL[kind]}<float>", "launches": launches,
+         "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": counted_traffic(workload, kernel),
+         "kernel": f"{kernel}<float>", "launches": launches,
          "avg_launch_us": round(1e3 * ms / max(launches, 1), 3),
          "bytes_per_launch": byts / max(launches, 1),
          "traffic_unit": "HBM bytes per launch (FETCH_SIZE + WRITE_SIZE, copy-scaled)"}
@@ -148,10 +151,10 @@ def workload_config(key, W, jt_stats, n_slots):
     }
 
 
-def time_batched(fbn, W, precision, steps, warmup, profile):
+def time_batched(fbn, W, precision, steps, warmup, profile, layout=0, tile=0):
     cases = W.slot_cases
     n = len(cases)
-    jt = fbn.JT(W.handles(fbn), precision=precision, max_slots=n)
+    jt = fbn.JT(W.handles(fbn), precision=precision, max_slots=n, layout=layout, tile_entries=tile)
     slots = list(range(n))
     fbn.set_evidence_batch(jt, slots, cases)
     for _ in range(warmup):
@@ -201,11 +204,11 @@ def time_plain(fbn, W, n_queries, graph=True):
     return len(lat) / dt, np.array(lat), res
 
 
-def time_with_host_io(fbn, W, precision, steps):
+def time_with_host_io(fbn, W, precision, steps, layout=0, tile=0):
     """Same batch, counting evidence upload and posterior download (PCIe)."""
     cases = W.slot_cases
     n = len(cases)
-    jt = fbn.JT(W.handles(fbn), precision=precision, max_slots=n)
+    jt = fbn.JT(W.handles(fbn), precision=precision, max_slots=n, layout=layout, tile_entries=tile)
     slots = list(range(n))
     marg = W.marg
     fbn.set_evidence_batch(jt, slots, cases)
@@ -433,6 +436,10 @@ def main():
     ap.add_argument("--fp32-only", action="store_true", help="time only the FP32 batched path (for profiling)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run plain 512 MiB device copies (reference for byte counters)")
+    ap.add_argument("--layout", type=int, default=0, help="table layout: 0 auto, 1 per slot, 2 interleaved")
+    ap.add_argument("--tile", type=int, default=0, help="table entries per work item (0: the library default)")
+    ap.add_argument("--no-tune", action="store_true",
+                    help="skip the autotuner (layout and tile from --layout / --tile)")
     ap.add_argument("--trace", type=int, default=4096, help="C5: trace queries")
     ap.add_argument("--budget-gb", type=float, default=32.0, help="C5: device-memory budget, GiB")
     ap.add_argument("--max-batch", type=int, default=32, help="C5: slots per resident tree at most")
@@ -454,9 +461,20 @@ def main():
     log(f"[bench] {key}: {len(W.nets)} network(s), {sum(x.n for x in W.nets)} variables, {n} slots, "
         f"{q} queries per step")
 
+    # layout and tile: the autotuner's measured choice for this batch (before
+    # the timed region), unless fixed on the command line
+    tuned = None
+    if not args.no_tune and not args.layout and not args.tile:
+        from paper_2212_04241_amd import tune
+        nets = W.nets if len(W.nets) > 1 else W.nets[0]
+        t0 = time.perf_counter()
+        tuned = tune.tune(nets, W.slot_cases, fbn.FBN_FP32_RESCALED)
+        args.layout, args.tile = tuned["layout"], tuned["tile"]
+        log(f"[bench] tuned in {time.perf_counter() - t0:.1f} s: layout {args.layout}, tile {args.tile} "
+            f"({tuned['ms']:.3f} ms per calibration)")
     # FP32 batched (the headline path), kernel timing by HIP events
     jt32, dt32, prof32, post32, lp32, st32 = time_batched(fbn, W, fbn.FBN_FP32_RESCALED,
-                                                          args.steps, args.warmup, True)
+                                                          args.steps, args.warmup, True, args.layout, args.tile)
     stats = jt32.stats
     qps32 = q * args.steps / dt32
     log(f"[bench] fp32 batched: {qps32:.1f} q/s, {1e3 * dt32 / args.steps:.3f} ms/step")
@@ -471,7 +489,7 @@ def main():
             dst.copy_(src)
         torch.cuda.synchronize()
         log("[bench] copy calibration: 3 x 512 MiB device copies")
-    roofline = roofline_of(prof32, key)
+    roofline = roofline_of(prof32, key, interleaved=bool(stats["interleaved"]))
     if args.fp32_only:
         # profiling runs: the headline path alone
         print(json.dumps({"value": round(qps32, 1), "unit": "queries/s", "ms_per_step": 1e3 * dt32 / args.steps,
@@ -481,7 +499,8 @@ def main():
         return
     # FP64 batched
     steps64 = max(1, args.steps // 2)
-    jt64, dt64, _, post64, lp64, st64 = time_batched(fbn, W, fbn.FBN_FP64, steps64, 1, False)
+    jt64, dt64, _, post64, lp64, st64 = time_batched(fbn, W, fbn.FBN_FP64, steps64, 1, False, args.layout,
+                                                     args.tile)
     qps64b = q * steps64 / dt64
     jt64.free()
     log(f"[bench] fp64 batched: {qps64b:.1f} q/s")
@@ -490,7 +509,7 @@ def main():
     log(f"[bench] fp64 plain (graph replay): {qps_plain:.1f} q/s, p50 {1e3 * np.median(lat):.3f} ms")
     qps_plain_eager, lat_e, _ = time_plain(fbn, W, args.plain_queries, graph=False)
     log(f"[bench] fp64 plain (eager launches): {qps_plain_eager:.1f} q/s")
-    qps_io = time_with_host_io(fbn, W, fbn.FBN_FP32_RESCALED, max(1, args.steps // 4))
+    qps_io = time_with_host_io(fbn, W, fbn.FBN_FP32_RESCALED, max(1, args.steps // 4), args.layout, args.tile)
     log(f"[bench] fp32 batched with host i/o: {qps_io:.1f} q/s")
 
     kern_total_ms = sum(v[0] for v in prof32.values())
@@ -509,7 +528,9 @@ def main():
         "vs_baseline": None,
         "dtype": "f32",
         "data": "synthetic",
-        "config": workload_config(key, W, stats, n),
+        "config": workload_config(key, W, stats, n) | {
+            "layout": "interleaved" if stats["interleaved"] else "per-slot", "tile": args.tile,
+            "tuner_trials_ms": tuned["trials"] if tuned else None},
         "roofline": roofline,
         "paths": {
             "fp32_batched": {"queries_per_s": round(qps32, 1),

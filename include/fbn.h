@@ -64,6 +64,15 @@ enum {
 
 enum { FBN_FP64 = 0, FBN_FP32_RESCALED = 1 };
 
+/* Device layout of the per-slot tables.  PER_SLOT keeps each slot's tables
+ * contiguous and spreads one slot's table entries over the lanes of a wave:
+ * long sums run across lanes.  INTERLEAVED stores entry x of slot s at
+ * x * max_slots + s and gives each lane one slot, with every index
+ * computation shared by the wave: gathers onto large separators are cheaper,
+ * but every long sum runs within one lane.  AUTO is PER_SLOT; the Python
+ * autotuner measures both.  Results are the same to rounding. */
+enum { FBN_LAYOUT_AUTO = 0, FBN_LAYOUT_PER_SLOT = 1, FBN_LAYOUT_INTERLEAVED = 2 };
+
 /* Device memory comes from the caller when alloc is set (e.g. PyTorch's
  * caching allocator); otherwise hipMalloc / hipFree are used. */
 typedef struct {
@@ -80,6 +89,8 @@ typedef struct {
     int32_t tile_entries;         /* table entries per workgroup; 0 = default */
     fbn_allocator allocator;
     void* stream;                 /* hipStream_t                              */
+    int32_t layout;               /* FBN_LAYOUT_*                             */
+    int32_t reserved;
 } fbn_jt_options;
 
 typedef struct {
@@ -91,7 +102,7 @@ typedef struct {
     uint64_t device_bytes; /* device memory held by the jt (host_only: the bytes a */
     uint64_t slot_bytes;   /* device build would hold); of which per evidence slot */
     int32_t n_trees;       /* networks (roots) in the jt: 1 unless built as a forest */
-    int32_t reserved;
+    int32_t interleaved;   /* 1 when the jt uses FBN_LAYOUT_INTERLEAVED              */
 } fbn_jt_stats_t;
 
 /* Fill opt with defaults: FP64, 1 slot, 2^31-1 max entries, device build. */

@@ -453,6 +453,7 @@ fbn_status setup_device(fbn_jt* jt) {
     c.kappa_total = p.kappa_total;
     c.sep_total = p.sep_total;
     c.nroots = p.n_roots;
+    c.S = p.interleaved ? (uint32_t)S : 0u;
     c.fp32 = f32 ? 1 : 0;
     c.tile = p.stage;
     HIP_OK(hipStreamSynchronize(jt->stream));
@@ -648,7 +649,8 @@ static fbn_status build_jt_impl(const std::vector<const fbn_net*>& nets, const f
     if (opt_in) opt = *opt_in;
     else fbn_default_options(&opt);
     if (opt.max_slots < 1 || (opt.precision != FBN_FP64 && opt.precision != FBN_FP32_RESCALED) ||
-        opt.tile_entries < 0 || opt.tile_entries > kTileMax)
+        opt.tile_entries < 0 || opt.tile_entries > kTileMax || opt.layout < FBN_LAYOUT_AUTO ||
+        opt.layout > FBN_LAYOUT_INTERLEAVED)
         return fail(FBN_E_INVALID_ARG, "bad options");
     if (opt.max_clique_entries == 0 || opt.max_clique_entries > 0x7fffffffull) opt.max_clique_entries = 0x7fffffffull;
     fbn_jt* jt = nullptr;
@@ -681,9 +683,11 @@ static fbn_status build_jt_impl(const std::vector<const fbn_net*>& nets, const f
             jt->tree = merge_forest(parts);
         }
         // default tile: 8 KB of table per slot, so four slots share a workgroup
-        const int def_tile = opt.precision == FBN_FP32_RESCALED ? 1024 : 512;
+        // interleaved: one wave per work item, 128 entries each by default
+        const bool il = opt.layout == FBN_LAYOUT_INTERLEAVED;
+        const int def_tile = il ? 128 : (opt.precision == FBN_FP32_RESCALED ? 1024 : 512);
         const uint32_t max_stage = (uint32_t)kStageBytes / (opt.precision == FBN_FP32_RESCALED ? 4u : 8u);
-        build_plan(jt->tree, opt.tile_entries ? opt.tile_entries : def_tile, max_stage, jt->plan);
+        build_plan(jt->tree, opt.tile_entries ? opt.tile_entries : def_tile, max_stage, jt->plan, il);
         const std::string bad = check_plan(jt->tree, jt->plan);
         if (!bad.empty()) {
             delete jt;
@@ -870,6 +874,63 @@ fbn_status fbn_calibrate(fbn_jt* jt, int32_t n, const int32_t* slots, double* lo
 // The launch sequence of one calibration of the n slots staged in d_slots:
 // collect layers leaves to root, then distribute layers root to leaves, then
 // the posteriors.
+// The same sequence on slot-interleaved tables.  wn = table bytes per entry
+// times the batch size, for the profiling byte counts.
+static fbn_status enqueue_interleaved(fbn_jt* jt, int32_t n, double wn) {
+    const Ctx& c = jt->ctx;
+    const Plan& p = jt->plan;
+    const int prec = jt->opt.precision == FBN_FP32_RESCALED ? 1 : 0;
+    hipStream_t s = jt->stream;
+    const int32_t* sl = jt->d_slots;
+    fbn_status st;
+    HIP_OK(launch_begin(c, sl, n, s));
+    // the large separators' running maxima start at zero
+    if (!p.finblks.empty()) HIP_OK(launch_zero(jt->d_bmax, 8ull * c.bmax_stride * (uint64_t)jt->opt.max_slots, s));
+    auto fins = [&](const Layer& ly, bool dist, int kind, double bytes) -> fbn_status {
+        fbn_status r;
+        if (ly.nfin > ly.nbig) {
+            if ((r = timed(jt, kind, bytes, [&] {
+                     return launch_interleaved(c, prec, dist ? kIlFinDistribute : kIlFinCollect,
+                                               jt->d_fins + ly.fin0 + ly.nbig, ly.nfin - ly.nbig, jt->d_fins, sl, n, s);
+                 })))
+                return r;
+            bytes = 0.0;
+        }
+        if (ly.nfb) {
+            const int ka = dist ? kIlFinDistributeA : kIlFinCollectA, kb = dist ? kIlFinDistributeB : kIlFinCollectB;
+            if ((r = timed(jt, kind, bytes, [&] {
+                     return launch_interleaved(c, prec, ka, jt->d_finblks + ly.fb0, ly.nfb, jt->d_fins, sl, n, s);
+                 })))
+                return r;
+            if ((r = timed(jt, kind, 0.0, [&] {
+                     return launch_interleaved(c, prec, kb, jt->d_finblks + ly.fb0, ly.nfb, jt->d_fins, sl, n, s);
+                 })))
+                return r;
+        }
+        return FBN_OK;
+    };
+    for (size_t h = 0; h < p.collect.size(); h++) {
+        const Layer& ly = p.collect[h];
+        if ((st = timed(jt, 0, 2.0 * wn * (double)jt->coll_entries[h], [&] {
+                 return launch_interleaved(c, prec, kIlCollect, jt->d_groups + ly.group0, ly.ngroup, jt->d_fins, sl,
+                                           n, s);
+             })))
+            return st;
+        if ((st = fins(ly, false, 1, 2.0 * wn * (double)jt->coll_sep[h]))) return st;
+    }
+    for (size_t d = 0; d < p.distribute.size(); d++) {
+        const Layer& ly = p.distribute[d];
+        if ((st = timed(jt, 2, wn * (double)jt->dist_entries[d], [&] {
+                 return launch_interleaved(c, prec, kIlDistribute, jt->d_works + ly.group0, ly.ngroup, jt->d_fins, sl,
+                                           n, s);
+             })))
+            return st;
+        if ((st = fins(ly, true, 3, 2.0 * wn * (double)jt->dist_sep[d]))) return st;
+    }
+    return timed(jt, 4, 16.0 * (wn / (prec ? 4.0 : 8.0)) * (double)c.marg_stride,
+                 [&] { return launch_marginals_interleaved(c, sl, n, s); });
+}
+
 static fbn_status enqueue_calibration(fbn_jt* jt, int32_t n) {
     fbn_status st = FBN_OK;
     const Ctx& c = jt->ctx;
@@ -879,6 +940,7 @@ static fbn_status enqueue_calibration(fbn_jt* jt, int32_t n) {
     // clear the per-slot flags of this batch
     HIP_OK(launch_begin(c, jt->d_slots, n, s));
     const double w = prec ? 4.0 : 8.0, nb = (double)n;
+    if (p.interleaved) return enqueue_interleaved(jt, n, w * nb);
     // a layer's finalisers: small separators one wave each, large ones in
     // blocks over two launches; the layer's bytes are booked on its first
     auto finalise = [&](const Layer& ly, bool dist, int kind, double bytes) -> fbn_status {
@@ -1005,6 +1067,7 @@ fbn_status fbn_jt_stats(const fbn_jt* jt, fbn_jt_stats_t* out) {
     out->n_edges = t.ne;
     out->root = t.root;
     out->n_trees = (int32_t)t.roots.size();
+    out->interleaved = jt->plan.interleaved ? 1 : 0;
     for (int c = 0; c < t.nc; c++) {
         out->H = std::max(out->H, t.height[(size_t)c]);
         out->D = std::max(out->D, t.depth[(size_t)c]);

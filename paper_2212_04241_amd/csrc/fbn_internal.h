@@ -138,7 +138,8 @@ struct DMargVar {
     uint32_t stride;     // stride of the variable in the separator layout
     uint32_t card;
     uint32_t smul, ssh;  // division by stride
-    uint32_t pad[3];
+    uint32_t cmul, csh;  // division by card
+    uint32_t pad;
 };
 
 // Distribute-sweep marginalisation of clique C onto a target separator S
@@ -191,5 +192,6 @@ constexpr int kBlock = 256;       // threads per workgroup
 constexpr int kTileMax = 4096;    // entries per workgroup tile
 constexpr int kMaxPieces = 32;    // runs (and packed targets) per workgroup
 constexpr uint32_t kFinBlock = 4096;  // separator entries per finaliser block at most
+constexpr uint32_t kFinBlockInterleaved = 256;  // the same with slot-interleaved tables
 
 }  // namespace fbn

@@ -37,6 +37,7 @@ struct Ctx {
     uint32_t sep_stride, part_stride, kexp_stride, marg_stride, ev_stride, bmax_stride, bmarg_stride;
     int32_t nvars, ne, kappa_total, fp32;
     uint32_t sep_total, nroots;  // the roots' one-entry separators follow sep_total
+    uint32_t S;            // slot-interleaved layout: entry x of slot s at x * S + s (0: per-slot layout)
     uint32_t tile;         // LDS entries reserved per slot in a workgroup
 };
 
@@ -69,5 +70,16 @@ hipError_t launch_begin(const Ctx& c, const int32_t* slots, int nslots, hipStrea
 hipError_t launch_expand_map(const uint32_t* map, uint32_t mh, uint32_t ml, uint32_t L, uint32_t Lmul,
                              uint32_t Lsh, uint32_t n, int32_t* out, hipStream_t s);
 hipError_t launch_zero(void* p, size_t bytes, hipStream_t s);
+
+// Slot-interleaved layout (kernels_interleaved.hip): one wave per work item,
+// lanes over the batch.  `items` is the layer's DGroup / DWork / DSepFin /
+// DFinBlk array by kind; `fins` is the whole finaliser array (block kinds).
+enum : int {
+    kIlCollect, kIlDistribute, kIlFinCollect, kIlFinDistribute,
+    kIlFinCollectA, kIlFinCollectB, kIlFinDistributeA, kIlFinDistributeB
+};
+hipError_t launch_interleaved(const Ctx& c, int prec, int kind, const void* items, uint32_t nitems,
+                              const DSepFin* fins, const int32_t* slots, int nslots, hipStream_t s);
+hipError_t launch_marginals_interleaved(const Ctx& c, const int32_t* slots, int nslots, hipStream_t s);
 
 }  // namespace fbn

@@ -1,0 +1,583 @@
+// Layer kernels for slot-interleaved tables (gfx950, wave64).
+//
+// Same operations as kernels.hip -- reduction, extension and
+// marginalisation over the layers of the tree (the paper, Section 2) -- for
+// trees that run large batches of evidence slots.  Every per-slot array is
+// stored entry-major with the slots interleaved: entry x of slot s lives at
+// x * S + s, S being the tree's slot capacity.  A wave takes one work item
+// (a collect tile, a block of one distribute target, a separator or a
+// finaliser block) for 64 batch positions, one per lane:
+//   * everything that depends only on the table entry -- index maps, packed
+//     digits, prior values, loop bounds -- is the same for the whole wave and
+//     is computed once, in scalar registers;
+//   * each lane does only its own slot's arithmetic, and every table load or
+//     store of the wave touches one contiguous run of slots;
+//   * every sum runs in a fixed order within its lane, so a slot's result
+//     does not depend on which other slots share the launch (no atomics on
+//     data, no cross-lane reductions).
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+
+#include "kernels.h"
+
+namespace fbn {
+namespace {
+
+constexpr int kLanes = 64;
+constexpr int kWavesPerBlock = kBlock / kLanes;
+constexpr uint32_t kUnroll = 8;  // entries whose loads are issued together
+
+__device__ __forceinline__ uint32_t mdiv_i(uint32_t n, uint32_t mul, uint32_t sh) {
+    return (uint32_t)(((uint64_t)__umulhi(n, mul) + n) >> sh);
+}
+
+// Wave-uniform value in a scalar register.
+__device__ __forceinline__ uint32_t uniform(uint32_t x) { return __builtin_amdgcn_readfirstlane(x); }
+
+// The wave's work item (blockIdx.x * waves + wave) and the lane's slot.
+__device__ __forceinline__ uint32_t wave_item() {
+    return uniform(blockIdx.x * kWavesPerBlock + threadIdx.x / kLanes);
+}
+__device__ __forceinline__ int lane_slot(const int32_t* slots, int nslots) {
+    const int b = (int)blockIdx.y * kLanes + (int)(threadIdx.x & (kLanes - 1));
+    return b < nslots ? slots[b] : -1;
+}
+
+// Broadcast lane u's value of v (u uniform) to the whole wave.
+__device__ __forceinline__ uint32_t bcast(uint32_t v, uint32_t u) {
+    return (uint32_t)__builtin_amdgcn_readlane((int)v, (int)u);
+}
+__device__ __forceinline__ uint64_t bcast(uint64_t v, uint32_t u) {
+    return ((uint64_t)bcast((uint32_t)(v >> 32), u) << 32) | bcast((uint32_t)v, u);
+}
+__device__ __forceinline__ float bcast(float v, uint32_t u) { return __uint_as_float(bcast(__float_as_uint(v), u)); }
+__device__ __forceinline__ double bcast(double v, uint32_t u) {
+    return __longlong_as_double((long long)bcast((uint64_t)__double_as_longlong(v), u));
+}
+
+constexpr int kKids = 6;  // child indices held per lane; more children are read per entry
+
+// ------------------------------------------------------------------ collect
+
+// psi[i] = prior[i] * [evidence agrees at i] * prod_children sepc[map(i)],
+// stored; contiguous parent-separator segments summed in float64.  The
+// entries are taken 64 at a time: lane j first works out entry j's digits,
+// prior value and child separator indices (one coalesced read of each
+// table), then the wave walks the 64 entries in order with those values
+// broadcast from lane j, each lane applying them to its own slot.
+template <typename T>
+__global__ __launch_bounds__(kBlock) void k_collect_i(Ctx c, const DGroup* __restrict__ groups, uint32_t ngroups,
+                                                      const int32_t* __restrict__ slots, int nslots) {
+    const uint32_t gi = wave_item();
+    if (gi >= ngroups) return;
+    const uint32_t lane = threadIdx.x & (kLanes - 1);
+    const int sl = lane_slot(slots, nslots);
+    const bool act = sl >= 0;                  // lanes past the batch still help with metadata
+    const uint64_t S = c.S;
+    const uint64_t s = act ? (uint64_t)sl : 0;
+    const DGroup g = groups[gi];
+    const T* __restrict__ prior = static_cast<const T*>(c.prior);
+    const T* __restrict__ sepc = static_cast<const T*>(c.sepc);
+    T* __restrict__ psi = static_cast<T*>(c.psi);
+    const uint32_t* __restrict__ map = c.map;
+    double part = 0.0;  // a partial group's single chunk sum
+    for (uint32_t p = 0; p < g.npiece; p++) {
+        const DPiece pc = c.pc[g.piece0 + p];
+        const DClique q = c.cl[pc.clique];
+        const DEvidence ev = c.ev[s * c.ev_stride + pc.clique];
+        const uint32_t nch = q.nchild;
+        const uint32_t end = pc.begin + pc.count;
+        uint32_t seg_left = q.seg - pc.begin % q.seg;
+        uint32_t out = q.psep + pc.begin / q.seg;
+        double acc = 0.0;
+        for (uint32_t i0 = pc.begin; i0 < end; i0 += kLanes) {
+            const uint32_t cnt = min((uint32_t)kLanes, end - i0);
+            // lane j: entry i0 + j
+            const uint32_t ej = i0 + min(lane, cnt - 1);
+            const uint32_t rj = mdiv_i(ej, q.Lmul, q.Lsh);
+            const uint32_t lj = ej - rj * q.L;
+            const uint64_t dj = c.dig[q.hdig + rj] | c.dig[q.ldig + lj];
+            const T pj = prior[q.off + ej];
+            uint32_t xj[kKids];
+#pragma unroll
+            for (int k = 0; k < kKids; k++) {
+                xj[k] = 0;
+                if (k < (int)nch) {
+                    const DChild ch = c.ch[q.child0 + k];
+                    xj[k] = ch.sep + map[ch.mh + rj] + map[ch.ml + lj];
+                }
+            }
+            for (uint32_t u0 = 0; u0 < cnt; u0 += kUnroll) {
+                T v[kUnroll];
+#pragma unroll
+                for (uint32_t x = 0; x < kUnroll; x++) {
+                    const uint32_t u = min(u0 + x, cnt - 1);
+                    const uint64_t d = bcast(dj, u);
+                    v[x] = ((d ^ ev.want) & ev.mask) ? T(0) : bcast(pj, u);
+#pragma unroll
+                    for (int k = 0; k < kKids; k++)
+                        if (k < (int)nch) v[x] *= sepc[(uint64_t)bcast(xj[k], u) * S + s];
+                }
+                for (uint32_t k = kKids; k < nch; k++) {
+                    const DChild ch = c.ch[q.child0 + k];
+#pragma unroll
+                    for (uint32_t x = 0; x < kUnroll; x++) {
+                        const uint32_t u = min(u0 + x, cnt - 1);
+                        const uint32_t idx = ch.sep + map[ch.mh + bcast(rj, u)] + map[ch.ml + bcast(lj, u)];
+                        v[x] *= sepc[(uint64_t)idx * S + s];
+                    }
+                }
+#pragma unroll
+                for (uint32_t x = 0; x < kUnroll; x++) {
+                    if (u0 + x < cnt) {
+                        if (act) psi[(q.off + i0 + u0 + x) * S + s] = v[x];
+                        acc += (double)v[x];
+                        if (--seg_left == 0) {
+                            if (g.part >= 0) part += acc;
+                            else if (act) c.acc[(uint64_t)out * S + s] = acc;
+                            acc = 0.0;
+                            out++;
+                            seg_left = q.seg;
+                        }
+                    }
+                }
+            }
+        }
+        if (g.part >= 0) part += acc;
+    }
+    if (g.part >= 0 && act) c.part[(uint64_t)(uint32_t)g.part * S + s] = part;
+}
+
+// ---------------------------------------------------------------- distribute
+
+// One work item of a target separator: outputs (g, t), g in [g0, g0+ng),
+// each the sum over rows k in [k0, k0+nk) and lo offsets u of phi* at entry
+// (RG[g] + RQ[k]) * L + LP[t] + LQ[u], phi* = psi * (parent ratio there).
+// The work's (output, entry) pairs are walked in order, 64 at a time: lane j
+// works out pair j's table entry, ratio entry and output index, and the
+// wave then sums with those broadcast, writing each output when its last
+// entry is in.
+template <typename T>
+__global__ __launch_bounds__(kBlock) void k_dist_i(Ctx c, const DWork* __restrict__ works, uint32_t nworks,
+                                                   const int32_t* __restrict__ slots, int nslots) {
+    const uint32_t wi = wave_item();
+    if (wi >= nworks) return;
+    const uint32_t lane = threadIdx.x & (kLanes - 1);
+    const int sl = lane_slot(slots, nslots);
+    const bool act = sl >= 0;
+    const uint64_t S = c.S;
+    const uint64_t s = act ? (uint64_t)sl : 0;
+    const DWork w = works[wi];
+    const DTarget tg = c.tg[w.target];
+    const DClique q = c.cl[tg.clique];
+    const T* __restrict__ psi = static_cast<const T*>(c.psi);
+    const T* __restrict__ sepd = static_cast<const T*>(c.sepd);
+    const uint32_t* __restrict__ map = c.map;
+    const bool ratio = q.pedge >= 0;
+    const uint32_t per = w.nk * tg.nQL;  // entries summed per output
+    const uint32_t total = w.ng * tg.nPL * per;
+    double acc = 0.0;
+    uint32_t left = per;
+    for (uint32_t f0 = 0; f0 < total; f0 += kLanes) {
+        const uint32_t cnt = min((uint32_t)kLanes, total - f0);
+        // lane j: pair f0 + j
+        const uint32_t f = f0 + min(lane, cnt - 1);
+        const uint32_t o = f / per, j = f - o * per;
+        const uint32_t gg = o / tg.nPL, t = o - gg * tg.nPL;
+        const uint32_t k = j / tg.nQL, u = j - k * tg.nQL;
+        const uint32_t row = map[tg.rg + w.g0 + gg] + map[tg.rq + w.k0 + k];
+        const uint32_t l = map[tg.lp + t] + map[tg.lq + u];
+        const uint32_t ej = row * q.L + l;  // within the clique
+        const uint32_t rj = ratio ? q.psep + map[q.pmh + row] + map[q.pml + l] : 0u;
+        const uint32_t mj = map[tg.tb + w.g0 + gg] + map[tg.tv + t];
+        for (uint32_t x0 = 0; x0 < cnt; x0 += kUnroll) {
+            T v[kUnroll], r[kUnroll];
+#pragma unroll
+            for (uint32_t x = 0; x < kUnroll; x++) {
+                const uint32_t b = min(x0 + x, cnt - 1);
+                v[x] = psi[(q.off + bcast(ej, b)) * S + s];
+                r[x] = ratio ? sepd[(uint64_t)bcast(rj, b) * S + s] : T(1);
+            }
+#pragma unroll
+            for (uint32_t x = 0; x < kUnroll; x++) {
+                if (x0 + x < cnt) {
+                    acc += (double)(ratio ? v[x] * r[x] : v[x]);
+                    if (--left == 0) {
+                        const uint32_t mo = bcast(mj, x0 + x);
+                        if (act) {
+                            if (tg.part0 < 0) c.acc[(uint64_t)(tg.sep + mo) * S + s] = acc;
+                            else c.part[(uint64_t)((uint32_t)tg.part0 + mo * tg.nchunk + w.chunk) * S + s] = acc;
+                        }
+                        acc = 0.0;
+                        left = per;
+                    }
+                }
+            }
+        }
+    }
+}
+
+// --------------------------------------------------------------- finalisers
+
+// Finish entry m of a separator: the sum of its partials in chunk order
+// (loaded eight at a time), or the layer kernel's whole sum.
+__device__ __forceinline__ double finish_i(const DSepFin& f, const Ctx& c, uint64_t S, uint64_t s, uint32_t m) {
+    if (!f.nchunk) return c.acc[(uint64_t)(f.sep + m) * S + s];
+    double v = 0.0;
+    const uint64_t p0 = (uint64_t)f.part0 + (uint64_t)m * f.nchunk;
+    for (uint32_t k0 = 0; k0 < f.nchunk; k0 += 8) {
+        const uint32_t cnt = min(8u, f.nchunk - k0);
+        double x[8];
+#pragma unroll
+        for (uint32_t y = 0; y < 8; y++) x[y] = c.part[(p0 + k0 + min(y, cnt - 1)) * S + s];
+#pragma unroll
+        for (uint32_t y = 0; y < 8; y++)
+            if (y < cnt) v += x[y];
+    }
+    c.acc[(uint64_t)(f.sep + m) * S + s] = v;
+    return v;
+}
+
+// After a collect layer: finish, rescale to a max in [0.5, 1), store, and
+// keep the exponent; a root's entry flags impossible evidence.
+template <typename T>
+__global__ __launch_bounds__(kBlock) void k_fin_collect_i(Ctx c, const DSepFin* __restrict__ fins, uint32_t nfins,
+                                                          const int32_t* __restrict__ slots, int nslots) {
+    const uint32_t fi = wave_item();
+    if (fi >= nfins) return;
+    const int sl = lane_slot(slots, nslots);
+    if (sl < 0) return;
+    const uint64_t S = c.S, s = (uint64_t)sl;
+    const DSepFin f = fins[fi];
+    double mx = 0.0;
+#pragma unroll 8
+    for (uint32_t m = 0; m < f.size; m++) mx = fmax(mx, finish_i(f, c, S, s, m));
+    if (f.edge < 0) {
+        if (!(c.acc[(uint64_t)f.sep * S + s] > 0.0)) atomicOr(&c.flags[s], c.fp32 ? 2 : 1);
+        return;
+    }
+    int k = 0;
+    if (mx > 0.0) frexp(mx, &k);
+    else atomicOr(&c.flags[s], c.fp32 ? 2 : 1);
+    const double scale = ldexp(1.0, -k);
+    T* __restrict__ sepc = static_cast<T*>(c.sepc);
+#pragma unroll 8
+    for (uint32_t m = 0; m < f.size; m++)
+        sepc[(uint64_t)(f.sep + m) * S + s] = (T)(c.acc[(uint64_t)(f.sep + m) * S + s] * scale);
+    c.kexp[(uint64_t)f.edge * S + s] = k;
+}
+
+// After a distribute layer: finish the new separator, its posterior sums,
+// and for a real separator the ratio new/old (0/0 = 0) rescaled.
+template <typename T>
+__global__ __launch_bounds__(kBlock) void k_fin_distribute_i(Ctx c, const DSepFin* __restrict__ fins,
+                                                             uint32_t nfins, const int32_t* __restrict__ slots,
+                                                             int nslots) {
+    const uint32_t fi = wave_item();
+    if (fi >= nfins) return;
+    const int sl = lane_slot(slots, nslots);
+    if (sl < 0) return;
+    const uint64_t S = c.S, s = (uint64_t)sl;
+    const DSepFin f = fins[fi];
+    if (f.nchunk) {
+#pragma unroll 8
+        for (uint32_t m = 0; m < f.size; m++) finish_i(f, c, S, s, m);
+    }
+    // the posterior sums go straight to the marginal accumulators
+    for (uint32_t a = 0; a < f.nmv; a++) {
+        const DMargVar mv = c.mv[f.mv0 + a];
+        const uint32_t span = mv.stride * mv.card;
+        for (uint32_t x = 0; x < mv.card; x++) {
+            double acc = 0.0;
+            for (uint32_t m = x * mv.stride; m < f.size; m += span) {
+#pragma unroll 8
+                for (uint32_t y = m; y < m + mv.stride; y++) acc += c.acc[(uint64_t)(f.sep + y) * S + s];
+            }
+            c.marg[(uint64_t)(mv.out + x) * S + s] = acc;
+        }
+    }
+    if (f.edge < 0) return;
+    const T* __restrict__ sepc = static_cast<const T*>(c.sepc);
+    T* __restrict__ sepd = static_cast<T*>(c.sepd);
+    double mx = 0.0;
+#pragma unroll 8
+    for (uint32_t m = 0; m < f.size; m++) {
+        const double den = (double)sepc[(uint64_t)(f.sep + m) * S + s];
+        mx = fmax(mx, den == 0.0 ? 0.0 : c.acc[(uint64_t)(f.sep + m) * S + s] / den);
+    }
+    int k = 0;
+    if (mx > 0.0) frexp(mx, &k);
+    const double scale = ldexp(1.0, -k);
+#pragma unroll 8
+    for (uint32_t m = 0; m < f.size; m++) {
+        const uint64_t x = (uint64_t)(f.sep + m) * S + s;
+        const double den = (double)sepc[x];
+        sepd[x] = (T)((den == 0.0 ? 0.0 : c.acc[x] / den) * scale);
+    }
+}
+
+// Large separators in blocks of at most kFinBlockInterleaved entries, one
+// wave per block.  Phase a finishes the block's entries and folds its
+// maximum into the separator's maximum with an integer atomic max on the
+// bit pattern (exact and order-independent for non-negative doubles; the
+// slot, the block's first id, is cleared before every calibration); in the
+// distribute sweep it also writes the block's share of every posterior sum.
+// Phase b rescales with the separator's maximum; the separator's blocks
+// split its posterior sums between them, each adding one sum's block
+// shares in block order.
+__device__ __forceinline__ void fold_max(const Ctx& c, const DFinBlk& b, uint64_t S, uint64_t s, double mx) {
+    atomicMax(reinterpret_cast<unsigned long long*>(c.bmax) + (uint64_t)b.blk0 * S + s,
+              (unsigned long long)__double_as_longlong(mx));
+}
+__device__ __forceinline__ double fin_max_i(const Ctx& c, const DFinBlk& b, uint64_t S, uint64_t s) {
+    return c.bmax[(uint64_t)b.blk0 * S + s];
+}
+
+__global__ __launch_bounds__(kBlock) void k_fin_collect_ia(Ctx c, const DSepFin* __restrict__ fins,
+                                                           const DFinBlk* __restrict__ blks, uint32_t nblks,
+                                                           const int32_t* __restrict__ slots, int nslots) {
+    const uint32_t bi = wave_item();
+    if (bi >= nblks) return;
+    const int sl = lane_slot(slots, nslots);
+    if (sl < 0) return;
+    const uint64_t S = c.S, s = (uint64_t)sl;
+    const DFinBlk b = blks[bi];
+    const DSepFin f = fins[b.fin];
+    double mx = 0.0;
+#pragma unroll 8
+    for (uint32_t m = b.begin; m < b.begin + b.count; m++) mx = fmax(mx, finish_i(f, c, S, s, m));
+    fold_max(c, b, S, s, mx);
+}
+
+template <typename T>
+__global__ __launch_bounds__(kBlock) void k_fin_collect_ib(Ctx c, const DSepFin* __restrict__ fins,
+                                                           const DFinBlk* __restrict__ blks, uint32_t nblks,
+                                                           const int32_t* __restrict__ slots, int nslots) {
+    const uint32_t bi = wave_item();
+    if (bi >= nblks) return;
+    const int sl = lane_slot(slots, nslots);
+    if (sl < 0) return;
+    const uint64_t S = c.S, s = (uint64_t)sl;
+    const DFinBlk b = blks[bi];
+    const DSepFin f = fins[b.fin];
+    const double mx = fin_max_i(c, b, S, s);
+    int k = 0;
+    if (mx > 0.0) frexp(mx, &k);
+    else if (b.begin == 0) atomicOr(&c.flags[s], c.fp32 ? 2 : 1);
+    const double scale = ldexp(1.0, -k);
+    T* __restrict__ sepc = static_cast<T*>(c.sepc);
+#pragma unroll 8
+    for (uint32_t m = b.begin; m < b.begin + b.count; m++) {
+        const uint64_t x = (uint64_t)(f.sep + m) * S + s;
+        sepc[x] = (T)(c.acc[x] * scale);
+    }
+    if (b.begin == 0) c.kexp[(uint64_t)f.edge * S + s] = k;
+}
+
+constexpr uint32_t kPostChunk = 16;  // posterior states accumulated per pass
+
+template <typename T>
+__global__ __launch_bounds__(kBlock) void k_fin_distribute_ia(Ctx c, const DSepFin* __restrict__ fins,
+                                                              const DFinBlk* __restrict__ blks, uint32_t nblks,
+                                                              const int32_t* __restrict__ slots, int nslots) {
+    __shared__ double post_acc[kWavesPerBlock][kPostChunk][kLanes];
+    const uint32_t bi = wave_item();
+    if (bi >= nblks) return;
+    const uint32_t lane = threadIdx.x & (kLanes - 1);
+    const int sl = lane_slot(slots, nslots);
+    if (sl < 0) return;
+    const uint64_t S = c.S, s = (uint64_t)sl;
+    const DFinBlk b = blks[bi];
+    const DSepFin f = fins[b.fin];
+    const T* __restrict__ sepc = static_cast<const T*>(c.sepc);
+    double mx = 0.0;
+#pragma unroll 8
+    for (uint32_t m = b.begin; m < b.begin + b.count; m++) {
+        const double v = finish_i(f, c, S, s, m);
+        const double den = (double)sepc[(uint64_t)(f.sep + m) * S + s];
+        mx = fmax(mx, den == 0.0 ? 0.0 : v / den);
+    }
+    fold_max(c, b, S, s, mx);
+    // this block's share of each posterior sum: one pass per variable and
+    // run of at most kPostChunk states; consecutive entries with the same
+    // digit are summed in a register and added to the state's LDS cell
+    // (one column per lane) when the digit changes
+    double(*pa)[kLanes] = post_acc[threadIdx.x / kLanes];
+    double* __restrict__ bm = c.bmarg;
+    const uint64_t o0 = (uint64_t)b.mbase + (uint64_t)(b.id - b.blk0) * b.mw;
+    const double* __restrict__ acc = c.acc;
+    uint32_t vo = 0;
+    for (uint32_t a = 0; a < f.nmv; a++) {
+        const DMargVar mv = c.mv[f.mv0 + a];
+        for (uint32_t x0 = 0; x0 < mv.card; x0 += kPostChunk) {
+            const uint32_t nx = min(kPostChunk, mv.card - x0);
+            for (uint32_t x = 0; x < nx; x++) pa[x][lane] = 0.0;
+            double run = 0.0;
+            uint32_t cur = 0xffffffffu;
+            for (uint32_t m0 = b.begin; m0 < b.begin + b.count; m0 += 8) {
+                const uint32_t cnt = min(8u, b.begin + b.count - m0);
+                double v[8];
+#pragma unroll
+                for (uint32_t y = 0; y < 8; y++)
+                    v[y] = acc[(uint64_t)(f.sep + m0 + min(y, cnt - 1)) * S + s];
+#pragma unroll
+                for (uint32_t y = 0; y < 8; y++) {
+                    if (y < cnt) {
+                        const uint32_t o = mdiv_i(m0 + y, mv.smul, mv.ssh);
+                        const uint32_t d = o - mdiv_i(o, mv.cmul, mv.csh) * mv.card;
+                        if (d != cur) {
+                            if (cur - x0 < nx) pa[cur - x0][lane] += run;
+                            run = 0.0;
+                            cur = d;
+                        }
+                        run += v[y];
+                    }
+                }
+            }
+            if (cur - x0 < nx) pa[cur - x0][lane] += run;
+            for (uint32_t x = 0; x < nx; x++) bm[(o0 + vo + x0 + x) * S + s] = pa[x][lane];
+        }
+        vo += mv.card;
+    }
+}
+
+template <typename T>
+__global__ __launch_bounds__(kBlock) void k_fin_distribute_ib(Ctx c, const DSepFin* __restrict__ fins,
+                                                              const DFinBlk* __restrict__ blks, uint32_t nblks,
+                                                              const int32_t* __restrict__ slots, int nslots) {
+    const uint32_t bi = wave_item();
+    if (bi >= nblks) return;
+    const int sl = lane_slot(slots, nslots);
+    if (sl < 0) return;
+    const uint64_t S = c.S, s = (uint64_t)sl;
+    const DFinBlk b = blks[bi];
+    const DSepFin f = fins[b.fin];
+    const double mx = fin_max_i(c, b, S, s);
+    int k = 0;
+    if (mx > 0.0) frexp(mx, &k);
+    const double scale = ldexp(1.0, -k);
+    const T* __restrict__ sepc = static_cast<const T*>(c.sepc);
+    T* __restrict__ sepd = static_cast<T*>(c.sepd);
+#pragma unroll 8
+    for (uint32_t m = b.begin; m < b.begin + b.count; m++) {
+        const uint64_t x = (uint64_t)(f.sep + m) * S + s;
+        const double den = (double)sepc[x];
+        sepd[x] = (T)((den == 0.0 ? 0.0 : c.acc[x] / den) * scale);
+    }
+    // posterior sums: block j of the separator adds sums j, j + nblk, ...
+    const uint32_t j = b.id - b.blk0;
+    for (uint32_t pidx = j; pidx < b.mw; pidx += b.nblk) {
+        uint32_t vo = 0, a = 0;
+        DMargVar mv = c.mv[f.mv0];
+        while (pidx >= vo + mv.card) {
+            vo += mv.card;
+            mv = c.mv[f.mv0 + ++a];
+        }
+        double acc = 0.0;
+#pragma unroll 8
+        for (uint32_t jj = 0; jj < b.nblk; jj++) acc += c.bmarg[((uint64_t)b.mbase + (uint64_t)jj * b.mw + pidx) * S + s];
+        c.marg[(uint64_t)(mv.out + pidx - vo) * S + s] = acc;
+    }
+}
+
+// ---------------------------------------------------------------- posteriors
+
+// Per slot: normalise every variable's marginal into the slot-major
+// posterior array read by the gather, and form log P(e) from the roots'
+// sums and the exponents (fixed order per lane).
+__global__ __launch_bounds__(kBlock) void k_marginals_i(Ctx c, const int32_t* __restrict__ slots, int nslots,
+                                                        uint32_t vars_per_wave) {
+    const uint32_t wi = wave_item();
+    const int sl = lane_slot(slots, nslots);
+    if (sl < 0) return;
+    const uint64_t S = c.S, s = (uint64_t)sl;
+    const uint32_t v0 = wi * vars_per_wave;
+    const uint32_t v1 = min((uint32_t)c.nvars, v0 + vars_per_wave);
+    double* __restrict__ post = c.post + s * c.marg_stride;
+    bool empty = false;
+    for (uint32_t v = v0; v < v1; v++) {
+        const DHomeVar h = c.hv[v];
+        double sum = 0.0;
+        for (uint32_t x = 0; x < h.card; x++) sum += c.marg[(uint64_t)(h.out + x) * S + s];
+        for (uint32_t x = 0; x < h.card; x++)
+            post[h.out + x] = sum > 0.0 ? c.marg[(uint64_t)(h.out + x) * S + s] / sum : 0.0;
+        if (!(sum > 0.0)) empty = true;
+    }
+    if (empty) atomicOr(&c.flags[s], c.fp32 ? 2 : 1);
+    if (wi != 0) return;
+    double lg = 0.0;
+    for (uint32_t r = 0; r < c.nroots; r++) {
+        const double z = c.acc[(uint64_t)(c.sep_total + r) * S + s];
+        lg += z > 0.0 ? log(z) : -INFINITY;
+    }
+    long long ks = 0;
+#pragma unroll 8
+    for (int e = 0; e < c.ne; e++) ks += c.kexp[(uint64_t)e * S + s];
+    c.logpe[s] = lg > -INFINITY ? lg + 0.69314718055994530942 * (double)(ks + c.kappa_total) : -INFINITY;
+}
+
+}  // namespace
+
+hipError_t launch_interleaved(const Ctx& c, int prec, int kind, const void* items, uint32_t nitems,
+                              const DSepFin* fins, const int32_t* slots, int nslots, hipStream_t st) {
+    if (!nitems || !nslots) return hipSuccess;
+    const dim3 grid((nitems + kWavesPerBlock - 1) / kWavesPerBlock, (unsigned)((nslots + kLanes - 1) / kLanes));
+    const dim3 block(kBlock);
+    const auto* groups = static_cast<const DGroup*>(items);
+    const auto* works = static_cast<const DWork*>(items);
+    const auto* sfins = static_cast<const DSepFin*>(items);
+    const auto* blks = static_cast<const DFinBlk*>(items);
+    switch (kind) {
+    case kIlCollect:
+        if (prec) hipLaunchKernelGGL(k_collect_i<float>, grid, block, 0, st, c, groups, nitems, slots, nslots);
+        else hipLaunchKernelGGL(k_collect_i<double>, grid, block, 0, st, c, groups, nitems, slots, nslots);
+        break;
+    case kIlDistribute:
+        if (prec) hipLaunchKernelGGL(k_dist_i<float>, grid, block, 0, st, c, works, nitems, slots, nslots);
+        else hipLaunchKernelGGL(k_dist_i<double>, grid, block, 0, st, c, works, nitems, slots, nslots);
+        break;
+    case kIlFinCollect:
+        if (prec) hipLaunchKernelGGL(k_fin_collect_i<float>, grid, block, 0, st, c, sfins, nitems, slots, nslots);
+        else hipLaunchKernelGGL(k_fin_collect_i<double>, grid, block, 0, st, c, sfins, nitems, slots, nslots);
+        break;
+    case kIlFinDistribute:
+        if (prec) hipLaunchKernelGGL(k_fin_distribute_i<float>, grid, block, 0, st, c, sfins, nitems, slots, nslots);
+        else hipLaunchKernelGGL(k_fin_distribute_i<double>, grid, block, 0, st, c, sfins, nitems, slots, nslots);
+        break;
+    case kIlFinCollectA:
+        hipLaunchKernelGGL(k_fin_collect_ia, grid, block, 0, st, c, fins, blks, nitems, slots, nslots);
+        break;
+    case kIlFinCollectB:
+        if (prec) hipLaunchKernelGGL(k_fin_collect_ib<float>, grid, block, 0, st, c, fins, blks, nitems, slots, nslots);
+        else hipLaunchKernelGGL(k_fin_collect_ib<double>, grid, block, 0, st, c, fins, blks, nitems, slots, nslots);
+        break;
+    case kIlFinDistributeA:
+        if (prec)
+            hipLaunchKernelGGL(k_fin_distribute_ia<float>, grid, block, 0, st, c, fins, blks, nitems, slots, nslots);
+        else
+            hipLaunchKernelGGL(k_fin_distribute_ia<double>, grid, block, 0, st, c, fins, blks, nitems, slots, nslots);
+        break;
+    case kIlFinDistributeB:
+        if (prec)
+            hipLaunchKernelGGL(k_fin_distribute_ib<float>, grid, block, 0, st, c, fins, blks, nitems, slots, nslots);
+        else
+            hipLaunchKernelGGL(k_fin_distribute_ib<double>, grid, block, 0, st, c, fins, blks, nitems, slots, nslots);
+        break;
+    default:
+        return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_marginals_interleaved(const Ctx& c, const int32_t* slots, int nslots, hipStream_t st) {
+    if (!nslots) return hipSuccess;
+    const uint32_t per = 64;  // variables per wave
+    const uint32_t waves = ((uint32_t)c.nvars + per - 1) / per;
+    const dim3 grid(std::max<uint32_t>(1u, (waves + kWavesPerBlock - 1) / kWavesPerBlock),
+                    (unsigned)((nslots + kLanes - 1) / kLanes));
+    hipLaunchKernelGGL(k_marginals_i, grid, dim3(kBlock), 0, st, c, slots, nslots, per);
+    return hipGetLastError();
+}
+
+}  // namespace fbn

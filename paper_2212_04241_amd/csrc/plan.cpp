@@ -102,20 +102,21 @@ uint32_t enumerate(const std::vector<int>& pos, const std::vector<int>& card_at,
     return start;
 }
 
-bool is_big(const DSepFin& f) { return f.size > kBigSeparator && f.edge >= 0; }
+bool is_big(const Plan& p, const DSepFin& f) { return f.size > p.big_separator && f.edge >= 0; }
 
 // Partition a layer's finalisers large-first and split each large one into
 // near-equal blocks of at most kFinBlock entries.
 void finish_layer(Plan& p, Layer& ly, std::vector<DSepFin>& fins) {
-    std::stable_partition(fins.begin(), fins.end(), is_big);
+    auto big = [&](const DSepFin& f) { return is_big(p, f); };
+    std::stable_partition(fins.begin(), fins.end(), big);
     ly.fin0 = (uint32_t)p.fins.size();
     ly.nfin = (uint32_t)fins.size();
-    ly.nbig = (uint32_t)std::count_if(fins.begin(), fins.end(), is_big);
+    ly.nbig = (uint32_t)std::count_if(fins.begin(), fins.end(), big);
     p.fins.insert(p.fins.end(), fins.begin(), fins.end());
     ly.fb0 = (uint32_t)p.finblks.size();
     for (uint32_t f = ly.fin0; f < ly.fin0 + ly.nbig; f++) {
         const DSepFin F = p.fins[f];
-        const uint32_t nblk = (F.size + kFinBlock - 1) / kFinBlock;
+        const uint32_t nblk = (F.size + p.fin_block - 1) / p.fin_block;
         uint32_t mw = 0;
         for (uint32_t k = 0; k < F.nmv; k++) mw += p.margvars[F.mv0 + k].card;
         const uint32_t blk0 = (uint32_t)p.finblks.size();
@@ -197,6 +198,7 @@ std::string check_plan(const Tree& t, const Plan& p) {
         if ((uint64_t)ly.fin0 + ly.nfin > p.fins.size()) return "layer fins";
         for (uint32_t w = ly.group0; w < ly.group0 + ly.ngroup; w++) {
             const DWork& W = p.works[w];
+            if (p.interleaved && W.npiece > 0) return "packed work in an interleaved plan";
             if (W.npiece > 0) {
                 // packed: whole cliques staged in LDS and all their targets
                 if (W.npiece > (uint32_t)kMaxPieces || (uint64_t)W.piece0 + W.npiece > p.pieces.size()) return "packed pieces";
@@ -265,7 +267,7 @@ std::string check_plan(const Tree& t, const Plan& p) {
             uint32_t b = ly.fb0;
             for (uint32_t f = ly.fin0; f < ly.fin0 + ly.nfin; f++) {
                 const DSepFin& F = p.fins[f];
-                if ((f < ly.fin0 + ly.nbig) != is_big(F)) return "large fin partition";
+                if ((f < ly.fin0 + ly.nbig) != is_big(p, F)) return "large fin partition";
                 if (f >= ly.fin0 + ly.nbig) continue;
                 uint32_t mw = 0;
                 for (uint32_t k = 0; k < F.nmv; k++) mw += p.margvars[F.mv0 + k].card;
@@ -273,7 +275,8 @@ std::string check_plan(const Tree& t, const Plan& p) {
                 const uint32_t blk0 = b;
                 for (; b < ly.fb0 + ly.nfb && p.finblks[b].fin == f; b++) {
                     const DFinBlk& B = p.finblks[b];
-                    if (B.id != b || B.blk0 != blk0 || B.begin != end || B.count == 0 || B.count > kFinBlock)
+                    if (B.id != b || B.blk0 != blk0 || B.begin != end || B.count == 0 || B.count > p.fin_block ||
+                        B.count > kFinBlock)
                         return "fin block layout";
                     if (B.mw != mw || (uint64_t)B.mbase + (uint64_t)B.nblk * mw > p.n_bmarg) return "fin block scratch";
                     end += B.count;
@@ -291,8 +294,10 @@ std::string check_plan(const Tree& t, const Plan& p) {
             const DMargVar& m = p.margvars[F.mv0 + k];
             if ((uint64_t)m.out + m.card > p.marg_total || m.card == 0 || m.stride == 0) return "posterior var range";
             if ((uint64_t)m.stride * m.card > F.size || F.size % ((uint64_t)m.stride * m.card)) return "posterior var stride";
-            for (uint32_t x : {0u, m.stride - 1, m.stride, F.size / m.card - 1})
+            for (uint32_t x : {0u, m.stride - 1, m.stride, F.size / m.card - 1, F.size - 1})
                 if (mdiv_host(x, m.smul, m.ssh) != x / m.stride) return "posterior var magic";
+            for (uint32_t x : {0u, m.card - 1, m.card, F.size / m.stride - 1})
+                if (mdiv_host(x, m.cmul, m.csh) != x / m.card) return "posterior var card magic";
         }
     }
     if ((uint64_t)p.sep_stride < (uint64_t)p.sep_real) return "separator stride";
@@ -306,8 +311,11 @@ std::string check_plan(const Tree& t, const Plan& p) {
     return "";
 }
 
-void build_plan(const Tree& t, int tile, uint32_t max_stage, Plan& p) {
+void build_plan(const Tree& t, int tile, uint32_t max_stage, Plan& p, bool interleaved) {
     p = Plan();
+    p.interleaved = interleaved;
+    p.fin_block = interleaved ? kFinBlockInterleaved : kFinBlock;
+    p.big_separator = interleaved ? kBigSeparatorInterleaved : kBigSeparator;
     max_stage = std::min<uint32_t>(std::max<uint32_t>(max_stage, 64), (uint32_t)kTileMax);
     p.max_stage = max_stage;
     if (tile <= 0) tile = 2048;
@@ -570,7 +578,7 @@ void build_plan(const Tree& t, int tile, uint32_t max_stage, Plan& p) {
             for (int v : lay)
                 if (p.post_sep[(size_t)v] < 0) tgts.push_back({{v}, vsep_off[(size_t)v], -2});
             const uint32_t dtile_c = std::min<uint32_t>(max_stage, std::max(dtile_base, d.L));
-            const bool packed = d.size <= dtile_c && tgts.size() <= (size_t)kMaxPieces;
+            const bool packed = !interleaved && d.size <= dtile_c && tgts.size() <= (size_t)kMaxPieces;
             if (packed) {
                 if (open_w >= 0) {
                     const DWork& W = p.works[(size_t)open_w];
@@ -692,6 +700,7 @@ void build_plan(const Tree& t, int tile, uint32_t max_stage, Plan& p) {
                         mv.stride = (uint32_t)vs[a];
                         mv.card = (uint32_t)t.card[(size_t)v];
                         magic_u32(mv.stride, mv.smul, mv.ssh);
+                        magic_u32(mv.card, mv.cmul, mv.csh);
                         p.margvars.push_back(mv);
                     }
                 } else {
@@ -701,6 +710,7 @@ void build_plan(const Tree& t, int tile, uint32_t max_stage, Plan& p) {
                     mv.stride = 1u;
                     mv.card = (uint32_t)t.card[(size_t)v];
                     magic_u32(1u, mv.smul, mv.ssh);
+                    magic_u32(mv.card, mv.cmul, mv.csh);
                     p.margvars.push_back(mv);
                 }
                 f.nmv = (uint32_t)p.margvars.size() - f.mv0;

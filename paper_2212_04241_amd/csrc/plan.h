@@ -14,9 +14,13 @@ struct Layer {
 };
 
 constexpr uint32_t kBigSeparator = 1024;  // entries above which a separator is split into blocks
+constexpr uint32_t kBigSeparatorInterleaved = 64;  // the same with slot-interleaved tables
 
 struct Plan {
     int tile = 2048;
+    bool interleaved = false;         // slot-interleaved tables: one wave per work item, lanes = slots
+    uint32_t fin_block = kFinBlock;   // separator entries per finaliser block
+    uint32_t big_separator = kBigSeparator;  // larger real separators are finalised in blocks
     uint32_t stage = 0;               // LDS entries per slot: largest collect tile or distribute block
     uint32_t max_stage = 0;           // bound on stage
     uint64_t T = 0;                   // prior / working-table entries
@@ -53,8 +57,11 @@ struct Plan {
 };
 
 // max_stage: entries one workgroup can stage in LDS for one slot (bounds
-// every tile, every distribute block and the row length L).
-void build_plan(const Tree& t, int tile, uint32_t max_stage, Plan& p);
+// every tile, every distribute block and the row length L).  interleaved:
+// the work items are sized for one wave each (tile entries), distribute
+// work is never packed, and large separators split into blocks of
+// kFinBlockInterleaved entries.
+void build_plan(const Tree& t, int tile, uint32_t max_stage, Plan& p, bool interleaved = false);
 
 // Checks, on the host, every bound the kernels rely on: tile and run sizes,
 // run alignment to separator segments, table offsets and every value of the

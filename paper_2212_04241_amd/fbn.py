@@ -19,6 +19,7 @@ FBN_OK = 0
 FBN_E_INVALID_ARG, FBN_E_PARSE, FBN_E_IO, FBN_E_NOMEM_HOST, FBN_E_NOMEM_DEVICE = 1, 2, 3, 4, 5
 FBN_E_TOO_LARGE, FBN_E_ZERO_EVIDENCE, FBN_E_STATE, FBN_E_DEVICE, FBN_E_UNDERFLOW = 6, 7, 8, 9, 10
 FBN_FP64, FBN_FP32_RESCALED = 0, 1
+FBN_LAYOUT_AUTO, FBN_LAYOUT_PER_SLOT, FBN_LAYOUT_INTERLEAVED = 0, 1, 2
 
 _ALLOC_FN = C.CFUNCTYPE(C.c_void_p, C.c_void_p, C.c_size_t, C.c_void_p)
 _FREE_FN = C.CFUNCTYPE(None, C.c_void_p, C.c_void_p, C.c_void_p)
@@ -31,14 +32,14 @@ class fbn_allocator(C.Structure):
 class fbn_jt_options(C.Structure):
     _fields_ = [("precision", C.c_int32), ("max_slots", C.c_int32), ("max_clique_entries", C.c_uint64),
                 ("host_only", C.c_int32), ("tile_entries", C.c_int32), ("allocator", fbn_allocator),
-                ("stream", C.c_void_p)]
+                ("stream", C.c_void_p), ("layout", C.c_int32), ("reserved", C.c_int32)]
 
 
 class fbn_jt_stats_t(C.Structure):
     _fields_ = [("n_vars", C.c_int32), ("n_cliques", C.c_int32), ("n_edges", C.c_int32), ("root", C.c_int32),
                 ("H", C.c_int32), ("D", C.c_int32), ("T", C.c_uint64), ("K", C.c_uint64),
                 ("max_clique", C.c_uint64), ("sep_total", C.c_uint64), ("device_bytes", C.c_uint64),
-                ("slot_bytes", C.c_uint64), ("n_trees", C.c_int32), ("reserved", C.c_int32)]
+                ("slot_bytes", C.c_uint64), ("n_trees", C.c_int32), ("interleaved", C.c_int32)]
 
 
 class FbnError(RuntimeError):
@@ -179,7 +180,8 @@ class JT:
     list of Nets for a forest (fbn_build_forest)."""
 
     def __init__(self, net, precision: int = FBN_FP64, max_slots: int = 1, max_clique_entries: int = 0,
-                 host_only: bool = False, tile_entries: int = 0, stream=None, torch_allocator: bool = False):
+                 host_only: bool = False, tile_entries: int = 0, stream=None, torch_allocator: bool = False,
+                 layout: int = 0):
         L = lib()
         opt = fbn_jt_options()
         L.fbn_default_options(C.byref(opt))
@@ -189,6 +191,7 @@ class JT:
             opt.max_clique_entries = max_clique_entries
         opt.host_only = 1 if host_only else 0
         opt.tile_entries = tile_entries
+        opt.layout = layout
         opt.stream = C.c_void_p(stream) if stream else None
         self._cb = None
         if torch_allocator and not host_only:

@@ -19,12 +19,12 @@ def say(*a):
     sys.stdout.flush()
 
 
-def gpu_run(net, cases, precision=fbn.FBN_FP64, tile=0, slots=None, jt=None, max_slots=None):
+def gpu_run(net, cases, precision=fbn.FBN_FP64, tile=0, slots=None, jt=None, max_slots=None, layout=0):
     """All cases in one batch.  Returns (post[n, sum card], log_pe[n], status[n], jt)."""
     n = len(cases)
     if jt is None:
         jt = fbn.JT(fbn.net_from_spec(net), precision=precision, max_slots=max_slots or max(n, 1),
-                    tile_entries=tile)
+                    tile_entries=tile, layout=layout)
     slots = list(range(n)) if slots is None else list(slots)
     fbn.set_evidence_batch(jt, slots, cases)
     lp, st = fbn.calibrate(jt, slots, want_results=True)

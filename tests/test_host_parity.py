@@ -231,3 +231,31 @@ def test_plan_bounds_check_c4_forest(precision):
     nets = [fbngen.make_net("C4", j) for j in range(256)]
     jt = fbn.JT([fbn.net_from_spec(n) for n in nets], host_only=True, precision=precision)
     assert jt.stats["n_trees"] == 256 and jt.stats["n_vars"] == sum(n.n for n in nets)
+
+
+# ---------------------------------------------------------------- autotuner
+
+def test_tuner_picks_the_fastest_and_caches(tmp_path):
+    from paper_2212_04241_amd import tune
+    net = fbngen.make_net("C1", 0)
+    cases = fbngen.make_cases("C1", net)[:4]
+    calls = []
+
+    def fake(nets, cs, precision, max_slots, layout, tile, reps):
+        calls.append((layout, tile))
+        if tile == 512:
+            raise fbn.FbnError(fbn.FBN_E_INVALID_ARG, "fake")
+        return {0: 5.0, 2048: 3.0, 4096: 4.0, 128: 9.0, 256: 2.5}[tile]
+
+    path = str(tmp_path / "tune.json")
+    r = tune.tune(net, cases, cache=path, measure=fake)
+    assert (r["layout"], r["tile"], r["cached"]) == (tune.INTERLEAVED, 256, False)
+    assert len(r["trials"]) == len(tune.DEFAULT_CANDIDATES) - 1
+    n = len(calls)
+    r2 = tune.tune(net, cases, cache=path, measure=fake)
+    assert r2["cached"] and len(calls) == n and (r2["layout"], r2["tile"]) == (r["layout"], r["tile"])
+    # another batch size or precision is another key
+    tune.tune(net, cases[:2], cache=path, measure=fake)
+    assert len(calls) > n
+    k1 = tune.network_key(net, 1, 4, 4)
+    assert k1 == tune.network_key(net, 1, 4, 4) != tune.network_key(net, 0, 4, 4)
