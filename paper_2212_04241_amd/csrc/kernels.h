@@ -47,7 +47,7 @@ constexpr int kStageBytes = 16384;
 // Slots one workgroup carries for a tile of `tile` entries of width w.
 inline int slots_per_block(uint32_t tile, int w) {
     int b = kStageBytes / (int)(tile * (uint32_t)w);
-    return b >= 4 ? 4 : (b >= 2 ? 2 : 1);
+    return b >= 8 ? 8 : (b >= 4 ? 4 : (b >= 2 ? 2 : 1));
 }
 
 // prec: 0 = float64 tables, 1 = float32 tables

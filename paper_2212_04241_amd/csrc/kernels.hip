@@ -863,7 +863,8 @@ template <typename T>
 void launch_collect_t(const Ctx& c, const DGroup* groups, uint32_t ngroups, const int32_t* slots, int nslots,
                       hipStream_t s) {
     const int B = nslots >= 4 ? slots_per_block(c.tile, sizeof(T)) : 1;
-    if (B >= 4) launch_collect_b<T, 4>(c, groups, ngroups, slots, nslots, s);
+    if (B >= 8 && nslots >= 8) launch_collect_b<T, 8>(c, groups, ngroups, slots, nslots, s);
+    else if (B >= 4) launch_collect_b<T, 4>(c, groups, ngroups, slots, nslots, s);
     else if (B == 2) launch_collect_b<T, 2>(c, groups, ngroups, slots, nslots, s);
     else launch_collect_b<T, 1>(c, groups, ngroups, slots, nslots, s);
 }
@@ -872,7 +873,8 @@ template <typename T>
 void launch_gather_t(const Ctx& c, const DWork* works, uint32_t nworks, const int32_t* slots, int nslots,
                      hipStream_t s) {
     const int B = nslots >= 4 ? slots_per_block(c.tile, sizeof(T)) : 1;
-    if (B >= 4) launch_gather_b<T, 4>(c, works, nworks, slots, nslots, s);
+    if (B >= 8 && nslots >= 8) launch_gather_b<T, 8>(c, works, nworks, slots, nslots, s);
+    else if (B >= 4) launch_gather_b<T, 4>(c, works, nworks, slots, nslots, s);
     else if (B == 2) launch_gather_b<T, 2>(c, works, nworks, slots, nslots, s);
     else launch_gather_b<T, 1>(c, works, nworks, slots, nslots, s);
 }

@@ -315,3 +315,21 @@ def test_torch_stream_and_allocator():
     check_fp64(post, lp, st, ref, "torch")
     del jt
     torch.cuda.synchronize()
+
+
+@pytest.mark.parametrize("prec,tile", [(fbn.FBN_FP32_RESCALED, 512), (fbn.FBN_FP64, 256), (fbn.FBN_FP32_RESCALED, 100)])
+def test_eight_slots_per_workgroup(prec, tile):
+    # small tiles let one workgroup carry eight slots; ragged batch sizes
+    # leave some of a workgroup's slots empty
+    net = fbngen.make_net("C2", 0)
+    cases = fbngen.make_cases("C2", net)[:19]
+    say("eight slots per workgroup", prec, tile)
+    ref, _ = oracle_run(net, cases)
+    post, lp, st, jt = gpu_run(net, cases, precision=prec, tile=tile)
+    (check_fp64 if prec == fbn.FBN_FP64 else check_fp32)(post, lp, st, ref, f"B8 tile {tile}")
+    # the same case alone in the same tree: bitwise equal
+    marg = int(np.sum(net.card))
+    fbn.set_evidence(jt, 18, *cases[3])
+    lp1, _ = fbn.calibrate(jt, [18], want_results=True)
+    p1, _, _ = fbn.query_all(jt, [18], marg)
+    assert np.array_equal(p1[0], post[3]) and lp1[0] == lp[3]
