@@ -156,6 +156,7 @@ struct DTarget {
     uint32_t sep;        // separator-arena offset of S
     int32_t part0;       // partial sums of S when a group's rows span work items, else -1
     uint32_t nchunk;
+    uint32_t qlmul, qlsh;  // division by nQL
 };
 
 // One workgroup of the distribute gather, in one of two forms.

@@ -514,7 +514,7 @@ __global__ __launch_bounds__(kBlock) void k_dist_gather(Ctx c, const DWork* __re
             const uint32_t lp = map[t2.lp + t];
             const uint32_t per = nk * t2.nQL;
             for (uint32_t j = sub; j < per; j += tpo) {
-                const uint32_t k = j / t2.nQL;
+                const uint32_t k = mdiv(j, t2.qlmul, t2.qlsh);
                 const uint32_t u = j - k * t2.nQL;
                 const uint32_t row = packed ? map[t2.rg + g] + map[t2.rq + k] : rowbase + k;
                 const uint32_t idx = gofs + row * L + lp + map[t2.lq + u];

@@ -257,6 +257,11 @@ std::string check_plan(const Tree& t, const Plan& p) {
         for (uint32_t t2 = 0; t2 < tg.nPL; t2++) mt = std::max<uint64_t>(mt, p.maps[tg.tv + t2]);
         const uint64_t sz = (uint64_t)tg.G * tg.nPL;
         if (mg + mt >= sz) return "target output range";
+        {
+            const uint32_t span = tg.NQ * tg.nQL;  // largest j the gather divides by nQL
+            for (uint32_t x : {0u, tg.nQL - 1, tg.nQL, span - 1})
+                if (mdiv_host(x, tg.qlmul, tg.qlsh) != x / tg.nQL) return "target nQL magic";
+        }
         if ((uint64_t)tg.sep + sz > p.sep_stride) return "target separator offset";
         if (tg.part0 >= 0 && (uint64_t)tg.part0 + sz * tg.nchunk > p.n_parts) return "target partials";
     }
@@ -637,6 +642,7 @@ void build_plan(const Tree& t, int tile, uint32_t max_stage, Plan& p, bool inter
                 T.sep = tg0.sep;
                 T.part0 = -1;
                 T.nchunk = 0;
+                magic_u32(T.nQL, T.qlmul, T.qlsh);
                 const uint32_t ti = (uint32_t)p.targets.size();
                 const uint32_t dtile = dtile_c;
                 const uint64_t group_entries = (uint64_t)T.NQ * d.L;
