@@ -56,6 +56,29 @@ __device__ __forceinline__ double wave_max(double v) {
     return v;
 }
 
+// XCD-aware placement of a layer's workgroups.  The hardware hands
+// consecutive workgroup ids to the chip's eight XCDs in turn, and each XCD
+// has its own L2.  A layer launch is (work item x slot group) flattened to
+// one dimension; workgroup w runs on XCD w % 8 as that XCD's (w / 8)-th, and
+// is given the pair at position start(XCD) + w / 8 of the slot-group-major
+// order, so that each XCD walks a contiguous range of slot groups and the
+// workgroups resident on one XCD gather from the separators of only a few
+// slots at a time.
+constexpr uint32_t kXcds = 8;
+
+struct Cell {
+    uint32_t item, group;  // work item, slot group
+};
+
+__device__ __forceinline__ Cell xcd_cell(uint32_t nitems, uint32_t ngroups) {
+    const uint32_t total = nitems * ngroups;
+    const uint32_t w = blockIdx.x;
+    const uint32_t x = w % kXcds, k = w / kXcds;
+    const uint32_t base = total / kXcds, extra = total % kXcds;
+    const uint32_t idx = x * base + min(x, extra) + k;
+    return Cell{idx % nitems, idx / nitems};
+}
+
 // Block-wide sum; every thread gets the result.
 __device__ __forceinline__ double block_sum(double v, double* scratch) {
     v = wave_sum(v);
@@ -87,7 +110,7 @@ struct KidC {
 };
 
 template <typename T, int B>
-__global__ __launch_bounds__(kBlock) void k_collect(Ctx c, const DGroup* __restrict__ groups,
+__global__ __launch_bounds__(kBlock) void k_collect(Ctx c, const DGroup* __restrict__ groups, uint32_t ngroups,
                                                     const int32_t* __restrict__ slots, int nslots) {
     __shared__ __align__(16) unsigned char stage[kStageBytes];
     __shared__ RunC runs[kMaxPieces];
@@ -96,11 +119,12 @@ __global__ __launch_bounds__(kBlock) void k_collect(Ctx c, const DGroup* __restr
     __shared__ uint32_t nseg_total;
     __shared__ double red[kWaves];
     T* vals = reinterpret_cast<T*>(stage);
-    const DGroup g = groups[blockIdx.x];
+    const Cell cell = xcd_cell(ngroups, ((uint32_t)nslots + B - 1) / B);
+    const DGroup g = groups[cell.item];
     int sl[B];
 #pragma unroll
     for (int b = 0; b < B; b++) {
-        const int k = (int)blockIdx.y * B + b;
+        const int k = (int)cell.group * B + b;
         sl[b] = k < nslots ? slots[k] : -1;
     }
     // ---- run metadata into LDS
@@ -373,17 +397,18 @@ struct TgtD {
 };
 
 template <typename T, int B>
-__global__ __launch_bounds__(kBlock) void k_dist_gather(Ctx c, const DWork* __restrict__ works,
+__global__ __launch_bounds__(kBlock) void k_dist_gather(Ctx c, const DWork* __restrict__ works, uint32_t nworks,
                                                         const int32_t* __restrict__ slots, int nslots) {
     __shared__ __align__(16) unsigned char stage[kStageBytes];
     __shared__ RunD runs[kMaxPieces];
     __shared__ TgtD tgts[kMaxPieces];
     T* vals = reinterpret_cast<T*>(stage);
-    const DWork w = works[blockIdx.x];
+    const Cell cell = xcd_cell(nworks, ((uint32_t)nslots + B - 1) / B);
+    const DWork w = works[cell.item];
     int sl[B];
 #pragma unroll
     for (int b = 0; b < B; b++) {
-        const int k = (int)blockIdx.y * B + b;
+        const int k = (int)cell.group * B + b;
         sl[b] = k < nslots ? slots[k] : -1;
     }
     const uint32_t* __restrict__ map = c.map;
@@ -848,15 +873,17 @@ __global__ void k_zero(uint32_t* __restrict__ p, size_t words) {
 template <typename T, int B>
 void launch_collect_b(const Ctx& c, const DGroup* groups, uint32_t ngroups, const int32_t* slots, int nslots,
                       hipStream_t s) {
-    dim3 grid(ngroups, (unsigned)((nslots + B - 1) / B));
-    hipLaunchKernelGGL((k_collect<T, B>), grid, dim3(kBlock), 0, s, c, groups, slots, nslots);
+    const uint64_t total = (uint64_t)ngroups * (uint64_t)((nslots + B - 1) / B);
+    hipLaunchKernelGGL((k_collect<T, B>), dim3((unsigned)total), dim3(kBlock), 0, s, c, groups, ngroups, slots,
+                       nslots);
 }
 
 template <typename T, int B>
 void launch_gather_b(const Ctx& c, const DWork* works, uint32_t nworks, const int32_t* slots, int nslots,
                      hipStream_t s) {
-    dim3 grid(nworks, (unsigned)((nslots + B - 1) / B));
-    hipLaunchKernelGGL((k_dist_gather<T, B>), grid, dim3(kBlock), 0, s, c, works, slots, nslots);
+    const uint64_t total = (uint64_t)nworks * (uint64_t)((nslots + B - 1) / B);
+    hipLaunchKernelGGL((k_dist_gather<T, B>), dim3((unsigned)total), dim3(kBlock), 0, s, c, works, nworks, slots,
+                       nslots);
 }
 
 template <typename T>
