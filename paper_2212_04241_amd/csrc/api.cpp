@@ -203,8 +203,8 @@ struct fbn_jt {
     void* d_psi = nullptr;
     void* d_sepc = nullptr;
     void* d_sepd = nullptr;
-    double* d_acc = nullptr;
-    double* d_part = nullptr;
+    void* d_acc = nullptr;   // separator sums and partial sums, table precision
+    void* d_part = nullptr;
     int32_t* d_kexp = nullptr;
     double* d_marg = nullptr;
     double* d_post = nullptr;
@@ -334,8 +334,9 @@ SlotLayout slot_layout(const fbn_jt* jt) {
     L.ev_stride = (uint32_t)jt->tree.nc;
     L.bmax_stride = (uint32_t)std::max<size_t>(p.finblks.size(), 1);
     L.bmarg_stride = std::max<uint32_t>(p.n_bmarg, 1);
-    const size_t u[kSlotBuffers] = {w * L.psi_stride, w * p.sep_stride, w * p.sep_stride, 8ull * p.sep_stride,
-                                    8ull * L.part_stride, 4ull * L.kexp_stride, 8ull * L.marg_stride,
+    // separator sums and partial sums are stored in table precision
+    const size_t u[kSlotBuffers] = {w * L.psi_stride, w * p.sep_stride, w * p.sep_stride, w * p.sep_stride,
+                                    w * L.part_stride, 4ull * L.kexp_stride, 8ull * L.marg_stride,
                                     8ull * L.marg_stride, 8, 4, sizeof(DEvidence) * L.ev_stride, 4,
                                     8ull * L.marg_stride, 8, 4, 8ull * L.bmax_stride, 8ull * L.bmarg_stride};
     std::copy(u, u + kSlotBuffers, L.unit);
@@ -395,7 +396,7 @@ fbn_status setup_device(fbn_jt* jt) {
     const uint32_t part_stride = SL.part_stride, kexp_stride = SL.kexp_stride, marg_stride = SL.marg_stride,
                    ev_stride = SL.ev_stride;
     const uint64_t before = jt->device_bytes;
-    void** dsts[kSlotBuffers] = {&jt->d_psi, &jt->d_sepc, &jt->d_sepd, (void**)&jt->d_acc, (void**)&jt->d_part,
+    void** dsts[kSlotBuffers] = {&jt->d_psi, &jt->d_sepc, &jt->d_sepd, &jt->d_acc, &jt->d_part,
                                  (void**)&jt->d_kexp, (void**)&jt->d_marg, (void**)&jt->d_post,
                                  (void**)&jt->d_logpe, (void**)&jt->d_flags, (void**)&jt->d_ev,
                                  (void**)&jt->d_slots, (void**)&jt->d_out_post, (void**)&jt->d_out_logpe,

@@ -23,8 +23,9 @@ struct Ctx {
     void* psi;             // T, working tables (psi_stride)
     void* sepc;            // T, collect messages, rescaled (sep_stride)
     void* sepd;            // T, distribute ratios, rescaled (sep_stride)
-    double* acc;           // float64 separator accumulators (sep_stride)
-    double* part;          // float64 partial sums (part_stride)
+    void* acc;             // new separator sums (sep_stride), table precision: every sum is
+                           // accumulated in float64 and rounded once when stored
+    void* part;            // partial sums (part_stride), table precision, likewise
     int32_t* kexp;         // collect rescale exponents (kexp_stride)
     double* marg;          // float64 marginal accumulators (marg_stride)
     double* post;          // float64 posteriors (marg_stride)

@@ -249,7 +249,7 @@ __global__ __launch_bounds__(kBlock) void k_collect(Ctx c, const DGroup* __restr
             double s = 0.0;
             for (uint32_t k = threadIdx.x; k < g.total; k += kBlock) s += (double)vals[b * c.tile + k];
             s = block_sum(s, red);
-            if (threadIdx.x == 0) c.part[(uint64_t)sl[b] * c.part_stride + (uint32_t)g.part] = s;
+            if (threadIdx.x == 0) static_cast<T*>(c.part)[(uint64_t)sl[b] * c.part_stride + (uint32_t)g.part] = (T)s;
         }
         return;
     }
@@ -281,7 +281,7 @@ __global__ __launch_bounds__(kBlock) void k_collect(Ctx c, const DGroup* __restr
         if (sidx < ns && sub == 0) {
 #pragma unroll
             for (int b = 0; b < B; b++)
-                if (sl[b] >= 0) c.acc[(uint64_t)sl[b] * c.sep_stride + out] = a[b];
+                if (sl[b] >= 0) static_cast<T*>(c.acc)[(uint64_t)sl[b] * c.sep_stride + out] = (T)a[b];
         }
     }
 }
@@ -337,8 +337,8 @@ __global__ __launch_bounds__(kBlock) void k_fin_collect(Ctx c, const DSepFin* __
     const uint32_t lane = tm.lane;
     const DSepFin f = fins[fi];
     const int slot = slots[blockIdx.y];
-    double* __restrict__ acc = c.acc + (uint64_t)slot * c.sep_stride;
-    const double* __restrict__ part = c.part + (uint64_t)slot * c.part_stride;
+    T* __restrict__ acc = static_cast<T*>(c.acc) + (uint64_t)slot * c.sep_stride;
+    const T* __restrict__ part = static_cast<const T*>(c.part) + (uint64_t)slot * c.part_stride;
     int32_t* kexp = c.kexp + (uint64_t)slot * c.kexp_stride;
 
     double mx = 0.0;
@@ -347,9 +347,9 @@ __global__ __launch_bounds__(kBlock) void k_fin_collect(Ctx c, const DSepFin* __
         double v;
         if (f.nchunk) {
             v = 0.0;
-            const double* pp = part + f.part0 + (uint64_t)m * f.nchunk;
+            const T* pp = part + f.part0 + (uint64_t)m * f.nchunk;
             for (uint32_t k = 0; k < f.nchunk; k++) v += pp[k];
-            acc[f.sep + m] = v;
+            acc[f.sep + m] = (T)v;
         } else {
             v = acc[f.sep + m];
         }
@@ -557,8 +557,8 @@ __global__ __launch_bounds__(kBlock) void k_dist_gather(Ctx c, const DWork* __re
 #pragma unroll
             for (int b = 0; b < B; b++) {
                 if (sl[b] < 0) continue;
-                if (part0 < 0) c.acc[(uint64_t)sl[b] * c.sep_stride + sep + m] = s[b];
-                else c.part[(uint64_t)sl[b] * c.part_stride + (uint32_t)part0 + m * nchunk + w.chunk] = s[b];
+                if (part0 < 0) static_cast<T*>(c.acc)[(uint64_t)sl[b] * c.sep_stride + sep + m] = (T)s[b];
+                else static_cast<T*>(c.part)[(uint64_t)sl[b] * c.part_stride + (uint32_t)part0 + m * nchunk + w.chunk] = (T)s[b];
             }
         }
     }
@@ -578,15 +578,15 @@ __global__ __launch_bounds__(kBlock) void k_fin_distribute(Ctx c, const DSepFin*
     const uint32_t lane = tm.lane;
     const DSepFin f = fins[fi];
     const int slot = slots[blockIdx.y];
-    double* __restrict__ acc = c.acc + (uint64_t)slot * c.sep_stride;
-    const double* __restrict__ part = c.part + (uint64_t)slot * c.part_stride;
+    T* __restrict__ acc = static_cast<T*>(c.acc) + (uint64_t)slot * c.sep_stride;
+    const T* __restrict__ part = static_cast<const T*>(c.part) + (uint64_t)slot * c.part_stride;
     if (f.nchunk) {
     #pragma unroll 4
     for (uint32_t m = lane; m < f.size; m += tm.size) {
             double v = 0.0;
-            const double* pp = part + f.part0 + (uint64_t)m * f.nchunk;
+            const T* pp = part + f.part0 + (uint64_t)m * f.nchunk;
             for (uint32_t k = 0; k < f.nchunk; k++) v += pp[k];
-            acc[f.sep + m] = v;
+            acc[f.sep + m] = (T)v;
         }
         tm.sync();  // other lanes of the team read these sums below
     }
@@ -652,12 +652,13 @@ __device__ __forceinline__ double block_max_all(double v, double* scratch) {
 
 // Finish entry m of a separator: the sum of its partials, or the layer
 // kernel's whole sum.
-__device__ __forceinline__ double finish_entry(const DSepFin& f, double* acc, const double* part, uint32_t m) {
+template <typename T>
+__device__ __forceinline__ double finish_entry(const DSepFin& f, T* acc, const T* part, uint32_t m) {
     if (!f.nchunk) return acc[m];
-    const double* pp = part + (uint64_t)m * f.nchunk;
+    const T* pp = part + (uint64_t)m * f.nchunk;
     double v = 0.0;
     for (uint32_t k = 0; k < f.nchunk; k++) v += pp[k];
-    acc[m] = v;
+    acc[m] = (T)v;
     return v;
 }
 
@@ -669,6 +670,7 @@ __device__ __forceinline__ double fin_max(const Ctx& c, const DFinBlk& b, int sl
     return block_max_all(mx, red);
 }
 
+template <typename T>
 __global__ __launch_bounds__(kBlock) void k_fin_collect_a(Ctx c, const DSepFin* __restrict__ fins,
                                                           const DFinBlk* __restrict__ blks,
                                                           const int32_t* __restrict__ slots) {
@@ -676,8 +678,8 @@ __global__ __launch_bounds__(kBlock) void k_fin_collect_a(Ctx c, const DSepFin* 
     const DFinBlk b = blks[blockIdx.x];
     const DSepFin f = fins[b.fin];
     const int slot = slots[blockIdx.y];
-    double* __restrict__ acc = c.acc + (uint64_t)slot * c.sep_stride + f.sep;
-    const double* __restrict__ part = c.part + (uint64_t)slot * c.part_stride + f.part0;
+    T* __restrict__ acc = static_cast<T*>(c.acc) + (uint64_t)slot * c.sep_stride + f.sep;
+    const T* __restrict__ part = static_cast<const T*>(c.part) + (uint64_t)slot * c.part_stride + f.part0;
     double mx = 0.0;
 #pragma unroll 4
     for (uint32_t m = b.begin + threadIdx.x; m < b.begin + b.count; m += kBlock)
@@ -699,7 +701,7 @@ __global__ __launch_bounds__(kBlock) void k_fin_collect_b(Ctx c, const DSepFin* 
     if (mx > 0.0) frexp(mx, &k);
     else if (b.begin == 0 && threadIdx.x == 0) atomicOr(&c.flags[slot], c.fp32 ? 2 : 1);
     const double scale = ldexp(1.0, -k);
-    const double* __restrict__ acc = c.acc + (uint64_t)slot * c.sep_stride + f.sep;
+    const T* __restrict__ acc = static_cast<const T*>(c.acc) + (uint64_t)slot * c.sep_stride + f.sep;
     T* __restrict__ sepc = static_cast<T*>(c.sepc) + (uint64_t)slot * c.sep_stride + f.sep;
 #pragma unroll 4
     for (uint32_t m = b.begin + threadIdx.x; m < b.begin + b.count; m += kBlock) sepc[m] = (T)(acc[m] * scale);
@@ -724,8 +726,8 @@ __global__ __launch_bounds__(kBlock) void k_fin_distribute_a(Ctx c, const DSepFi
     const DFinBlk b = blks[blockIdx.x];
     const DSepFin f = fins[b.fin];
     const int slot = slots[blockIdx.y];
-    double* __restrict__ acc = c.acc + (uint64_t)slot * c.sep_stride + f.sep;
-    const double* __restrict__ part = c.part + (uint64_t)slot * c.part_stride + f.part0;
+    T* __restrict__ acc = static_cast<T*>(c.acc) + (uint64_t)slot * c.sep_stride + f.sep;
+    const T* __restrict__ part = static_cast<const T*>(c.part) + (uint64_t)slot * c.part_stride + f.part0;
     const T* __restrict__ sepc = static_cast<const T*>(c.sepc) + (uint64_t)slot * c.sep_stride + f.sep;
     double mx = 0.0;
 #pragma unroll 4
@@ -770,7 +772,7 @@ __global__ __launch_bounds__(kBlock) void k_fin_distribute_b(Ctx c, const DSepFi
     int k = 0;
     if (mx > 0.0) frexp(mx, &k);
     const double scale = ldexp(1.0, -k);
-    const double* __restrict__ acc = c.acc + (uint64_t)slot * c.sep_stride + f.sep;
+    const T* __restrict__ acc = static_cast<const T*>(c.acc) + (uint64_t)slot * c.sep_stride + f.sep;
     const T* __restrict__ sepc = static_cast<const T*>(c.sepc) + (uint64_t)slot * c.sep_stride + f.sep;
     T* __restrict__ sepd = static_cast<T*>(c.sepd) + (uint64_t)slot * c.sep_stride + f.sep;
 #pragma unroll 4
@@ -803,12 +805,13 @@ __global__ __launch_bounds__(kBlock) void k_marginals(Ctx c, const int32_t* __re
     const double* marg = c.marg + (uint64_t)slot * c.marg_stride;
     double* post = c.post + (uint64_t)slot * c.marg_stride;
     {
-        const double* acc = c.acc + (uint64_t)slot * c.sep_stride;
+        const float* accf = static_cast<const float*>(c.acc) + (uint64_t)slot * c.sep_stride;
+        const double* accd = static_cast<const double*>(c.acc) + (uint64_t)slot * c.sep_stride;
         const int32_t* kexp = c.kexp + (uint64_t)slot * c.kexp_stride;
         double lg = 0.0;
         long long ks = 0;
         for (uint32_t r = threadIdx.x; r < c.nroots; r += kBlock) {
-            const double z = acc[c.sep_total + r];
+            const double z = c.fp32 ? (double)accf[c.sep_total + r] : accd[c.sep_total + r];
             lg += z > 0.0 ? log(z) : -INFINITY;
         }
         for (int e = threadIdx.x; e < c.ne; e += kBlock) ks += kexp[e];
@@ -930,7 +933,8 @@ hipError_t launch_fin_blocks(const Ctx& c, int prec, bool distribute, int phase,
     if (!nblks || !nslots) return hipSuccess;
     const dim3 grid(nblks, (unsigned)nslots), block(kBlock);
     if (!distribute && phase == 0) {
-        hipLaunchKernelGGL(k_fin_collect_a, grid, block, 0, s, c, fins, blks, slots);
+        if (prec) hipLaunchKernelGGL(k_fin_collect_a<float>, grid, block, 0, s, c, fins, blks, slots);
+        else hipLaunchKernelGGL(k_fin_collect_a<double>, grid, block, 0, s, c, fins, blks, slots);
     } else if (!distribute) {
         if (prec) hipLaunchKernelGGL(k_fin_collect_b<float>, grid, block, 0, s, c, fins, blks, slots);
         else hipLaunchKernelGGL(k_fin_collect_b<double>, grid, block, 0, s, c, fins, blks, slots);

@@ -32,6 +32,16 @@ __device__ __forceinline__ uint32_t mdiv_i(uint32_t n, uint32_t mul, uint32_t sh
     return (uint32_t)(((uint64_t)__umulhi(n, mul) + n) >> sh);
 }
 
+// New separator sums and partial sums, stored in table precision.
+template <typename T>
+__device__ __forceinline__ T* accp(const Ctx& c) {
+    return static_cast<T*>(c.acc);
+}
+template <typename T>
+__device__ __forceinline__ T* partp(const Ctx& c) {
+    return static_cast<T*>(c.part);
+}
+
 // Wave-uniform value in a scalar register.
 __device__ __forceinline__ uint32_t uniform(uint32_t x) { return __builtin_amdgcn_readfirstlane(x); }
 
@@ -135,7 +145,7 @@ __global__ __launch_bounds__(kBlock) void k_collect_i(Ctx c, const DGroup* __res
                         acc += (double)v[x];
                         if (--seg_left == 0) {
                             if (g.part >= 0) part += acc;
-                            else if (act) c.acc[(uint64_t)out * S + s] = acc;
+                            else if (act) accp<T>(c)[(uint64_t)out * S + s] = acc;
                             acc = 0.0;
                             out++;
                             seg_left = q.seg;
@@ -146,7 +156,7 @@ __global__ __launch_bounds__(kBlock) void k_collect_i(Ctx c, const DGroup* __res
         }
         if (g.part >= 0) part += acc;
     }
-    if (g.part >= 0 && act) c.part[(uint64_t)(uint32_t)g.part * S + s] = part;
+    if (g.part >= 0 && act) partp<T>(c)[(uint64_t)(uint32_t)g.part * S + s] = part;
 }
 
 // ---------------------------------------------------------------- distribute
@@ -206,8 +216,8 @@ __global__ __launch_bounds__(kBlock) void k_dist_i(Ctx c, const DWork* __restric
                     if (--left == 0) {
                         const uint32_t mo = bcast(mj, x0 + x);
                         if (act) {
-                            if (tg.part0 < 0) c.acc[(uint64_t)(tg.sep + mo) * S + s] = acc;
-                            else c.part[(uint64_t)((uint32_t)tg.part0 + mo * tg.nchunk + w.chunk) * S + s] = acc;
+                            if (tg.part0 < 0) accp<T>(c)[(uint64_t)(tg.sep + mo) * S + s] = acc;
+                            else partp<T>(c)[(uint64_t)((uint32_t)tg.part0 + mo * tg.nchunk + w.chunk) * S + s] = acc;
                         }
                         acc = 0.0;
                         left = per;
@@ -222,20 +232,21 @@ __global__ __launch_bounds__(kBlock) void k_dist_i(Ctx c, const DWork* __restric
 
 // Finish entry m of a separator: the sum of its partials in chunk order
 // (loaded eight at a time), or the layer kernel's whole sum.
+template <typename T>
 __device__ __forceinline__ double finish_i(const DSepFin& f, const Ctx& c, uint64_t S, uint64_t s, uint32_t m) {
-    if (!f.nchunk) return c.acc[(uint64_t)(f.sep + m) * S + s];
+    if (!f.nchunk) return accp<T>(c)[(uint64_t)(f.sep + m) * S + s];
     double v = 0.0;
     const uint64_t p0 = (uint64_t)f.part0 + (uint64_t)m * f.nchunk;
     for (uint32_t k0 = 0; k0 < f.nchunk; k0 += 8) {
         const uint32_t cnt = min(8u, f.nchunk - k0);
         double x[8];
 #pragma unroll
-        for (uint32_t y = 0; y < 8; y++) x[y] = c.part[(p0 + k0 + min(y, cnt - 1)) * S + s];
+        for (uint32_t y = 0; y < 8; y++) x[y] = partp<T>(c)[(p0 + k0 + min(y, cnt - 1)) * S + s];
 #pragma unroll
         for (uint32_t y = 0; y < 8; y++)
             if (y < cnt) v += x[y];
     }
-    c.acc[(uint64_t)(f.sep + m) * S + s] = v;
+    accp<T>(c)[(uint64_t)(f.sep + m) * S + s] = v;
     return v;
 }
 
@@ -252,9 +263,9 @@ __global__ __launch_bounds__(kBlock) void k_fin_collect_i(Ctx c, const DSepFin* 
     const DSepFin f = fins[fi];
     double mx = 0.0;
 #pragma unroll 8
-    for (uint32_t m = 0; m < f.size; m++) mx = fmax(mx, finish_i(f, c, S, s, m));
+    for (uint32_t m = 0; m < f.size; m++) mx = fmax(mx, finish_i<T>(f, c, S, s, m));
     if (f.edge < 0) {
-        if (!(c.acc[(uint64_t)f.sep * S + s] > 0.0)) atomicOr(&c.flags[s], c.fp32 ? 2 : 1);
+        if (!(accp<T>(c)[(uint64_t)f.sep * S + s] > 0.0)) atomicOr(&c.flags[s], c.fp32 ? 2 : 1);
         return;
     }
     int k = 0;
@@ -264,7 +275,7 @@ __global__ __launch_bounds__(kBlock) void k_fin_collect_i(Ctx c, const DSepFin* 
     T* __restrict__ sepc = static_cast<T*>(c.sepc);
 #pragma unroll 8
     for (uint32_t m = 0; m < f.size; m++)
-        sepc[(uint64_t)(f.sep + m) * S + s] = (T)(c.acc[(uint64_t)(f.sep + m) * S + s] * scale);
+        sepc[(uint64_t)(f.sep + m) * S + s] = (T)(accp<T>(c)[(uint64_t)(f.sep + m) * S + s] * scale);
     c.kexp[(uint64_t)f.edge * S + s] = k;
 }
 
@@ -282,7 +293,7 @@ __global__ __launch_bounds__(kBlock) void k_fin_distribute_i(Ctx c, const DSepFi
     const DSepFin f = fins[fi];
     if (f.nchunk) {
 #pragma unroll 8
-        for (uint32_t m = 0; m < f.size; m++) finish_i(f, c, S, s, m);
+        for (uint32_t m = 0; m < f.size; m++) finish_i<T>(f, c, S, s, m);
     }
     // the posterior sums go straight to the marginal accumulators
     for (uint32_t a = 0; a < f.nmv; a++) {
@@ -292,7 +303,7 @@ __global__ __launch_bounds__(kBlock) void k_fin_distribute_i(Ctx c, const DSepFi
             double acc = 0.0;
             for (uint32_t m = x * mv.stride; m < f.size; m += span) {
 #pragma unroll 8
-                for (uint32_t y = m; y < m + mv.stride; y++) acc += c.acc[(uint64_t)(f.sep + y) * S + s];
+                for (uint32_t y = m; y < m + mv.stride; y++) acc += accp<T>(c)[(uint64_t)(f.sep + y) * S + s];
             }
             c.marg[(uint64_t)(mv.out + x) * S + s] = acc;
         }
@@ -304,7 +315,7 @@ __global__ __launch_bounds__(kBlock) void k_fin_distribute_i(Ctx c, const DSepFi
 #pragma unroll 8
     for (uint32_t m = 0; m < f.size; m++) {
         const double den = (double)sepc[(uint64_t)(f.sep + m) * S + s];
-        mx = fmax(mx, den == 0.0 ? 0.0 : c.acc[(uint64_t)(f.sep + m) * S + s] / den);
+        mx = fmax(mx, den == 0.0 ? 0.0 : accp<T>(c)[(uint64_t)(f.sep + m) * S + s] / den);
     }
     int k = 0;
     if (mx > 0.0) frexp(mx, &k);
@@ -313,7 +324,7 @@ __global__ __launch_bounds__(kBlock) void k_fin_distribute_i(Ctx c, const DSepFi
     for (uint32_t m = 0; m < f.size; m++) {
         const uint64_t x = (uint64_t)(f.sep + m) * S + s;
         const double den = (double)sepc[x];
-        sepd[x] = (T)((den == 0.0 ? 0.0 : c.acc[x] / den) * scale);
+        sepd[x] = (T)((den == 0.0 ? 0.0 : accp<T>(c)[x] / den) * scale);
     }
 }
 
@@ -334,6 +345,7 @@ __device__ __forceinline__ double fin_max_i(const Ctx& c, const DFinBlk& b, uint
     return c.bmax[(uint64_t)b.blk0 * S + s];
 }
 
+template <typename T>
 __global__ __launch_bounds__(kBlock) void k_fin_collect_ia(Ctx c, const DSepFin* __restrict__ fins,
                                                            const DFinBlk* __restrict__ blks, uint32_t nblks,
                                                            const int32_t* __restrict__ slots, int nslots) {
@@ -346,7 +358,7 @@ __global__ __launch_bounds__(kBlock) void k_fin_collect_ia(Ctx c, const DSepFin*
     const DSepFin f = fins[b.fin];
     double mx = 0.0;
 #pragma unroll 8
-    for (uint32_t m = b.begin; m < b.begin + b.count; m++) mx = fmax(mx, finish_i(f, c, S, s, m));
+    for (uint32_t m = b.begin; m < b.begin + b.count; m++) mx = fmax(mx, finish_i<T>(f, c, S, s, m));
     fold_max(c, b, S, s, mx);
 }
 
@@ -370,7 +382,7 @@ __global__ __launch_bounds__(kBlock) void k_fin_collect_ib(Ctx c, const DSepFin*
 #pragma unroll 8
     for (uint32_t m = b.begin; m < b.begin + b.count; m++) {
         const uint64_t x = (uint64_t)(f.sep + m) * S + s;
-        sepc[x] = (T)(c.acc[x] * scale);
+        sepc[x] = (T)(accp<T>(c)[x] * scale);
     }
     if (b.begin == 0) c.kexp[(uint64_t)f.edge * S + s] = k;
 }
@@ -394,7 +406,7 @@ __global__ __launch_bounds__(kBlock) void k_fin_distribute_ia(Ctx c, const DSepF
     double mx = 0.0;
 #pragma unroll 8
     for (uint32_t m = b.begin; m < b.begin + b.count; m++) {
-        const double v = finish_i(f, c, S, s, m);
+        const double v = finish_i<T>(f, c, S, s, m);
         const double den = (double)sepc[(uint64_t)(f.sep + m) * S + s];
         mx = fmax(mx, den == 0.0 ? 0.0 : v / den);
     }
@@ -406,7 +418,7 @@ __global__ __launch_bounds__(kBlock) void k_fin_distribute_ia(Ctx c, const DSepF
     double(*pa)[kLanes] = post_acc[threadIdx.x / kLanes];
     double* __restrict__ bm = c.bmarg;
     const uint64_t o0 = (uint64_t)b.mbase + (uint64_t)(b.id - b.blk0) * b.mw;
-    const double* __restrict__ acc = c.acc;
+    const T* __restrict__ acc = accp<T>(c);
     uint32_t vo = 0;
     for (uint32_t a = 0; a < f.nmv; a++) {
         const DMargVar mv = c.mv[f.mv0 + a];
@@ -463,7 +475,7 @@ __global__ __launch_bounds__(kBlock) void k_fin_distribute_ib(Ctx c, const DSepF
     for (uint32_t m = b.begin; m < b.begin + b.count; m++) {
         const uint64_t x = (uint64_t)(f.sep + m) * S + s;
         const double den = (double)sepc[x];
-        sepd[x] = (T)((den == 0.0 ? 0.0 : c.acc[x] / den) * scale);
+        sepd[x] = (T)((den == 0.0 ? 0.0 : accp<T>(c)[x] / den) * scale);
     }
     // posterior sums: block j of the separator adds sums j, j + nblk, ...
     const uint32_t j = b.id - b.blk0;
@@ -508,7 +520,8 @@ __global__ __launch_bounds__(kBlock) void k_marginals_i(Ctx c, const int32_t* __
     if (wi != 0) return;
     double lg = 0.0;
     for (uint32_t r = 0; r < c.nroots; r++) {
-        const double z = c.acc[(uint64_t)(c.sep_total + r) * S + s];
+        const uint64_t zi = (uint64_t)(c.sep_total + r) * S + s;
+        const double z = c.fp32 ? (double)static_cast<const float*>(c.acc)[zi] : static_cast<const double*>(c.acc)[zi];
         lg += z > 0.0 ? log(z) : -INFINITY;
     }
     long long ks = 0;
@@ -546,7 +559,8 @@ hipError_t launch_interleaved(const Ctx& c, int prec, int kind, const void* item
         else hipLaunchKernelGGL(k_fin_distribute_i<double>, grid, block, 0, st, c, sfins, nitems, slots, nslots);
         break;
     case kIlFinCollectA:
-        hipLaunchKernelGGL(k_fin_collect_ia, grid, block, 0, st, c, fins, blks, nitems, slots, nslots);
+        if (prec) hipLaunchKernelGGL(k_fin_collect_ia<float>, grid, block, 0, st, c, fins, blks, nitems, slots, nslots);
+        else hipLaunchKernelGGL(k_fin_collect_ia<double>, grid, block, 0, st, c, fins, blks, nitems, slots, nslots);
         break;
     case kIlFinCollectB:
         if (prec) hipLaunchKernelGGL(k_fin_collect_ib<float>, grid, block, 0, st, c, fins, blks, nitems, slots, nslots);
