@@ -44,11 +44,17 @@ def log(*a):
 
 
 def sources_sha256():
+    """Hash of the kernel sources' code: comments and blank lines removed, so
+    that only a change to the code itself invalidates recorded counters."""
     import hashlib
+    import re
     h = hashlib.sha256()
     for f in KERNEL_SOURCES:
-        with open(os.path.join(ROOT, f), "rb") as fh:
-            h.update(fh.read())
+        with open(os.path.join(ROOT, f)) as fh:
+            for line in fh:
+                line = re.sub(r"//.*$", "", line).rstrip()
+                if line:
+                    h.update(line.encode() + b"\n")
     return h.hexdigest()
 
 
@@ -105,7 +111,7 @@ class Workload:
     all of them and one slot carries one case of every network, so a slot
     answers len(nets) queries."""
 
-    def __init__(self, key):
+    def __init__(self, key, n_cases=None):
         import fbngen
         self.key = key
         cfg = fbngen.CONFIGS[key]
@@ -117,6 +123,8 @@ class Workload:
         else:
             self.nets = [fbngen.make_net(key, 0)]
             self.cases = [fbngen.make_cases(key, self.nets[0])]
+            if n_cases:
+                self.cases[0] = self.cases[0][:n_cases]
             self.slot_cases = self.cases[0]
         self.per_slot = len(self.nets)
         self.marg_off = np.concatenate([[0], np.cumsum([int(np.sum(n.card)) for n in self.nets])]).astype(int)
@@ -440,6 +448,7 @@ def main():
     ap.add_argument("--tile", type=int, default=0, help="table entries per work item (0: the library default)")
     ap.add_argument("--no-tune", action="store_true",
                     help="skip the autotuner (layout and tile from --layout / --tile)")
+    ap.add_argument("--cases", type=int, default=0, help="single-network workloads: the first N cases only")
     ap.add_argument("--trace", type=int, default=4096, help="C5: trace queries")
     ap.add_argument("--budget-gb", type=float, default=32.0, help="C5: device-memory budget, GiB")
     ap.add_argument("--max-batch", type=int, default=32, help="C5: slots per resident tree at most")
@@ -455,7 +464,7 @@ def main():
     key = args.workload
     if key == "C5":
         return bench_served(args, fbn)
-    W = Workload(key)
+    W = Workload(key, args.cases or None)
     n = len(W.slot_cases)
     q = n * W.per_slot
     log(f"[bench] {key}: {len(W.nets)} network(s), {sum(x.n for x in W.nets)} variables, {n} slots, "

@@ -26,8 +26,9 @@
 // reused for every slot, and the per-slot gathers are independent loads in
 // flight together.  Tables stream through HBM in coalesced runs of
 // consecutive entries; index maps come from small factored tables
-// (H[hi] + L[lo]) that stay in cache; separator sums and scale factors are
-// float64.  No atomics on data, so a case gives bitwise the same result
+// (H[hi] + L[lo]) that stay in cache; separator sums are accumulated in
+// float64 and stored in table precision, scale factors are exact powers of
+// two.  No atomics on data, so a case gives bitwise the same result
 // alone or in any batch.
 #include <hip/hip_runtime.h>
 
