@@ -189,6 +189,10 @@ fbn_status fbn_fetch_async(fbn_jt* jt, int32_t n_slots, const int32_t* slots, do
  * resets the counters.  Arrays have FBN_PROFILE_KINDS entries. */
 enum { FBN_PROFILE_KINDS = 5 };
 fbn_status fbn_jt_profile_enable(fbn_jt* jt, int32_t on);
+/* Which kinds are timed while profiling is on: bit k for kind k (default all,
+ * 0x1f).  Launches of other kinds get no events, so a run timing one kind
+ * pays for one event pair per launch of that kind only. */
+fbn_status fbn_jt_profile_kinds(fbn_jt* jt, uint32_t mask);
 fbn_status fbn_jt_profile_read(fbn_jt* jt, double* ms, int64_t* launches, double* bytes);
 
 const char* fbn_status_str(fbn_status s);

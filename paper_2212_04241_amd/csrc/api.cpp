@@ -238,6 +238,7 @@ struct fbn_jt {
         double bytes;
     };
     bool prof = false;
+    uint32_t prof_mask = (1u << FBN_PROFILE_KINDS) - 1;
     std::vector<Rec> recs;
     std::vector<hipEvent_t> pool;
     double prof_ms[FBN_PROFILE_KINDS] = {}, prof_bytes[FBN_PROFILE_KINDS] = {};
@@ -494,7 +495,7 @@ fbn_status stage_slots(fbn_jt* jt, int32_t n, const int32_t* slots) {
 
 template <class F>
 fbn_status timed(fbn_jt* jt, int kind, double bytes, F launch) {
-    if (!jt->prof) {
+    if (!jt->prof || !((jt->prof_mask >> kind) & 1u)) {
         HIP_OK(launch());
         return FBN_OK;
     }
@@ -1151,6 +1152,13 @@ fbn_status fbn_jt_profile_enable(fbn_jt* jt, int32_t on) {
     if (!jt) return fail(FBN_E_INVALID_ARG, "null jt");
     if (jt->opt.host_only) return fail(FBN_E_STATE, "host-only jt");
     jt->prof = on != 0;
+    return FBN_OK;
+}
+
+fbn_status fbn_jt_profile_kinds(fbn_jt* jt, uint32_t mask) {
+    if (!jt) return fail(FBN_E_INVALID_ARG, "null jt");
+    if (mask >> FBN_PROFILE_KINDS) return fail(FBN_E_INVALID_ARG, "unknown profile kind");
+    jt->prof_mask = mask;
     return FBN_OK;
 }
 

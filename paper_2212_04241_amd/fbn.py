@@ -98,6 +98,7 @@ def lib():
         "fbn_jt_device_index_map": (C.c_int32, [C.c_void_p, C.c_int32, i32p, C.c_size_t]),
         "fbn_jt_profile_enable": (C.c_int32, [C.c_void_p, C.c_int32]),
         "fbn_jt_profile_read": (C.c_int32, [C.c_void_p, f64p, P(C.c_int64), f64p]),
+        "fbn_jt_profile_kinds": (C.c_int32, [C.c_void_p, C.c_uint32]),
         "fbn_jt_elim_order": (C.c_int32, [C.c_void_p, i32p]),
         "fbn_jt_homes": (C.c_int32, [C.c_void_p, i32p, i32p]),
     }
@@ -351,6 +352,12 @@ PROFILE_KINDS = ("collect", "collect_finalise", "distribute", "distribute_finali
 
 def jt_profile_enable(jt: JT, on: bool = True) -> None:
     _check(lib().fbn_jt_profile_enable(jt._h, 1 if on else 0), "fbn_jt_profile_enable")
+
+
+def jt_profile_kinds(jt: JT, kinds=None) -> None:
+    """Time only the named kinds (None: all) while profiling is on."""
+    mask = (1 << len(PROFILE_KINDS)) - 1 if kinds is None else sum(1 << PROFILE_KINDS.index(k) for k in kinds)
+    _check(lib().fbn_jt_profile_kinds(jt._h, mask), "fbn_jt_profile_kinds")
 
 
 def jt_profile_read(jt: JT) -> dict:
