@@ -323,6 +323,40 @@ __device__ __forceinline__ bool team_of(uint32_t nbig, uint32_t nfins, double* r
     return fi < nfins;
 }
 
+// Finish the entries [b, e) of separator f (acc and part offset to the
+// separator): an entry whose sum was split over chunks gets its partials
+// added by tpe lanes of one wave (a power of two, about four partials per
+// lane), combined by a fixed xor-shuffle tree, and stored; fn(m, v) is then
+// called once per entry, v its finished value.  t is the thread's index in
+// its team of nt threads (a wave or a workgroup); every thread of the team
+// must make the call.
+template <typename T, typename F>
+__device__ __forceinline__ void finish_range(const DSepFin& f, T* acc, const T* part, uint32_t b, uint32_t e,
+                                             uint32_t t, uint32_t nt, F fn) {
+    if (!f.nchunk) {
+        for (uint32_t m = b + t; m < e; m += nt) fn(m, (double)acc[m]);
+        return;
+    }
+    uint32_t tpe = 1;
+    while (tpe < (uint32_t)kWave && tpe * 4 < f.nchunk) tpe *= 2;
+    const uint32_t lane = t & (kWave - 1), wv = t / kWave, nw = nt / kWave;
+    const uint32_t epw = (uint32_t)kWave / tpe, sub = lane & (tpe - 1), eo = lane / tpe;
+    for (uint32_t m0 = b + wv * epw; m0 < e; m0 += nw * epw) {
+        const uint32_t m = m0 + eo;
+        double v = 0.0;
+        if (m < e) {
+            const T* pp = part + (uint64_t)m * f.nchunk;
+#pragma unroll 4
+            for (uint32_t k = sub; k < f.nchunk; k += tpe) v += pp[k];
+        }
+        for (uint32_t o = tpe / 2; o > 0; o >>= 1) v += __shfl_xor(v, (int)o, kWave);
+        if (m < e && sub == 0) {
+            acc[m] = (T)v;
+            fn(m, v);
+        }
+    }
+}
+
 // After a collect layer, per separator: finish the message (sum partial
 // sums where a segment spanned several tiles), rescale it by an exact power
 // of two so its largest entry lies in [0.5, 1), store it in table precision
@@ -343,19 +377,9 @@ __global__ __launch_bounds__(kBlock) void k_fin_collect(Ctx c, const DSepFin* __
     int32_t* kexp = c.kexp + (uint64_t)slot * c.kexp_stride;
 
     double mx = 0.0;
-#pragma unroll 4
-    for (uint32_t m = lane; m < f.size; m += tm.size) {
-        double v;
-        if (f.nchunk) {
-            v = 0.0;
-            const T* pp = part + f.part0 + (uint64_t)m * f.nchunk;
-            for (uint32_t k = 0; k < f.nchunk; k++) v += pp[k];
-            acc[f.sep + m] = (T)v;
-        } else {
-            v = acc[f.sep + m];
-        }
-        mx = fmax(mx, v);
-    }
+    finish_range(f, acc + f.sep, part + f.part0, 0u, f.size, lane, tm.size,
+                 [&](uint32_t, double v) { mx = fmax(mx, v); });
+    if (f.nchunk) tm.sync();  // other lanes rescale these sums below
     mx = tm.max(mx);
 
     if (f.edge < 0) {
@@ -582,13 +606,7 @@ __global__ __launch_bounds__(kBlock) void k_fin_distribute(Ctx c, const DSepFin*
     T* __restrict__ acc = static_cast<T*>(c.acc) + (uint64_t)slot * c.sep_stride;
     const T* __restrict__ part = static_cast<const T*>(c.part) + (uint64_t)slot * c.part_stride;
     if (f.nchunk) {
-    #pragma unroll 4
-    for (uint32_t m = lane; m < f.size; m += tm.size) {
-            double v = 0.0;
-            const T* pp = part + f.part0 + (uint64_t)m * f.nchunk;
-            for (uint32_t k = 0; k < f.nchunk; k++) v += pp[k];
-            acc[f.sep + m] = (T)v;
-        }
+        finish_range(f, acc + f.sep, part + f.part0, 0u, f.size, lane, tm.size, [](uint32_t, double) {});
         tm.sync();  // other lanes of the team read these sums below
     }
     // posteriors: each state of each assigned variable is a team-wide sum
@@ -651,18 +669,6 @@ __device__ __forceinline__ double block_max_all(double v, double* scratch) {
     return s;
 }
 
-// Finish entry m of a separator: the sum of its partials, or the layer
-// kernel's whole sum.
-template <typename T>
-__device__ __forceinline__ double finish_entry(const DSepFin& f, T* acc, const T* part, uint32_t m) {
-    if (!f.nchunk) return acc[m];
-    const T* pp = part + (uint64_t)m * f.nchunk;
-    double v = 0.0;
-    for (uint32_t k = 0; k < f.nchunk; k++) v += pp[k];
-    acc[m] = (T)v;
-    return v;
-}
-
 // Separator maximum over the blocks of b's separator.
 __device__ __forceinline__ double fin_max(const Ctx& c, const DFinBlk& b, int slot, double* red) {
     const double* bm = c.bmax + (uint64_t)slot * c.bmax_stride + b.blk0;
@@ -682,9 +688,8 @@ __global__ __launch_bounds__(kBlock) void k_fin_collect_a(Ctx c, const DSepFin* 
     T* __restrict__ acc = static_cast<T*>(c.acc) + (uint64_t)slot * c.sep_stride + f.sep;
     const T* __restrict__ part = static_cast<const T*>(c.part) + (uint64_t)slot * c.part_stride + f.part0;
     double mx = 0.0;
-#pragma unroll 4
-    for (uint32_t m = b.begin + threadIdx.x; m < b.begin + b.count; m += kBlock)
-        mx = fmax(mx, finish_entry(f, acc, part, m));
+    finish_range(f, acc, part, b.begin, b.begin + b.count, threadIdx.x, (uint32_t)kBlock,
+                 [&](uint32_t, double v) { mx = fmax(mx, v); });
     mx = block_max_all(mx, red);
     if (threadIdx.x == 0) c.bmax[(uint64_t)slot * c.bmax_stride + b.id] = mx;
 }
@@ -731,13 +736,11 @@ __global__ __launch_bounds__(kBlock) void k_fin_distribute_a(Ctx c, const DSepFi
     const T* __restrict__ part = static_cast<const T*>(c.part) + (uint64_t)slot * c.part_stride + f.part0;
     const T* __restrict__ sepc = static_cast<const T*>(c.sepc) + (uint64_t)slot * c.sep_stride + f.sep;
     double mx = 0.0;
-#pragma unroll 4
-    for (uint32_t m = b.begin + threadIdx.x; m < b.begin + b.count; m += kBlock) {
-        const double v = finish_entry(f, acc, part, m);
+    finish_range(f, acc, part, b.begin, b.begin + b.count, threadIdx.x, (uint32_t)kBlock, [&](uint32_t m, double v) {
         vals[m - b.begin] = v;
         const double den = (double)sepc[m];
         mx = fmax(mx, den == 0.0 ? 0.0 : v / den);
-    }
+    });
     mx = block_max_all(mx, red);  // (its barriers also publish vals)
     if (threadIdx.x == 0) c.bmax[(uint64_t)slot * c.bmax_stride + b.id] = mx;
     // this block's share of each posterior sum: the entries with digit x

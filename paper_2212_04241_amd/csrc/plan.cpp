@@ -102,7 +102,12 @@ uint32_t enumerate(const std::vector<int>& pos, const std::vector<int>& card_at,
     return start;
 }
 
-bool is_big(const Plan& p, const DSepFin& f) { return f.size > p.big_separator && f.edge >= 0; }
+// Finalised in blocks: a real separator above the size threshold, or any
+// real or one-variable separator whose entries add many partial sums.
+bool is_big(const Plan& p, const DSepFin& f) {
+    if (f.edge == -1) return false;
+    return (f.size > p.big_separator && f.edge >= 0) || (uint64_t)f.size * f.nchunk > kFinWork;
+}
 
 // Partition a layer's finalisers large-first and split each large one into
 // near-equal blocks of at most kFinBlock entries.
@@ -116,7 +121,10 @@ void finish_layer(Plan& p, Layer& ly, std::vector<DSepFin>& fins) {
     ly.fb0 = (uint32_t)p.finblks.size();
     for (uint32_t f = ly.fin0; f < ly.fin0 + ly.nbig; f++) {
         const DSepFin F = p.fins[f];
-        const uint32_t nblk = (F.size + p.fin_block - 1) / p.fin_block;
+        // entries per block: at most fin_block, and at most kFinWork partial sums
+        const uint32_t per = (uint32_t)std::max<uint64_t>(
+            1, std::min<uint64_t>(p.fin_block, kFinWork / std::max<uint32_t>(F.nchunk, 1)));
+        const uint32_t nblk = (F.size + per - 1) / per;
         uint32_t mw = 0;
         for (uint32_t k = 0; k < F.nmv; k++) mw += p.margvars[F.mv0 + k].card;
         const uint32_t blk0 = (uint32_t)p.finblks.size();
