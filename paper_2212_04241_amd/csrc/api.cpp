@@ -951,8 +951,8 @@ static fbn_status enqueue_calibration(fbn_jt* jt, int32_t n) {
             const DSepFin* f = jt->d_fins + ly.fin0 + ly.nbig;
             const uint32_t nf = ly.nfin - ly.nbig;
             if ((r = timed(jt, kind, bytes, [&] {
-                     return dist ? launch_fin_distribute(c, prec, f, nf, 0, jt->d_slots, n, s)
-                                 : launch_fin_collect(c, prec, f, nf, 0, jt->d_slots, n, s);
+                     return dist ? launch_fin_distribute(c, prec, f, nf, ly.nteam, jt->d_slots, n, s)
+                                 : launch_fin_collect(c, prec, f, nf, ly.nteam, jt->d_slots, n, s);
                  })))
                 return r;
             bytes = 0.0;

@@ -117,6 +117,11 @@ void finish_layer(Plan& p, Layer& ly, std::vector<DSepFin>& fins) {
     ly.fin0 = (uint32_t)p.fins.size();
     ly.nfin = (uint32_t)fins.size();
     ly.nbig = (uint32_t)std::count_if(fins.begin(), fins.end(), big);
+    // after the large ones, those that get a workgroup team
+    std::stable_partition(fins.begin() + ly.nbig, fins.end(),
+                          [](const DSepFin& f) { return f.size > kTeamSeparator; });
+    ly.nteam = (uint32_t)std::count_if(fins.begin() + ly.nbig, fins.end(),
+                                       [](const DSepFin& f) { return f.size > kTeamSeparator; });
     p.fins.insert(p.fins.end(), fins.begin(), fins.end());
     ly.fb0 = (uint32_t)p.finblks.size();
     for (uint32_t f = ly.fin0; f < ly.fin0 + ly.nbig; f++) {
@@ -277,6 +282,7 @@ std::string check_plan(const Tree& t, const Plan& p) {
     for (const std::vector<Layer>* sweep : {&p.collect, &p.distribute})
         for (const Layer& ly : *sweep) {
             if (ly.nbig > ly.nfin || (uint64_t)ly.fb0 + ly.nfb > p.finblks.size()) return "layer fin blocks";
+            if ((uint64_t)ly.nbig + ly.nteam > ly.nfin) return "layer fin teams";
             uint32_t b = ly.fb0;
             for (uint32_t f = ly.fin0; f < ly.fin0 + ly.nfin; f++) {
                 const DSepFin& F = p.fins[f];

@@ -11,11 +11,13 @@ struct Layer {
     uint32_t fin0 = 0, nfin = 0;      // into Plan::fins (separators finalised after it)
     uint32_t nbig = 0;                // the first nbig fins are large: split over Plan::finblks
     uint32_t fb0 = 0, nfb = 0;        // their blocks, into Plan::finblks
+    uint32_t nteam = 0;               // the next nteam fins get a workgroup each, the rest a wave
 };
 
 constexpr uint32_t kBigSeparator = 1024;  // entries above which a separator is split into blocks
 constexpr uint32_t kBigSeparatorInterleaved = 64;  // the same with slot-interleaved tables
 constexpr uint64_t kFinWork = 16384;  // partial sums one finaliser block adds at most (entries x chunks)
+constexpr uint32_t kTeamSeparator = 256;  // separators above this get a workgroup rather than a wave
 
 struct Plan {
     int tile = 2048;
