@@ -106,7 +106,7 @@ uint32_t enumerate(const std::vector<int>& pos, const std::vector<int>& card_at,
 // real or one-variable separator whose entries add many partial sums.
 bool is_big(const Plan& p, const DSepFin& f) {
     if (f.edge == -1) return false;
-    return (f.size > p.big_separator && f.edge >= 0) || (uint64_t)f.size * f.nchunk > kFinWork;
+    return (f.size > p.big_separator && f.edge >= 0) || (uint64_t)f.size * f.nchunk > p.fin_work;
 }
 
 // Partition a layer's finalisers large-first and split each large one into
@@ -128,7 +128,7 @@ void finish_layer(Plan& p, Layer& ly, std::vector<DSepFin>& fins) {
         const DSepFin F = p.fins[f];
         // entries per block: at most fin_block, and at most kFinWork partial sums
         const uint32_t per = (uint32_t)std::max<uint64_t>(
-            1, std::min<uint64_t>(p.fin_block, kFinWork / std::max<uint32_t>(F.nchunk, 1)));
+            1, std::min<uint64_t>(p.fin_block, p.fin_work / std::max<uint32_t>(F.nchunk, 1)));
         const uint32_t nblk = (F.size + per - 1) / per;
         uint32_t mw = 0;
         for (uint32_t k = 0; k < F.nmv; k++) mw += p.margvars[F.mv0 + k].card;
@@ -335,6 +335,7 @@ void build_plan(const Tree& t, int tile, uint32_t max_stage, Plan& p, bool inter
     p.interleaved = interleaved;
     p.fin_block = interleaved ? kFinBlockInterleaved : kFinBlock;
     p.big_separator = interleaved ? kBigSeparatorInterleaved : kBigSeparator;
+    p.fin_work = interleaved ? kFinWorkInterleaved : kFinWork;
     max_stage = std::min<uint32_t>(std::max<uint32_t>(max_stage, 64), (uint32_t)kTileMax);
     p.max_stage = max_stage;
     if (tile <= 0) tile = 2048;

@@ -17,6 +17,7 @@ struct Layer {
 constexpr uint32_t kBigSeparator = 1024;  // entries above which a separator is split into blocks
 constexpr uint32_t kBigSeparatorInterleaved = 64;  // the same with slot-interleaved tables
 constexpr uint64_t kFinWork = 16384;  // partial sums one finaliser block adds at most (entries x chunks)
+constexpr uint64_t kFinWorkInterleaved = 1024;  // the same when one lane adds them all
 constexpr uint32_t kTeamSeparator = 256;  // separators above this get a workgroup rather than a wave
 
 struct Plan {
@@ -24,6 +25,7 @@ struct Plan {
     bool interleaved = false;         // slot-interleaved tables: one wave per work item, lanes = slots
     uint32_t fin_block = kFinBlock;   // separator entries per finaliser block
     uint32_t big_separator = kBigSeparator;  // larger real separators are finalised in blocks
+    uint64_t fin_work = kFinWork;     // partial sums per finaliser block at most
     uint32_t stage = 0;               // LDS entries per slot: largest collect tile or distribute block
     uint32_t max_stage = 0;           // bound on stage
     uint64_t T = 0;                   // prior / working-table entries
