@@ -685,9 +685,9 @@ static fbn_status build_jt_impl(const std::vector<const fbn_net*>& nets, const f
             jt->tree = merge_forest(parts);
         }
         // default tile: 8 KB of table per slot, so four slots share a workgroup
-        // interleaved: one wave per work item, 128 entries each by default
+        // interleaved: one wave per work item, 64 entries each by default
         const bool il = opt.layout == FBN_LAYOUT_INTERLEAVED;
-        const int def_tile = il ? 128 : (opt.precision == FBN_FP32_RESCALED ? 1024 : 512);
+        const int def_tile = il ? 64 : (opt.precision == FBN_FP32_RESCALED ? 1024 : 512);
         const uint32_t max_stage = (uint32_t)kStageBytes / (opt.precision == FBN_FP32_RESCALED ? 4u : 8u);
         build_plan(jt->tree, opt.tile_entries ? opt.tile_entries : def_tile, max_stage, jt->plan, il);
         const std::string bad = check_plan(jt->tree, jt->plan);

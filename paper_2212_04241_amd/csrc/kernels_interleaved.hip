@@ -586,7 +586,7 @@ hipError_t launch_interleaved(const Ctx& c, int prec, int kind, const void* item
 
 hipError_t launch_marginals_interleaved(const Ctx& c, const int32_t* slots, int nslots, hipStream_t st) {
     if (!nslots) return hipSuccess;
-    const uint32_t per = 64;  // variables per wave
+    const uint32_t per = 16;  // variables per wave
     const uint32_t waves = ((uint32_t)c.nvars + per - 1) / per;
     const dim3 grid(std::max<uint32_t>(1u, (waves + kWavesPerBlock - 1) / kWavesPerBlock),
                     (unsigned)((nslots + kLanes - 1) / kLanes));
