@@ -230,8 +230,47 @@ __global__ __launch_bounds__(kBlock) void k_dist_i(Ctx c, const DWork* __restric
 
 // --------------------------------------------------------------- finalisers
 
-// Finish entry m of a separator: the sum of its partials in chunk order
-// (loaded eight at a time), or the layer kernel's whole sum.
+// Finish the entries [b, e) of separator f: with partial sums, an entry's
+// value is the sum of its chunks in order.  The partials of consecutive
+// entries are contiguous, so the whole range is read as one run, eight
+// loads in flight, each entry's sum closed and stored as its last chunk
+// comes in.  fn(m, v) is called once per entry in entry order.
+template <typename T, typename F>
+__device__ __forceinline__ void finish_range_i(const DSepFin& f, const Ctx& c, uint64_t S, uint64_t s, uint32_t b,
+                                               uint32_t e, F fn) {
+    T* __restrict__ acc = accp<T>(c);
+    if (!f.nchunk) {
+#pragma unroll 8
+        for (uint32_t m = b; m < e; m++) fn(m, (double)acc[(uint64_t)(f.sep + m) * S + s]);
+        return;
+    }
+    const T* __restrict__ part = partp<T>(c);
+    const uint64_t q0 = (uint64_t)f.part0 + (uint64_t)b * f.nchunk;
+    const uint64_t q1 = (uint64_t)f.part0 + (uint64_t)e * f.nchunk;
+    double v = 0.0;
+    uint32_t m = b, left = f.nchunk;
+    for (uint64_t q = q0; q < q1; q += 8) {
+        double x[8];
+#pragma unroll
+        for (uint32_t y = 0; y < 8; y++) x[y] = part[min(q + y, q1 - 1) * S + s];
+#pragma unroll
+        for (uint32_t y = 0; y < 8; y++) {
+            if (q + y < q1) {
+                v += x[y];
+                if (--left == 0) {
+                    acc[(uint64_t)(f.sep + m) * S + s] = (T)v;
+                    fn(m, v);
+                    v = 0.0;
+                    left = f.nchunk;
+                    m++;
+                }
+            }
+        }
+    }
+}
+
+// Finish entry m alone: the sum of its partials in chunk order (loaded
+// eight at a time), or the layer kernel's whole sum.
 template <typename T>
 __device__ __forceinline__ double finish_i(const DSepFin& f, const Ctx& c, uint64_t S, uint64_t s, uint32_t m) {
     if (!f.nchunk) return accp<T>(c)[(uint64_t)(f.sep + m) * S + s];
@@ -246,7 +285,7 @@ __device__ __forceinline__ double finish_i(const DSepFin& f, const Ctx& c, uint6
         for (uint32_t y = 0; y < 8; y++)
             if (y < cnt) v += x[y];
     }
-    accp<T>(c)[(uint64_t)(f.sep + m) * S + s] = v;
+    accp<T>(c)[(uint64_t)(f.sep + m) * S + s] = (T)v;
     return v;
 }
 
@@ -262,8 +301,7 @@ __global__ __launch_bounds__(kBlock) void k_fin_collect_i(Ctx c, const DSepFin* 
     const uint64_t S = c.S, s = (uint64_t)sl;
     const DSepFin f = fins[fi];
     double mx = 0.0;
-#pragma unroll 8
-    for (uint32_t m = 0; m < f.size; m++) mx = fmax(mx, finish_i<T>(f, c, S, s, m));
+    finish_range_i<T>(f, c, S, s, 0u, f.size, [&](uint32_t, double v) { mx = fmax(mx, v); });
     if (f.edge < 0) {
         if (!(accp<T>(c)[(uint64_t)f.sep * S + s] > 0.0)) atomicOr(&c.flags[s], c.fp32 ? 2 : 1);
         return;
@@ -357,8 +395,7 @@ __global__ __launch_bounds__(kBlock) void k_fin_collect_ia(Ctx c, const DSepFin*
     const DFinBlk b = blks[bi];
     const DSepFin f = fins[b.fin];
     double mx = 0.0;
-#pragma unroll 8
-    for (uint32_t m = b.begin; m < b.begin + b.count; m++) mx = fmax(mx, finish_i<T>(f, c, S, s, m));
+    finish_range_i<T>(f, c, S, s, b.begin, b.begin + b.count, [&](uint32_t, double v) { mx = fmax(mx, v); });
     fold_max(c, b, S, s, mx);
 }
 
