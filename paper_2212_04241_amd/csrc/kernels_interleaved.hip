@@ -424,16 +424,21 @@ __global__ __launch_bounds__(kBlock) void k_fin_collect_ib(Ctx c, const DSepFin*
     if (b.begin == 0) c.kexp[(uint64_t)f.edge * S + s] = k;
 }
 
-constexpr uint32_t kPostChunk = 16;  // posterior states accumulated per pass
+// Entries m < n of a separator whose digit of a variable (stride, card) is x:
+// whole periods of stride * card entries hold stride each.
+__device__ __forceinline__ uint32_t digit_below_i(uint32_t n, uint32_t stride, uint32_t card, uint32_t x) {
+    const uint32_t span = stride * card;
+    const uint32_t r = n % span;
+    const uint32_t lo = x * stride;
+    return (n / span) * stride + (r > lo ? min(r - lo, stride) : 0u);
+}
 
 template <typename T>
 __global__ __launch_bounds__(kBlock) void k_fin_distribute_ia(Ctx c, const DSepFin* __restrict__ fins,
                                                               const DFinBlk* __restrict__ blks, uint32_t nblks,
                                                               const int32_t* __restrict__ slots, int nslots) {
-    __shared__ double post_acc[kWavesPerBlock][kPostChunk][kLanes];
     const uint32_t bi = wave_item();
     if (bi >= nblks) return;
-    const uint32_t lane = threadIdx.x & (kLanes - 1);
     const int sl = lane_slot(slots, nslots);
     if (sl < 0) return;
     const uint64_t S = c.S, s = (uint64_t)sl;
@@ -448,44 +453,26 @@ __global__ __launch_bounds__(kBlock) void k_fin_distribute_ia(Ctx c, const DSepF
         mx = fmax(mx, den == 0.0 ? 0.0 : v / den);
     }
     fold_max(c, b, S, s, mx);
-    // this block's share of each posterior sum: one pass per variable and
-    // run of at most kPostChunk states; consecutive entries with the same
-    // digit are summed in a register and added to the state's LDS cell
-    // (one column per lane) when the digit changes
-    double(*pa)[kLanes] = post_acc[threadIdx.x / kLanes];
+    // this block's share of each posterior sum: for each state x of each
+    // variable, the block's entries with digit x, m = (o * card + x) *
+    // stride + r, enumerated by e = o * stride + r between the counts of
+    // such entries below the block's ends
     double* __restrict__ bm = c.bmarg;
     const uint64_t o0 = (uint64_t)b.mbase + (uint64_t)(b.id - b.blk0) * b.mw;
     const T* __restrict__ acc = accp<T>(c);
     uint32_t vo = 0;
     for (uint32_t a = 0; a < f.nmv; a++) {
         const DMargVar mv = c.mv[f.mv0 + a];
-        for (uint32_t x0 = 0; x0 < mv.card; x0 += kPostChunk) {
-            const uint32_t nx = min(kPostChunk, mv.card - x0);
-            for (uint32_t x = 0; x < nx; x++) pa[x][lane] = 0.0;
-            double run = 0.0;
-            uint32_t cur = 0xffffffffu;
-            for (uint32_t m0 = b.begin; m0 < b.begin + b.count; m0 += 8) {
-                const uint32_t cnt = min(8u, b.begin + b.count - m0);
-                double v[8];
-#pragma unroll
-                for (uint32_t y = 0; y < 8; y++)
-                    v[y] = acc[(uint64_t)(f.sep + m0 + min(y, cnt - 1)) * S + s];
-#pragma unroll
-                for (uint32_t y = 0; y < 8; y++) {
-                    if (y < cnt) {
-                        const uint32_t o = mdiv_i(m0 + y, mv.smul, mv.ssh);
-                        const uint32_t d = o - mdiv_i(o, mv.cmul, mv.csh) * mv.card;
-                        if (d != cur) {
-                            if (cur - x0 < nx) pa[cur - x0][lane] += run;
-                            run = 0.0;
-                            cur = d;
-                        }
-                        run += v[y];
-                    }
-                }
+        for (uint32_t x = 0; x < mv.card; x++) {
+            const uint32_t e0 = digit_below_i(b.begin, mv.stride, mv.card, x);
+            const uint32_t e1 = digit_below_i(b.begin + b.count, mv.stride, mv.card, x);
+            double sum = 0.0;
+#pragma unroll 8
+            for (uint32_t e = e0; e < e1; e++) {
+                const uint32_t o = mdiv_i(e, mv.smul, mv.ssh);
+                sum += (double)acc[(uint64_t)(f.sep + (o * mv.card + x) * mv.stride + (e - o * mv.stride)) * S + s];
             }
-            if (cur - x0 < nx) pa[cur - x0][lane] += run;
-            for (uint32_t x = 0; x < nx; x++) bm[(o0 + vo + x0 + x) * S + s] = pa[x][lane];
+            bm[(o0 + vo + x) * S + s] = sum;
         }
         vo += mv.card;
     }
