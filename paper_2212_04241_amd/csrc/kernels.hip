@@ -859,9 +859,14 @@ __global__ void k_gather(Ctx c, const int32_t* __restrict__ slots, double* __res
     }
 }
 
+// Start of a calibration: clear the batch's flags (and, with interleaved
+// tables, its running sum of collect exponents, kept after the edges' own).
 __global__ void k_begin(Ctx c, const int32_t* __restrict__ slots, int n) {
     const int b = blockIdx.x * blockDim.x + threadIdx.x;
-    if (b < n) c.flags[slots[b]] = 0;
+    if (b < n) {
+        c.flags[slots[b]] = 0;
+        if (c.S) c.kexp[(uint64_t)c.ne * c.S + (uint32_t)slots[b]] = 0;
+    }
 }
 
 __global__ void k_expand_map(const uint32_t* __restrict__ map, uint32_t mh, uint32_t ml, uint32_t L,

@@ -315,6 +315,7 @@ __global__ __launch_bounds__(kBlock) void k_fin_collect_i(Ctx c, const DSepFin* 
     for (uint32_t m = 0; m < f.size; m++)
         sepc[(uint64_t)(f.sep + m) * S + s] = (T)(accp<T>(c)[(uint64_t)(f.sep + m) * S + s] * scale);
     c.kexp[(uint64_t)f.edge * S + s] = k;
+    atomicAdd(&c.kexp[(uint64_t)c.ne * S + s], k);  // exact: integer sum
 }
 
 // After a distribute layer: finish the new separator, its posterior sums,
@@ -421,7 +422,10 @@ __global__ __launch_bounds__(kBlock) void k_fin_collect_ib(Ctx c, const DSepFin*
         const uint64_t x = (uint64_t)(f.sep + m) * S + s;
         sepc[x] = (T)(accp<T>(c)[x] * scale);
     }
-    if (b.begin == 0) c.kexp[(uint64_t)f.edge * S + s] = k;
+    if (b.begin == 0) {
+        c.kexp[(uint64_t)f.edge * S + s] = k;
+        atomicAdd(&c.kexp[(uint64_t)c.ne * S + s], k);  // exact: integer sum
+    }
 }
 
 // Entries m < n of a separator whose digit of a variable (stride, card) is x:
@@ -548,9 +552,7 @@ __global__ __launch_bounds__(kBlock) void k_marginals_i(Ctx c, const int32_t* __
         const double z = c.fp32 ? (double)static_cast<const float*>(c.acc)[zi] : static_cast<const double*>(c.acc)[zi];
         lg += z > 0.0 ? log(z) : -INFINITY;
     }
-    long long ks = 0;
-#pragma unroll 8
-    for (int e = 0; e < c.ne; e++) ks += c.kexp[(uint64_t)e * S + s];
+    const long long ks = c.kexp[(uint64_t)c.ne * S + s];  // summed by the collect finalisers
     c.logpe[s] = lg > -INFINITY ? lg + 0.69314718055994530942 * (double)(ks + c.kappa_total) : -INFINITY;
 }
 
