@@ -558,7 +558,9 @@ void build_plan(const Tree& t, int tile, uint32_t max_stage, Plan& p, bool inter
     // ---- distribute layers (depth): marginalise each clique onto each child
     // separator and onto the virtual separator of each private variable
     p.distribute.assign((size_t)D + 1, Layer());
-    const uint32_t dtile_base = (uint32_t)std::max(tile, 64);
+    // interleaved: a distribute work item is walked by one wave, and fewer,
+    // longer items mean fewer partial sums for the finalisers to add
+    const uint32_t dtile_base = (uint32_t)std::max(interleaved ? 4 * tile : tile, 64);
     for (int dd = 0; dd <= D; dd++) {
         Layer& ly = p.distribute[(size_t)dd];
         ly.group0 = (uint32_t)p.works.size();
