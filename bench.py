@@ -65,11 +65,11 @@ KIND_KERNEL_IL = {"collect": "k_collect_i", "collect_finalise": "k_fin_collect_i
                   "distribute_finalise": "k_fin_distribute_i", "posteriors": "k_marginals_i"}
 
 
-def counted_traffic(workload, kernel):
+def counted_traffic(workload, kernel, layout, tile):
     """HBM bytes per launch of the dominant kernel from the committed
     FETCH_SIZE / WRITE_SIZE summary (copy-scaled), or None when there is no
-    summary for this workload and kernel or the kernel sources changed since
-    the counters were taken."""
+    summary for this workload and kernel, it was taken with another layout or
+    tile, or the kernel sources changed since the counters were taken."""
     path = os.path.join(PROFILES, f"{kernel}_{workload}_counters.txt")
     if not os.path.exists(path):
         return None
@@ -81,13 +81,15 @@ def counted_traffic(workload, kernel):
                 kv[k.strip()] = v.strip()
     if kv.get("source_sha256") != sources_sha256():
         return None
+    if kv.get("layout") != str(int(layout)) or kv.get("tile") != str(int(tile)):
+        return None
     try:
         return float(kv["traffic_bytes_per_launch"])
     except (KeyError, ValueError):
         return None
 
 
-def roofline_of(prof, workload, note=None, interleaved=False):
+def roofline_of(prof, workload, layout, tile, note=None, interleaved=False):
     """Roofline object for the kernel kind with the most time in `prof`
     (kind -> (ms, launches, algorithmic bytes)), measured by HIP events."""
     kind = max(prof, key=lambda k: prof[k][0])
@@ -95,7 +97,7 @@ def roofline_of(prof, workload, note=None, interleaved=False):
     achieved = byts / (ms * 1e-3) / 1e9 if ms > 0 else 0.0
     kernel = (KIND_KERNEL_IL if interleaved else KIND_KERNEL)[kind]
     r = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-         "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": counted_traffic(workload, kernel),
+         "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": counted_traffic(workload, kernel, layout, tile),
          "kernel": f"{kernel}<float>", "launches": launches,
          "avg_launch_us": round(1e3 * ms / max(launches, 1), 3),
          "bytes_per_launch": byts / max(launches, 1),
@@ -369,7 +371,7 @@ def bench_served(args, fbn):
     fallbacks = int(np.count_nonzero(sat.precision == fbn.FBN_FP64))
     srv.close()
 
-    roofline = roofline_of({k: tuple(v) for k, v in prof.items()}, "C5",
+    roofline = roofline_of({k: tuple(v) for k, v in prof.items()}, "C5", 0, 0,
                            "one full batch per resident tree, eager launches, HIP events")
 
     def lat(r):
@@ -511,7 +513,7 @@ def main():
             dst.copy_(src)
         torch.cuda.synchronize()
         log("[bench] copy calibration: 3 x 512 MiB device copies")
-    roofline = roofline_of(prof32, key, interleaved=bool(stats["interleaved"]))
+    roofline = roofline_of(prof32, key, args.layout, args.tile, interleaved=bool(stats["interleaved"]))
     if args.fp32_only:
         # profiling runs: the headline path alone
         print(json.dumps({"value": round(qps32, 1), "unit": "queries/s", "ms_per_step": 1e3 * dt32 / args.steps,

@@ -60,25 +60,26 @@ def _store(path, data):
     os.replace(tmp, path)
 
 
-def measure_on_device(nets, cases, precision, max_slots, layout, tile, reps=3) -> float:
+def measure_on_device(nets, cases, precision, max_slots, layout, tile, reps=5) -> float:
     """Milliseconds per calibration of `cases` (one per slot) with the given
-    layout and tile, after one warm-up calibration."""
+    layout and tile: the median of `reps` synchronised calibrations after one
+    warm-up calibration."""
     handles = [fbn.net_from_spec(n) for n in nets] if isinstance(nets, (list, tuple)) else fbn.net_from_spec(nets)
     jt = fbn.JT(handles, precision=precision, max_slots=max_slots, layout=layout, tile_entries=tile)
     slots = list(range(len(cases)))
     fbn.set_evidence_batch(jt, slots, cases)
     fbn.calibrate(jt, slots, want_results=True)          # warm-up, synchronises
-    t0 = time.perf_counter()
-    for _ in range(reps - 1):
-        fbn.calibrate(jt, slots)
-    fbn.calibrate(jt, slots, want_results=True)          # synchronises
-    ms = 1e3 * (time.perf_counter() - t0) / reps
+    times = []
+    for _ in range(reps):
+        t0 = time.perf_counter()
+        fbn.calibrate(jt, slots, want_results=True)      # synchronises
+        times.append(time.perf_counter() - t0)
     jt.free()
-    return ms
+    return 1e3 * float(np.median(times))
 
 
 def tune(nets, cases, precision: int = fbn.FBN_FP32_RESCALED, max_slots: int | None = None,
-         candidates=None, reps: int = 3, cache: str | None = None, measure=None) -> dict:
+         candidates=None, reps: int = 5, cache: str | None = None, measure=None) -> dict:
     """Best (layout, tile) for calibrating `cases` on the tree of `nets` (one
     network or a list, as for fbn.JT).  Returns {"layout", "tile", "ms",
     "trials": [[layout, tile, ms], ...], "cached": bool}.  `measure` replaces
