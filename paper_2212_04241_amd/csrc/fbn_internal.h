@@ -193,6 +193,7 @@ constexpr int kBlock = 256;       // threads per workgroup
 constexpr int kTileMax = 4096;    // entries per workgroup tile
 constexpr int kMaxPieces = 32;    // runs (and packed targets) per workgroup
 constexpr uint32_t kFinBlock = 4096;  // separator entries per finaliser block at most
-constexpr uint32_t kFinBlockInterleaved = 32;  // the same with slot-interleaved tables
+constexpr uint32_t kFinBlockInterleaved = 16;  // the same with slot-interleaved tables
+constexpr uint32_t kBigSeparatorInterleaved = 8;  // slot-interleaved: larger separators are split into blocks
 
 }  // namespace fbn

@@ -249,12 +249,12 @@ __device__ __forceinline__ void finish_range_i(const DSepFin& f, const Ctx& c, u
     const uint64_t q1 = (uint64_t)f.part0 + (uint64_t)e * f.nchunk;
     double v = 0.0;
     uint32_t m = b, left = f.nchunk;
-    for (uint64_t q = q0; q < q1; q += 8) {
-        double x[8];
+    for (uint64_t q = q0; q < q1; q += 16) {
+        double x[16];
 #pragma unroll
-        for (uint32_t y = 0; y < 8; y++) x[y] = part[min(q + y, q1 - 1) * S + s];
+        for (uint32_t y = 0; y < 16; y++) x[y] = part[min(q + y, q1 - 1) * S + s];
 #pragma unroll
-        for (uint32_t y = 0; y < 8; y++) {
+        for (uint32_t y = 0; y < 16; y++) {
             if (q + y < q1) {
                 v += x[y];
                 if (--left == 0) {
@@ -269,24 +269,78 @@ __device__ __forceinline__ void finish_range_i(const DSepFin& f, const Ctx& c, u
     }
 }
 
-// Finish entry m alone: the sum of its partials in chunk order (loaded
-// eight at a time), or the layer kernel's whole sum.
-template <typename T>
-__device__ __forceinline__ double finish_i(const DSepFin& f, const Ctx& c, uint64_t S, uint64_t s, uint32_t m) {
-    if (!f.nchunk) return accp<T>(c)[(uint64_t)(f.sep + m) * S + s];
-    double v = 0.0;
-    const uint64_t p0 = (uint64_t)f.part0 + (uint64_t)m * f.nchunk;
-    for (uint32_t k0 = 0; k0 < f.nchunk; k0 += 8) {
-        const uint32_t cnt = min(8u, f.nchunk - k0);
-        double x[8];
+// New values of n (1 <= n <= N) consecutive entries m0, m0 + 1, ... of a
+// separator: fn(m, value) for each, then v[j] = entry m0 + j as stored in
+// table precision (the rest of v zero).  An entry with chunks is the sum of
+// its chunk partials in chunk order, stored into the accumulator.  A block
+// at least half full walks the chunks with one load per entry each (N loads
+// in flight, straight-line code); a sparser one walks the (entry, chunk)
+// pairs flat and reads v back.
+template <typename T, uint32_t N, typename F>
+__device__ __forceinline__ void finish_block_i(const DSepFin& f, const Ctx& c, uint64_t S, uint64_t s, uint32_t m0,
+                                               uint32_t n, double (&v)[N], F fn) {
+    T* __restrict__ acc = accp<T>(c);
+    if (f.nchunk && 2 * n >= N) {
+        const T* __restrict__ part = partp<T>(c);
+        const uint64_t p0 = (uint64_t)f.part0 + (uint64_t)m0 * f.nchunk;
 #pragma unroll
-        for (uint32_t y = 0; y < 8; y++) x[y] = partp<T>(c)[(p0 + k0 + min(y, cnt - 1)) * S + s];
+        for (uint32_t j = 0; j < N; j++) v[j] = 0.0;
+#pragma unroll 1
+        for (uint32_t k = 0; k < f.nchunk; k++) {
+            T x[N];
 #pragma unroll
-        for (uint32_t y = 0; y < 8; y++)
-            if (y < cnt) v += x[y];
+            for (uint32_t j = 0; j < N; j++) x[j] = part[(p0 + (uint64_t)min(j, n - 1) * f.nchunk + k) * S + s];
+#pragma unroll
+            for (uint32_t j = 0; j < N; j++) v[j] += (double)x[j];
+        }
+#pragma unroll
+        for (uint32_t j = 0; j < N; j++) {
+            if (j < n) {
+                fn(m0 + j, v[j]);
+                const T t = (T)v[j];
+                acc[(uint64_t)(f.sep + m0 + j) * S + s] = t;
+                v[j] = (double)t;
+            } else {
+                v[j] = 0.0;
+            }
+        }
+        return;
     }
-    accp<T>(c)[(uint64_t)(f.sep + m) * S + s] = (T)v;
-    return v;
+    if (f.nchunk) finish_range_i<T>(f, c, S, s, m0, m0 + n, fn);
+    T x[N];
+#pragma unroll
+    for (uint32_t j = 0; j < N; j++) x[j] = acc[(uint64_t)(f.sep + m0 + min(j, n - 1)) * S + s];
+#pragma unroll
+    for (uint32_t j = 0; j < N; j++) {
+        v[j] = j < n ? (double)x[j] : 0.0;
+        if (!f.nchunk && j < n) fn(m0 + j, v[j]);
+    }
+}
+
+// Posterior shares of n (>= 1) consecutive entries m0, m0 + 1, ... of a
+// separator whose values are v[0..n) (the rest of v is zero): for each
+// variable the separator carries and each state x, the sum of the values
+// whose digit of that variable is x, in entry order, passed to
+// put(variable, x, k, sum) with k the running (variable, state) index.
+template <uint32_t N, typename Put>
+__device__ __forceinline__ void shares_i(const DSepFin& f, const Ctx& c, uint32_t m0, uint32_t n,
+                                         const double (&v)[N], Put put) {
+    uint32_t k = 0;
+    for (uint32_t a = 0; a < f.nmv; a++) {
+        const DMargVar mv = c.mv[f.mv0 + a];
+        uint32_t dg[N];
+#pragma unroll
+        for (uint32_t j = 0; j < N; j++) {
+            const uint32_t t = mdiv_i(m0 + min(j, n - 1), mv.smul, mv.ssh);
+            dg[j] = t - mdiv_i(t, mv.cmul, mv.csh) * mv.card;
+        }
+        for (uint32_t x = 0; x < mv.card; x++) {
+            double sum = 0.0;
+#pragma unroll
+            for (uint32_t j = 0; j < N; j++) sum += dg[j] == x ? v[j] : 0.0;
+            put(mv, x, k++, sum);
+        }
+    }
 }
 
 // After a collect layer: finish, rescale to a max in [0.5, 1), store, and
@@ -300,10 +354,12 @@ __global__ __launch_bounds__(kBlock) void k_fin_collect_i(Ctx c, const DSepFin* 
     if (sl < 0) return;
     const uint64_t S = c.S, s = (uint64_t)sl;
     const DSepFin f = fins[fi];
+    // the whole separator (at most kBigSeparatorInterleaved entries) in registers
+    double v[kBigSeparatorInterleaved];
     double mx = 0.0;
-    finish_range_i<T>(f, c, S, s, 0u, f.size, [&](uint32_t, double v) { mx = fmax(mx, v); });
+    finish_block_i<T>(f, c, S, s, 0u, f.size, v, [&](uint32_t, double w) { mx = fmax(mx, w); });
     if (f.edge < 0) {
-        if (!(accp<T>(c)[(uint64_t)f.sep * S + s] > 0.0)) atomicOr(&c.flags[s], c.fp32 ? 2 : 1);
+        if (!(v[0] > 0.0)) atomicOr(&c.flags[s], c.fp32 ? 2 : 1);
         return;
     }
     int k = 0;
@@ -311,9 +367,9 @@ __global__ __launch_bounds__(kBlock) void k_fin_collect_i(Ctx c, const DSepFin* 
     else atomicOr(&c.flags[s], c.fp32 ? 2 : 1);
     const double scale = ldexp(1.0, -k);
     T* __restrict__ sepc = static_cast<T*>(c.sepc);
-#pragma unroll 8
-    for (uint32_t m = 0; m < f.size; m++)
-        sepc[(uint64_t)(f.sep + m) * S + s] = (T)(accp<T>(c)[(uint64_t)(f.sep + m) * S + s] * scale);
+#pragma unroll
+    for (uint32_t j = 0; j < kBigSeparatorInterleaved; j++)
+        if (j < f.size) sepc[(uint64_t)(f.sep + j) * S + s] = (T)(v[j] * scale);
     c.kexp[(uint64_t)f.edge * S + s] = k;
     atomicAdd(&c.kexp[(uint64_t)c.ne * S + s], k);  // exact: integer sum
 }
@@ -330,10 +386,37 @@ __global__ __launch_bounds__(kBlock) void k_fin_distribute_i(Ctx c, const DSepFi
     if (sl < 0) return;
     const uint64_t S = c.S, s = (uint64_t)sl;
     const DSepFin f = fins[fi];
-    if (f.nchunk) {
-#pragma unroll 8
-        for (uint32_t m = 0; m < f.size; m++) finish_i<T>(f, c, S, s, m);
+    if (f.size <= kBigSeparatorInterleaved) {
+        // the whole separator in registers: new values, posterior sums
+        // straight to the marginal accumulators, then the ratio
+        double v[kBigSeparatorInterleaved];
+        T den[kBigSeparatorInterleaved];
+        const T* __restrict__ sepc = static_cast<const T*>(c.sepc);
+        if (f.edge >= 0) {
+#pragma unroll
+            for (uint32_t j = 0; j < kBigSeparatorInterleaved; j++)
+                den[j] = sepc[(uint64_t)(f.sep + min(j, f.size - 1)) * S + s];
+        }
+        finish_block_i<T>(f, c, S, s, 0u, f.size, v, [](uint32_t, double) {});
+        double mx = 0.0;
+#pragma unroll
+        for (uint32_t j = 0; j < kBigSeparatorInterleaved; j++)
+            if (f.edge >= 0 && j < f.size) mx = fmax(mx, den[j] == T(0) ? 0.0 : v[j] / (double)den[j]);
+        shares_i(f, c, 0, f.size, v, [&](const DMargVar& mv, uint32_t x, uint32_t, double sum) {
+            c.marg[(uint64_t)(mv.out + x) * S + s] = sum;
+        });
+        if (f.edge < 0) return;
+        int k = 0;
+        if (mx > 0.0) frexp(mx, &k);
+        const double scale = ldexp(1.0, -k);
+        T* __restrict__ sepd = static_cast<T*>(c.sepd);
+#pragma unroll
+        for (uint32_t j = 0; j < kBigSeparatorInterleaved; j++)
+            if (j < f.size)
+                sepd[(uint64_t)(f.sep + j) * S + s] = (T)((den[j] == T(0) ? 0.0 : v[j] / (double)den[j]) * scale);
+        return;
     }
+    if (f.nchunk) finish_range_i<T>(f, c, S, s, 0u, f.size, [](uint32_t, double) {});
     // the posterior sums go straight to the marginal accumulators
     for (uint32_t a = 0; a < f.nmv; a++) {
         const DMargVar mv = c.mv[f.mv0 + a];
@@ -395,8 +478,8 @@ __global__ __launch_bounds__(kBlock) void k_fin_collect_ia(Ctx c, const DSepFin*
     const uint64_t S = c.S, s = (uint64_t)sl;
     const DFinBlk b = blks[bi];
     const DSepFin f = fins[b.fin];
-    double mx = 0.0;
-    finish_range_i<T>(f, c, S, s, b.begin, b.begin + b.count, [&](uint32_t, double v) { mx = fmax(mx, v); });
+    double mx = 0.0, v[kFinBlockInterleaved];
+    finish_block_i<T>(f, c, S, s, b.begin, b.count, v, [&](uint32_t, double w) { mx = fmax(mx, w); });
     fold_max(c, b, S, s, mx);
 }
 
@@ -417,24 +500,17 @@ __global__ __launch_bounds__(kBlock) void k_fin_collect_ib(Ctx c, const DSepFin*
     else if (b.begin == 0) atomicOr(&c.flags[s], c.fp32 ? 2 : 1);
     const double scale = ldexp(1.0, -k);
     T* __restrict__ sepc = static_cast<T*>(c.sepc);
-#pragma unroll 8
-    for (uint32_t m = b.begin; m < b.begin + b.count; m++) {
-        const uint64_t x = (uint64_t)(f.sep + m) * S + s;
-        sepc[x] = (T)(accp<T>(c)[x] * scale);
-    }
+    T a[kFinBlockInterleaved];
+#pragma unroll
+    for (uint32_t j = 0; j < kFinBlockInterleaved; j++)
+        a[j] = accp<T>(c)[(uint64_t)(f.sep + b.begin + min(j, b.count - 1)) * S + s];
+#pragma unroll
+    for (uint32_t j = 0; j < kFinBlockInterleaved; j++)
+        if (j < b.count) sepc[(uint64_t)(f.sep + b.begin + j) * S + s] = (T)((double)a[j] * scale);
     if (b.begin == 0) {
         c.kexp[(uint64_t)f.edge * S + s] = k;
         atomicAdd(&c.kexp[(uint64_t)c.ne * S + s], k);  // exact: integer sum
     }
-}
-
-// Entries m < n of a separator whose digit of a variable (stride, card) is x:
-// whole periods of stride * card entries hold stride each.
-__device__ __forceinline__ uint32_t digit_below_i(uint32_t n, uint32_t stride, uint32_t card, uint32_t x) {
-    const uint32_t span = stride * card;
-    const uint32_t r = n % span;
-    const uint32_t lo = x * stride;
-    return (n / span) * stride + (r > lo ? min(r - lo, stride) : 0u);
 }
 
 template <typename T>
@@ -449,37 +525,24 @@ __global__ __launch_bounds__(kBlock) void k_fin_distribute_ia(Ctx c, const DSepF
     const DFinBlk b = blks[bi];
     const DSepFin f = fins[b.fin];
     const T* __restrict__ sepc = static_cast<const T*>(c.sepc);
+    // the block's new separator values, as stored, stay in registers for
+    // the ratio maximum and the posterior shares
+    T den[kFinBlockInterleaved];
+#pragma unroll
+    for (uint32_t j = 0; j < kFinBlockInterleaved; j++)
+        den[j] = sepc[(uint64_t)(f.sep + b.begin + min(j, b.count - 1)) * S + s];
+    double v[kFinBlockInterleaved];
+    finish_block_i<T>(f, c, S, s, b.begin, b.count, v, [](uint32_t, double) {});
     double mx = 0.0;
-#pragma unroll 8
-    for (uint32_t m = b.begin; m < b.begin + b.count; m++) {
-        const double v = finish_i<T>(f, c, S, s, m);
-        const double den = (double)sepc[(uint64_t)(f.sep + m) * S + s];
-        mx = fmax(mx, den == 0.0 ? 0.0 : v / den);
-    }
+#pragma unroll
+    for (uint32_t j = 0; j < kFinBlockInterleaved; j++)
+        if (j < b.count) mx = fmax(mx, den[j] == T(0) ? 0.0 : v[j] / (double)den[j]);
     fold_max(c, b, S, s, mx);
-    // this block's share of each posterior sum: for each state x of each
-    // variable, the block's entries with digit x, m = (o * card + x) *
-    // stride + r, enumerated by e = o * stride + r between the counts of
-    // such entries below the block's ends
+    // this block's share of each posterior sum
     double* __restrict__ bm = c.bmarg;
     const uint64_t o0 = (uint64_t)b.mbase + (uint64_t)(b.id - b.blk0) * b.mw;
-    const T* __restrict__ acc = accp<T>(c);
-    uint32_t vo = 0;
-    for (uint32_t a = 0; a < f.nmv; a++) {
-        const DMargVar mv = c.mv[f.mv0 + a];
-        for (uint32_t x = 0; x < mv.card; x++) {
-            const uint32_t e0 = digit_below_i(b.begin, mv.stride, mv.card, x);
-            const uint32_t e1 = digit_below_i(b.begin + b.count, mv.stride, mv.card, x);
-            double sum = 0.0;
-#pragma unroll 8
-            for (uint32_t e = e0; e < e1; e++) {
-                const uint32_t o = mdiv_i(e, mv.smul, mv.ssh);
-                sum += (double)acc[(uint64_t)(f.sep + (o * mv.card + x) * mv.stride + (e - o * mv.stride)) * S + s];
-            }
-            bm[(o0 + vo + x) * S + s] = sum;
-        }
-        vo += mv.card;
-    }
+    shares_i(f, c, b.begin, b.count, v,
+             [&](const DMargVar&, uint32_t, uint32_t k, double sum) { bm[(o0 + k) * S + s] = sum; });
 }
 
 template <typename T>
@@ -499,12 +562,18 @@ __global__ __launch_bounds__(kBlock) void k_fin_distribute_ib(Ctx c, const DSepF
     const double scale = ldexp(1.0, -k);
     const T* __restrict__ sepc = static_cast<const T*>(c.sepc);
     T* __restrict__ sepd = static_cast<T*>(c.sepd);
-#pragma unroll 8
-    for (uint32_t m = b.begin; m < b.begin + b.count; m++) {
-        const uint64_t x = (uint64_t)(f.sep + m) * S + s;
-        const double den = (double)sepc[x];
-        sepd[x] = (T)((den == 0.0 ? 0.0 : accp<T>(c)[x] / den) * scale);
+    T a[kFinBlockInterleaved], den[kFinBlockInterleaved];
+#pragma unroll
+    for (uint32_t j = 0; j < kFinBlockInterleaved; j++) {
+        const uint64_t x = (uint64_t)(f.sep + b.begin + min(j, b.count - 1)) * S + s;
+        a[j] = accp<T>(c)[x];
+        den[j] = sepc[x];
     }
+#pragma unroll
+    for (uint32_t j = 0; j < kFinBlockInterleaved; j++)
+        if (j < b.count)
+            sepd[(uint64_t)(f.sep + b.begin + j) * S + s] =
+                (T)((den[j] == T(0) ? 0.0 : (double)a[j] / (double)den[j]) * scale);
     // posterior sums: block j of the separator adds sums j, j + nblk, ...
     const uint32_t j = b.id - b.blk0;
     for (uint32_t pidx = j; pidx < b.mw; pidx += b.nblk) {

@@ -287,7 +287,12 @@ std::string check_plan(const Tree& t, const Plan& p) {
             for (uint32_t f = ly.fin0; f < ly.fin0 + ly.nfin; f++) {
                 const DSepFin& F = p.fins[f];
                 if ((f < ly.fin0 + ly.nbig) != is_big(p, F)) return "large fin partition";
-                if (f >= ly.fin0 + ly.nbig) continue;
+                if (f >= ly.fin0 + ly.nbig) {
+                    // interleaved collect finalisers hold a whole small separator in registers
+                    if (p.interleaved && sweep == &p.collect && F.size > kBigSeparatorInterleaved)
+                        return "small collect fin size";
+                    continue;
+                }
                 uint32_t mw = 0;
                 for (uint32_t k = 0; k < F.nmv; k++) mw += p.margvars[F.mv0 + k].card;
                 uint32_t end = 0;

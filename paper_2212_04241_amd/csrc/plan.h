@@ -15,7 +15,6 @@ struct Layer {
 };
 
 constexpr uint32_t kBigSeparator = 1024;  // entries above which a separator is split into blocks
-constexpr uint32_t kBigSeparatorInterleaved = 8;  // the same with slot-interleaved tables
 constexpr uint64_t kFinWork = 16384;  // partial sums one finaliser block adds at most (entries x chunks)
 constexpr uint64_t kFinWorkInterleaved = 1024;  // the same when one lane adds them all
 constexpr uint32_t kTeamSeparator = 256;  // separators above this get a workgroup rather than a wave
