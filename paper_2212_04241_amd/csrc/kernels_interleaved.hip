@@ -70,12 +70,91 @@ constexpr int kKids = 6;  // child indices held per lane; more children are read
 
 // ------------------------------------------------------------------ collect
 
-// psi[i] = prior[i] * [evidence agrees at i] * prod_children sepc[map(i)],
-// stored; contiguous parent-separator segments summed in float64.  The
+// One piece of a collect group with NC children handled with loads issued
+// together (NC == kKids: further children, if any, read per entry).  The
 // entries are taken 64 at a time: lane j first works out entry j's digits,
 // prior value and child separator indices (one coalesced read of each
 // table), then the wave walks the 64 entries in order with those values
 // broadcast from lane j, each lane applying them to its own slot.
+template <typename T, int NC>
+__device__ __forceinline__ void collect_piece_i(const Ctx& c, const DPiece& pc, const DClique& q,
+                                                const DEvidence& ev, uint32_t lane, bool act, uint64_t S,
+                                                uint64_t s, bool partial, double& part) {
+    constexpr uint32_t U = NC <= 2 ? kUnroll : kUnroll / 2;  // entries per batch of loads
+    constexpr int NW = NC > 0 ? NC : 1;
+    const T* __restrict__ prior = static_cast<const T*>(c.prior);
+    const T* __restrict__ sepc = static_cast<const T*>(c.sepc);
+    T* __restrict__ psi = static_cast<T*>(c.psi);
+    const uint32_t* __restrict__ map = c.map;
+    const uint32_t nch = q.nchild;
+    const uint32_t end = pc.begin + pc.count;
+    uint32_t seg_left = q.seg - pc.begin % q.seg;
+    uint32_t out = q.psep + pc.begin / q.seg;
+    double acc = 0.0;
+    for (uint32_t i0 = pc.begin; i0 < end; i0 += kLanes) {
+        const uint32_t cnt = min((uint32_t)kLanes, end - i0);
+        // lane j: entry i0 + j
+        const uint32_t ej = i0 + min(lane, cnt - 1);
+        const uint32_t rj = mdiv_i(ej, q.Lmul, q.Lsh);
+        const uint32_t lj = ej - rj * q.L;
+        const uint64_t dj = c.dig[q.hdig + rj] | c.dig[q.ldig + lj];
+        const T pj = prior[q.off + ej];
+        uint32_t xj[NW];
+#pragma unroll
+        for (int k = 0; k < NC; k++) {
+            const DChild ch = c.ch[q.child0 + k];
+            xj[k] = ch.sep + map[ch.mh + rj] + map[ch.ml + lj];
+        }
+        for (uint32_t u0 = 0; u0 < cnt; u0 += U) {
+            T w[U][NW];
+#pragma unroll
+            for (uint32_t x = 0; x < U; x++) {
+                const uint32_t u = min(u0 + x, cnt - 1);
+#pragma unroll
+                for (int k = 0; k < NC; k++) w[x][k] = sepc[(uint64_t)bcast(xj[k], u) * S + s];
+            }
+            T v[U];
+#pragma unroll
+            for (uint32_t x = 0; x < U; x++) {
+                const uint32_t u = min(u0 + x, cnt - 1);
+                const uint64_t d = bcast(dj, u);
+                v[x] = ((d ^ ev.want) & ev.mask) ? T(0) : bcast(pj, u);
+#pragma unroll
+                for (int k = 0; k < NC; k++) v[x] *= w[x][k];
+            }
+            if (NC == kKids) {
+                for (uint32_t k = kKids; k < nch; k++) {
+                    const DChild ch = c.ch[q.child0 + k];
+#pragma unroll
+                    for (uint32_t x = 0; x < U; x++) {
+                        const uint32_t u = min(u0 + x, cnt - 1);
+                        const uint32_t idx = ch.sep + map[ch.mh + bcast(rj, u)] + map[ch.ml + bcast(lj, u)];
+                        v[x] *= sepc[(uint64_t)idx * S + s];
+                    }
+                }
+            }
+#pragma unroll
+            for (uint32_t x = 0; x < U; x++) {
+                if (u0 + x < cnt) {
+                    if (act) psi[(q.off + i0 + u0 + x) * S + s] = v[x];
+                    acc += (double)v[x];
+                    if (--seg_left == 0) {
+                        if (partial) part += acc;
+                        else if (act) accp<T>(c)[(uint64_t)out * S + s] = acc;
+                        acc = 0.0;
+                        out++;
+                        seg_left = q.seg;
+                    }
+                }
+            }
+        }
+    }
+    if (partial) part += acc;
+}
+
+// psi[i] = prior[i] * [evidence agrees at i] * prod_children sepc[map(i)],
+// stored; contiguous parent-separator segments summed in float64.  One wave
+// per group of pieces, a lane per slot.
 template <typename T>
 __global__ __launch_bounds__(kBlock) void k_collect_i(Ctx c, const DGroup* __restrict__ groups, uint32_t ngroups,
                                                       const int32_t* __restrict__ slots, int nslots) {
@@ -87,76 +166,23 @@ __global__ __launch_bounds__(kBlock) void k_collect_i(Ctx c, const DGroup* __res
     const uint64_t S = c.S;
     const uint64_t s = act ? (uint64_t)sl : 0;
     const DGroup g = groups[gi];
-    const T* __restrict__ prior = static_cast<const T*>(c.prior);
-    const T* __restrict__ sepc = static_cast<const T*>(c.sepc);
-    T* __restrict__ psi = static_cast<T*>(c.psi);
-    const uint32_t* __restrict__ map = c.map;
+    const bool partial = g.part >= 0;
     double part = 0.0;  // a partial group's single chunk sum
     for (uint32_t p = 0; p < g.npiece; p++) {
         const DPiece pc = c.pc[g.piece0 + p];
         const DClique q = c.cl[pc.clique];
         const DEvidence ev = c.ev[s * c.ev_stride + pc.clique];
-        const uint32_t nch = q.nchild;
-        const uint32_t end = pc.begin + pc.count;
-        uint32_t seg_left = q.seg - pc.begin % q.seg;
-        uint32_t out = q.psep + pc.begin / q.seg;
-        double acc = 0.0;
-        for (uint32_t i0 = pc.begin; i0 < end; i0 += kLanes) {
-            const uint32_t cnt = min((uint32_t)kLanes, end - i0);
-            // lane j: entry i0 + j
-            const uint32_t ej = i0 + min(lane, cnt - 1);
-            const uint32_t rj = mdiv_i(ej, q.Lmul, q.Lsh);
-            const uint32_t lj = ej - rj * q.L;
-            const uint64_t dj = c.dig[q.hdig + rj] | c.dig[q.ldig + lj];
-            const T pj = prior[q.off + ej];
-            uint32_t xj[kKids];
-#pragma unroll
-            for (int k = 0; k < kKids; k++) {
-                xj[k] = 0;
-                if (k < (int)nch) {
-                    const DChild ch = c.ch[q.child0 + k];
-                    xj[k] = ch.sep + map[ch.mh + rj] + map[ch.ml + lj];
-                }
-            }
-            for (uint32_t u0 = 0; u0 < cnt; u0 += kUnroll) {
-                T v[kUnroll];
-#pragma unroll
-                for (uint32_t x = 0; x < kUnroll; x++) {
-                    const uint32_t u = min(u0 + x, cnt - 1);
-                    const uint64_t d = bcast(dj, u);
-                    v[x] = ((d ^ ev.want) & ev.mask) ? T(0) : bcast(pj, u);
-#pragma unroll
-                    for (int k = 0; k < kKids; k++)
-                        if (k < (int)nch) v[x] *= sepc[(uint64_t)bcast(xj[k], u) * S + s];
-                }
-                for (uint32_t k = kKids; k < nch; k++) {
-                    const DChild ch = c.ch[q.child0 + k];
-#pragma unroll
-                    for (uint32_t x = 0; x < kUnroll; x++) {
-                        const uint32_t u = min(u0 + x, cnt - 1);
-                        const uint32_t idx = ch.sep + map[ch.mh + bcast(rj, u)] + map[ch.ml + bcast(lj, u)];
-                        v[x] *= sepc[(uint64_t)idx * S + s];
-                    }
-                }
-#pragma unroll
-                for (uint32_t x = 0; x < kUnroll; x++) {
-                    if (u0 + x < cnt) {
-                        if (act) psi[(q.off + i0 + u0 + x) * S + s] = v[x];
-                        acc += (double)v[x];
-                        if (--seg_left == 0) {
-                            if (g.part >= 0) part += acc;
-                            else if (act) accp<T>(c)[(uint64_t)out * S + s] = acc;
-                            acc = 0.0;
-                            out++;
-                            seg_left = q.seg;
-                        }
-                    }
-                }
-            }
+        switch (q.nchild) {
+        case 0: collect_piece_i<T, 0>(c, pc, q, ev, lane, act, S, s, partial, part); break;
+        case 1: collect_piece_i<T, 1>(c, pc, q, ev, lane, act, S, s, partial, part); break;
+        case 2: collect_piece_i<T, 2>(c, pc, q, ev, lane, act, S, s, partial, part); break;
+        case 3: collect_piece_i<T, 3>(c, pc, q, ev, lane, act, S, s, partial, part); break;
+        case 4: collect_piece_i<T, 4>(c, pc, q, ev, lane, act, S, s, partial, part); break;
+        case 5: collect_piece_i<T, 5>(c, pc, q, ev, lane, act, S, s, partial, part); break;
+        default: collect_piece_i<T, kKids>(c, pc, q, ev, lane, act, S, s, partial, part); break;
         }
-        if (g.part >= 0) part += acc;
     }
-    if (g.part >= 0 && act) partp<T>(c)[(uint64_t)(uint32_t)g.part * S + s] = part;
+    if (partial && act) partp<T>(c)[(uint64_t)(uint32_t)g.part * S + s] = part;
 }
 
 // ---------------------------------------------------------------- distribute
