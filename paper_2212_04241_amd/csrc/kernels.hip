@@ -110,6 +110,49 @@ struct KidC {
     uint32_t sep, mh, ml;
 };
 
+// One table entry of a collect tile for every slot of the workgroup, with
+// NC child messages whose loads are issued together (NC == kMaxKids:
+// further children, if any, read one by one).
+template <typename T, int B>
+struct EntryC {
+    uint32_t hi, lo;
+    T prior;
+    uint64_t dig, toff;
+    uint32_t gi, child0, nchild;
+};
+
+template <typename T, int B, int NC>
+__device__ __forceinline__ void collect_entry(const Ctx& c, const EntryC<T, B>& e, const DEvidence (&ev)[B],
+                                              const int (&sl)[B], const uint32_t (&ksep)[kMaxKids],
+                                              const uint32_t (&kmh)[kMaxKids], const uint32_t (&kml)[kMaxKids],
+                                              T* const (&psi_b)[B], const T* const (&sepc_b)[B], T* vals) {
+    constexpr int NW = NC > 0 ? NC : 1;
+    const uint32_t* __restrict__ map = c.map;
+    uint32_t jk[NW];
+#pragma unroll
+    for (int k = 0; k < NC; k++) jk[k] = ksep[k] + map[kmh[k] + e.hi] + map[kml[k] + e.lo];
+    T w[B][NW];
+#pragma unroll
+    for (int b = 0; b < B; b++)
+#pragma unroll
+        for (int k = 0; k < NC; k++) w[b][k] = sepc_b[b][jk[k]];  // a slot past the batch reads slot 0's
+#pragma unroll
+    for (int b = 0; b < B; b++) {
+        if (sl[b] < 0) continue;
+        T v = ((e.dig ^ ev[b].want) & ev[b].mask) ? T(0) : e.prior;
+#pragma unroll
+        for (int k = 0; k < NC; k++) v *= w[b][k];
+        if (NC == kMaxKids) {
+            for (uint32_t k = kMaxKids; k < e.nchild; k++) {
+                const DChild ch = c.ch[e.child0 + k];
+                v *= sepc_b[b][ch.sep + map[ch.mh + e.hi] + map[ch.ml + e.lo]];
+            }
+        }
+        psi_b[b][e.toff] = v;
+        vals[b * c.tile + e.gi] = v;
+    }
+}
+
 template <typename T, int B>
 __global__ __launch_bounds__(kBlock) void k_collect(Ctx c, const DGroup* __restrict__ groups, uint32_t ngroups,
                                                     const int32_t* __restrict__ slots, int nslots) {
@@ -219,24 +262,18 @@ __global__ __launch_bounds__(kBlock) void k_collect(Ctx c, const DGroup* __restr
         const uint32_t lo = i - hi * r_L;
         const T pv = r_prior[i];
         const uint64_t d = anyev ? (c.dig[r_hdig + hi] | c.dig[r_ldig + lo]) : 0;
-        uint32_t jk[kMaxKids];
-#pragma unroll
-        for (int k = 0; k < kMaxKids; k++)
-            if (k < (int)nk) jk[k] = ksep[k] + map[kmh[k] + hi] + map[kml[k] + lo];
         const uint64_t toff = (uint64_t)(r_prior - prior) + i;
-#pragma unroll
-        for (int b = 0; b < B; b++) {
-            if (sl[b] < 0) continue;
-            T v = ((d ^ ev[b].want) & ev[b].mask) ? T(0) : pv;
-#pragma unroll
-            for (int k = 0; k < kMaxKids; k++)
-                if (k < (int)nk) v *= sepc_b[b][jk[k]];
-            for (uint32_t k = kMaxKids; k < nk; k++) {
-                const DChild ch = c.ch[runs[p].child0 + k];
-                v *= sepc_b[b][ch.sep + map[ch.mh + hi] + map[ch.ml + lo]];
-            }
-            psi_b[b][toff] = v;
-            vals[b * c.tile + gi] = v;
+        const EntryC<T, B> e{hi, lo, pv, d, toff, gi, runs[p].child0, nk};
+        switch (nk) {
+        case 0: collect_entry<T, B, 0>(c, e, ev, sl, ksep, kmh, kml, psi_b, sepc_b, vals); break;
+        case 1: collect_entry<T, B, 1>(c, e, ev, sl, ksep, kmh, kml, psi_b, sepc_b, vals); break;
+        case 2: collect_entry<T, B, 2>(c, e, ev, sl, ksep, kmh, kml, psi_b, sepc_b, vals); break;
+        case 3: collect_entry<T, B, 3>(c, e, ev, sl, ksep, kmh, kml, psi_b, sepc_b, vals); break;
+        case 4: collect_entry<T, B, 4>(c, e, ev, sl, ksep, kmh, kml, psi_b, sepc_b, vals); break;
+        case 5: collect_entry<T, B, 5>(c, e, ev, sl, ksep, kmh, kml, psi_b, sepc_b, vals); break;
+        case 6: collect_entry<T, B, 6>(c, e, ev, sl, ksep, kmh, kml, psi_b, sepc_b, vals); break;
+        case 7: collect_entry<T, B, 7>(c, e, ev, sl, ksep, kmh, kml, psi_b, sepc_b, vals); break;
+        default: collect_entry<T, B, kMaxKids>(c, e, ev, sl, ksep, kmh, kml, psi_b, sepc_b, vals); break;
         }
     }
     __syncthreads();

@@ -26,7 +26,8 @@ namespace {
 
 constexpr int kLanes = 64;
 constexpr int kWavesPerBlock = kBlock / kLanes;
-constexpr uint32_t kUnroll = 8;  // entries whose loads are issued together
+constexpr uint32_t kUnroll = 8;  // collect: entries whose loads are issued together
+constexpr uint32_t kDistBatch = 16;  // distribute: (output, entry) pairs whose loads are issued together
 
 __device__ __forceinline__ uint32_t mdiv_i(uint32_t n, uint32_t mul, uint32_t sh) {
     return (uint32_t)(((uint64_t)__umulhi(n, mul) + n) >> sh);
@@ -227,16 +228,16 @@ __global__ __launch_bounds__(kBlock) void k_dist_i(Ctx c, const DWork* __restric
         const uint32_t ej = row * q.L + l;  // within the clique
         const uint32_t rj = ratio ? q.psep + map[q.pmh + row] + map[q.pml + l] : 0u;
         const uint32_t mj = map[tg.tb + w.g0 + gg] + map[tg.tv + t];
-        for (uint32_t x0 = 0; x0 < cnt; x0 += kUnroll) {
-            T v[kUnroll], r[kUnroll];
+        for (uint32_t x0 = 0; x0 < cnt; x0 += kDistBatch) {
+            T v[kDistBatch], r[kDistBatch];
 #pragma unroll
-            for (uint32_t x = 0; x < kUnroll; x++) {
+            for (uint32_t x = 0; x < kDistBatch; x++) {
                 const uint32_t b = min(x0 + x, cnt - 1);
                 v[x] = psi[(q.off + bcast(ej, b)) * S + s];
                 r[x] = ratio ? sepd[(uint64_t)bcast(rj, b) * S + s] : T(1);
             }
 #pragma unroll
-            for (uint32_t x = 0; x < kUnroll; x++) {
+            for (uint32_t x = 0; x < kDistBatch; x++) {
                 if (x0 + x < cnt) {
                     acc += (double)(ratio ? v[x] * r[x] : v[x]);
                     if (--left == 0) {
