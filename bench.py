@@ -161,11 +161,13 @@ def workload_config(key, W, jt_stats, n_slots):
     }
 
 
-def time_batched(fbn, W, precision, steps, warmup, profile, layout=0, tile=0):
+def time_batched(fbn, W, precision, steps, warmup, profile, layout=0, tile=0, event_every=1):
     """Time `steps` calibrations of the whole batch.  With profile, one
     untimed warm-up step times every kernel kind (the per-kind breakdown
-    returned as `kinds`), and the timed steps record HIP events around the
-    launches of the kind with the most time only."""
+    returned as `kinds`), and timed steps record HIP events around the
+    launches of the kind with the most time only, in one step of every
+    `event_every` (each event pair is a marker on the stream that costs a
+    few microseconds, so the other steps run without them)."""
     cases = W.slot_cases
     n = len(cases)
     jt = fbn.JT(W.handles(fbn), precision=precision, max_slots=n, layout=layout, tile_entries=tile)
@@ -183,7 +185,9 @@ def time_batched(fbn, W, precision, steps, warmup, profile, layout=0, tile=0):
         fbn.jt_profile_kinds(jt, [dominant])
     fbn.jt_profile_read(jt)             # synchronises; clears counters
     t0 = time.perf_counter()
-    for _ in range(steps):
+    for i in range(steps):
+        if profile:
+            fbn.jt_profile_enable(jt, (i + 1) % event_every == 0 or (i == steps - 1 and steps < event_every))
         fbn.calibrate(jt, slots)
     prof = fbn.jt_profile_read(jt)      # synchronises the stream
     dt = time.perf_counter() - t0
@@ -461,6 +465,8 @@ def main():
                     help="also run plain 512 MiB device copies (reference for byte counters)")
     ap.add_argument("--layout", type=int, default=0, help="table layout: 0 auto, 1 per slot, 2 interleaved")
     ap.add_argument("--tile", type=int, default=0, help="table entries per work item (0: the library default)")
+    ap.add_argument("--event-every", type=int, default=4,
+                    help="HIP events around the dominant kernel in one timed step of every N")
     ap.add_argument("--no-tune", action="store_true",
                     help="skip the autotuner (layout and tile from --layout / --tile)")
     ap.add_argument("--cases", type=int, default=0, help="single-network workloads: the first N cases only")
@@ -498,7 +504,8 @@ def main():
             f"({tuned['ms']:.3f} ms per calibration)")
     # FP32 batched (the headline path), kernel timing by HIP events
     jt32, dt32, (prof32, kinds32), post32, lp32, st32 = time_batched(fbn, W, fbn.FBN_FP32_RESCALED, args.steps,
-                                                                     args.warmup, True, args.layout, args.tile)
+                                                                     args.warmup, True, args.layout, args.tile,
+                                                                     args.event_every)
     stats = jt32.stats
     qps32 = q * args.steps / dt32
     log(f"[bench] fp32 batched: {qps32:.1f} q/s, {1e3 * dt32 / args.steps:.3f} ms/step")
@@ -560,7 +567,8 @@ def main():
                              "useful_GBps": round(n * args.steps / dt32 * 3 * T * 4 / 1e9, 1),
                              "kernel_ms_one_profiled_step": {k: round(v[0], 4) for k, v in kinds32.items()},
                              "kernel_share": round(sum(v[0] for v in kinds32.values()) / (1e3 * dt32 / args.steps), 3),
-                             "timed_region_events": "around the dominant kind's launches only"},
+                             "timed_region_events": f"around the dominant kind's launches, in one timed step of every "
+                                                    f"{args.event_every}"},
             "fp64_batched": {"queries_per_s": round(qps64b, 1),
                              "useful_GBps": round(n * steps64 / dt64 * 3 * T * 8 / 1e9, 1)},
             "fp64_plain_per_query": {"queries_per_s": round(qps_plain, 1),
