@@ -161,14 +161,27 @@ def workload_config(key, W, jt_stats, n_slots):
     }
 
 
-def time_batched(fbn, W, precision, steps, warmup, profile, layout=0, tile=0, event_every=1):
+def fitting_slots(fbn, W, precision, layout, tile, frac=0.9):
+    """How many of the workload's slots a device build of this precision and
+    layout can hold in `frac` of the free device memory (host-only build
+    for the footprint)."""
+    import torch
+    n = len(W.slot_cases)
+    jt = fbn.JT(W.handles(fbn), precision=precision, max_slots=n, layout=layout, tile_entries=tile, host_only=True)
+    st = jt.stats
+    fixed = st["device_bytes"] - n * st["slot_bytes"]
+    free, _ = torch.cuda.mem_get_info()
+    return max(1, min(n, int((frac * free - fixed) // max(1, st["slot_bytes"]))))
+
+
+def time_batched(fbn, W, precision, steps, warmup, profile, layout=0, tile=0, event_every=1, n_cases=None):
     """Time `steps` calibrations of the whole batch.  With profile, one
     untimed warm-up step times every kernel kind (the per-kind breakdown
     returned as `kinds`), and timed steps record HIP events around the
     launches of the kind with the most time only, in one step of every
     `event_every` (each event pair is a marker on the stream that costs a
     few microseconds, so the other steps run without them)."""
-    cases = W.slot_cases
+    cases = W.slot_cases[:n_cases] if n_cases else W.slot_cases
     n = len(cases)
     jt = fbn.JT(W.handles(fbn), precision=precision, max_slots=n, layout=layout, tile_entries=tile)
     slots = list(range(n))
@@ -530,11 +543,13 @@ def main():
         return
     # FP64 batched
     steps64 = max(1, args.steps // 2)
+    # float64 tables take twice the memory: as many cases as fit
+    n64 = fitting_slots(fbn, W, fbn.FBN_FP64, args.layout, args.tile)
     jt64, dt64, _, post64, lp64, st64 = time_batched(fbn, W, fbn.FBN_FP64, steps64, 1, False, args.layout,
-                                                     args.tile)
-    qps64b = q * steps64 / dt64
+                                                     args.tile, n_cases=n64)
+    qps64b = n64 * W.per_slot * steps64 / dt64
     jt64.free()
-    log(f"[bench] fp64 batched: {qps64b:.1f} q/s")
+    log(f"[bench] fp64 batched: {qps64b:.1f} q/s ({n64} slots)")
     # FP64 plain, one query per calibration
     qps_plain, lat, plain = time_plain(fbn, W, args.plain_queries)
     log(f"[bench] fp64 plain (graph replay): {qps_plain:.1f} q/s, p50 {1e3 * np.median(lat):.3f} ms")
@@ -569,8 +584,8 @@ def main():
                              "kernel_share": round(sum(v[0] for v in kinds32.values()) / (1e3 * dt32 / args.steps), 3),
                              "timed_region_events": f"around the dominant kind's launches, in one timed step of every "
                                                     f"{args.event_every}"},
-            "fp64_batched": {"queries_per_s": round(qps64b, 1),
-                             "useful_GBps": round(n * steps64 / dt64 * 3 * T * 8 / 1e9, 1)},
+            "fp64_batched": {"queries_per_s": round(qps64b, 1), "slots": n64,
+                             "useful_GBps": round(n64 * steps64 / dt64 * 3 * T * 8 / 1e9, 1)},
             "fp64_plain_per_query": {"queries_per_s": round(qps_plain, 1),
                                      "p50_ms": round(1e3 * float(np.median(lat)), 4),
                                      "p99_ms": round(1e3 * float(np.percentile(lat, 99)), 4),
