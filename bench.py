@@ -334,7 +334,8 @@ def bench_served(args, fbn):
     queries = trace_queries(times[:n], which[:n], cases)
     log(f"[bench] C5: 8 networks, {n} trace queries")
     t0 = time.perf_counter()
-    srv = Server(nets, budget_bytes=int(args.budget_gb * (1 << 30)), max_batch=args.max_batch)
+    srv = Server(nets, budget_bytes=int(args.budget_gb * (1 << 30)), max_batch=args.max_batch, tile=args.tile,
+                 layout=args.layout)
     log(f"[bench] server up in {time.perf_counter() - t0:.1f} s: {srv.slots} slots per tree, "
         f"{srv.device_bytes / 2**30:.2f} GiB resident, plan {srv.planned_bytes / 2**30:.2f} GiB of "
         f"{args.budget_gb} GiB")
@@ -388,8 +389,9 @@ def bench_served(args, fbn):
     fallbacks = int(np.count_nonzero(sat.precision == fbn.FBN_FP64))
     srv.close()
 
-    roofline = roofline_of({k: tuple(v) for k, v in prof.items()}, "C5", 0, 0,
-                           "one full batch per resident tree, eager launches, HIP events")
+    roofline = roofline_of({k: tuple(v) for k, v in prof.items()}, "C5", args.layout, args.tile,
+                           "one full batch per resident tree, eager launches, HIP events",
+                           interleaved=args.layout == 2)
 
     def lat(r):
         return {"queries_per_s": round(r.qps, 1), "p50_ms": round(1e3 * r.percentile(50), 3),
@@ -411,6 +413,7 @@ def bench_served(args, fbn):
         "config": {"workload": f"C5: {fbngen.CONFIGS['C5'].description}", "networks": 8,
                    "trace_queries": n, "budget_GiB": args.budget_gb, "slots_per_tree": slots,
                    "resident_GiB": round(resident / 2**30, 3), "max_batch": args.max_batch,
+                   "layout": "interleaved" if args.layout == 2 else "per-slot", "tile": args.tile,
                    "step": "one closed-loop replay of the trace"},
         "roofline": roofline,
         "paths": {

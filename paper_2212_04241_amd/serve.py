@@ -80,17 +80,19 @@ class Server:
     .card), one stream each, sized by `budget_bytes`."""
 
     def __init__(self, nets, budget_bytes: int = 32 << 30, max_batch: int = 32, depth: int = 2,
-                 graph: bool = True, tile: int = 0, warm: bool = True):
+                 graph: bool = True, tile: int = 0, warm: bool = True, layout: int = 0):
         import torch
         self._torch = torch
         self.nets = list(nets)
         self.card_sum = [int(np.sum(n.card)) for n in self.nets]
         self.tile = tile
+        self.layout = layout
         self.depth = max(1, depth)
         handles = [fbn.net_from_spec(n) for n in self.nets]
         fixed, slot, fb = [], [], []
         for h in handles:
-            a = fbn.JT(h, host_only=True, precision=fbn.FBN_FP32_RESCALED, max_slots=1, tile_entries=tile)
+            a = fbn.JT(h, host_only=True, precision=fbn.FBN_FP32_RESCALED, max_slots=1, tile_entries=tile,
+                       layout=layout)
             fixed.append(a.stats["device_bytes"] - a.stats["slot_bytes"])
             slot.append(a.stats["slot_bytes"])
             b = fbn.JT(h, host_only=True, precision=fbn.FBN_FP64, max_slots=1, tile_entries=tile)
@@ -107,7 +109,7 @@ class Server:
         self.jts = []
         for h, s in zip(handles, self.streams):
             jt = fbn.JT(h, precision=fbn.FBN_FP32_RESCALED, max_slots=self.slots, tile_entries=tile,
-                        stream=s.cuda_stream)
+                        stream=s.cuda_stream, layout=layout)
             if graph:
                 fbn.set_graph_mode(jt, True)
             self.jts.append(jt)
