@@ -553,13 +553,17 @@ __global__ __launch_bounds__(kBlock) void k_dist_gather(Ctx c, const DWork* __re
             pedge = q.pedge;
             if (pedge >= 0) pr = q.psep + map[q.pmh + row] + map[q.pml + l];
         }
+        // every slot's loads issued together (a slot past the batch reads
+        // slot 0's tables; a root clique reads ratio entry 0, unused)
+        T v[B], r[B];
 #pragma unroll
         for (int b = 0; b < B; b++) {
-            if (sl[b] < 0) continue;
-            T v = psi_b[b][off + ent];
-            if (pedge >= 0) v *= sepd_b[b][pr];
-            vals[b * c.tile + gi] = v;
+            v[b] = psi_b[b][off + ent];
+            r[b] = sepd_b[b][pr];
         }
+#pragma unroll
+        for (int b = 0; b < B; b++)
+            if (sl[b] >= 0) vals[b * c.tile + gi] = pedge >= 0 ? v[b] * r[b] : v[b];
     }
     __syncthreads();
 
