@@ -394,6 +394,53 @@ __device__ __forceinline__ void finish_range(const DSepFin& f, T* acc, const T* 
     }
 }
 
+// Entries m < n of a separator whose digit of a variable (stride, card) is x:
+// whole periods of stride * card entries hold stride each.
+__device__ __forceinline__ uint32_t digit_below(uint32_t n, uint32_t stride, uint32_t card, uint32_t x) {
+    const uint32_t span = stride * card;
+    const uint32_t r = n % span;
+    const uint32_t lo = x * stride;
+    return (n / span) * stride + (r > lo ? min(r - lo, stride) : 0u);
+}
+
+// Posterior shares of the entries [b, e) of separator f: for every state x
+// of every variable it carries (mw pairs in all, taken in variable order),
+// the sum of get(m) over the entries m with digit x.  Each pair gets tpp
+// lanes of one wave (a power of two, as many as the team allows), whose
+// sums are combined by a fixed xor-shuffle tree; put(pair, variable, x,
+// sum) is called once per pair.  t is the thread's index in its team of nt
+// threads; every thread of the team must make the call.
+template <typename Get, typename Put>
+__device__ __forceinline__ void shares_grouped(const DSepFin& f, const Ctx& c, uint32_t b, uint32_t e, uint32_t mw,
+                                               uint32_t t, uint32_t nt, Get get, Put put) {
+    uint32_t tpp = 1;
+    while (tpp < (uint32_t)kWave && tpp * 2 * mw <= nt) tpp *= 2;
+    const uint32_t sub = t & (tpp - 1);
+    for (uint32_t base = 0; base < mw * tpp; base += nt) {
+        const uint32_t pidx = (base + t) / tpp;
+        double s = 0.0;
+        DMargVar mv{};
+        uint32_t x = 0;
+        if (pidx < mw) {
+            uint32_t vo = 0, a = 0;
+            mv = c.mv[f.mv0];
+            while (pidx >= vo + mv.card) {
+                vo += mv.card;
+                mv = c.mv[f.mv0 + ++a];
+            }
+            x = pidx - vo;
+            const uint32_t e0 = digit_below(b, mv.stride, mv.card, x);
+            const uint32_t e1 = digit_below(e, mv.stride, mv.card, x);
+            for (uint32_t k = e0 + sub; k < e1; k += tpp) {
+                const uint32_t o = mdiv(k, mv.smul, mv.ssh);
+                s += get((o * mv.card + x) * mv.stride + (k - o * mv.stride));
+            }
+        }
+        for (uint32_t o2 = tpp / 2; o2 > 0; o2 >>= 1) s += __shfl_xor(s, (int)o2, kWave);
+        if (pidx < mw && sub == 0) put(pidx, mv, x, s);
+    }
+}
+
 // After a collect layer, per separator: finish the message (sum partial
 // sums where a segment spanned several tiles), rescale it by an exact power
 // of two so its largest entry lies in [0.5, 1), store it in table precision
@@ -653,20 +700,10 @@ __global__ __launch_bounds__(kBlock) void k_fin_distribute(Ctx c, const DSepFin*
     // posteriors: each state of each assigned variable is a team-wide sum
     // over the separator entries carrying that state
     double* __restrict__ marg = c.marg + (uint64_t)slot * c.marg_stride;
-    for (uint32_t a = 0; a < f.nmv; a++) {
-        const DMargVar mv = c.mv[f.mv0 + a];
-        const uint32_t per = f.size / mv.card;
-        for (uint32_t x = 0; x < mv.card; x++) {
-            double s = 0.0;
-#pragma unroll 4
-            for (uint32_t e = lane; e < per; e += tm.size) {
-                const uint32_t o = mdiv(e, mv.smul, mv.ssh);
-                s += acc[f.sep + (o * mv.card + x) * mv.stride + (e - o * mv.stride)];
-            }
-            s = tm.sum(s);
-            if (lane == 0) marg[mv.out + x] = s;
-        }
-    }
+    uint32_t mw = 0;
+    for (uint32_t a = 0; a < f.nmv; a++) mw += c.mv[f.mv0 + a].card;
+    shares_grouped(f, c, 0u, f.size, mw, lane, tm.size, [&](uint32_t m) { return (double)acc[f.sep + m]; },
+                   [&](uint32_t, const DMargVar& mv, uint32_t x, double s) { marg[mv.out + x] = s; });
     if (f.edge < 0) return;
     const T* __restrict__ sepc = static_cast<const T*>(c.sepc) + (uint64_t)slot * c.sep_stride;
     T* __restrict__ sepd = static_cast<T*>(c.sepd) + (uint64_t)slot * c.sep_stride;
@@ -755,15 +792,6 @@ __global__ __launch_bounds__(kBlock) void k_fin_collect_b(Ctx c, const DSepFin* 
     if (b.begin == 0 && threadIdx.x == 0) c.kexp[(uint64_t)slot * c.kexp_stride + f.edge] = k;
 }
 
-// Entries m < n of a separator whose digit of a variable (stride, card) is x:
-// whole periods of stride * card entries hold stride each.
-__device__ __forceinline__ uint32_t digit_below(uint32_t n, uint32_t stride, uint32_t card, uint32_t x) {
-    const uint32_t span = stride * card;
-    const uint32_t r = n % span;
-    const uint32_t lo = x * stride;
-    return (n / span) * stride + (r > lo ? min(r - lo, stride) : 0u);
-}
-
 template <typename T>
 __global__ __launch_bounds__(kBlock) void k_fin_distribute_a(Ctx c, const DSepFin* __restrict__ fins,
                                                              const DFinBlk* __restrict__ blks,
@@ -787,22 +815,9 @@ __global__ __launch_bounds__(kBlock) void k_fin_distribute_a(Ctx c, const DSepFi
     // this block's share of each posterior sum: the entries with digit x
     // are m = (o * card + x) * stride + r, enumerated by e = o * stride + r
     double* __restrict__ bm = c.bmarg + (uint64_t)slot * c.bmarg_stride + b.mbase + (b.id - b.blk0) * b.mw;
-    uint32_t vo = 0;
-    for (uint32_t a = 0; a < f.nmv; a++) {
-        const DMargVar mv = c.mv[f.mv0 + a];
-        for (uint32_t x = 0; x < mv.card; x++) {
-            const uint32_t e0 = digit_below(b.begin, mv.stride, mv.card, x);
-            const uint32_t e1 = digit_below(b.begin + b.count, mv.stride, mv.card, x);
-            double s = 0.0;
-            for (uint32_t e = e0 + threadIdx.x; e < e1; e += kBlock) {
-                const uint32_t o = mdiv(e, mv.smul, mv.ssh);
-                s += vals[(o * mv.card + x) * mv.stride + (e - o * mv.stride) - b.begin];
-            }
-            s = block_sum(s, red);
-            if (threadIdx.x == 0) bm[vo + x] = s;
-        }
-        vo += mv.card;
-    }
+    shares_grouped(f, c, b.begin, b.begin + b.count, b.mw, threadIdx.x, (uint32_t)kBlock,
+                   [&](uint32_t m) { return vals[m - b.begin]; },
+                   [&](uint32_t k, const DMargVar&, uint32_t, double s) { bm[k] = s; });
 }
 
 template <typename T>
