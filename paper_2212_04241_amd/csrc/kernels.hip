@@ -732,8 +732,8 @@ __global__ __launch_bounds__(kBlock) void k_fin_distribute(Ctx c, const DSepFin*
 // distribute sweep, the block's partial posterior sums.  Phase two takes the
 // separator's maximum over its blocks and writes the rescaled message
 // (collect) or ratio (distribute); the separator's first block also adds the
-// posterior sums of all blocks, in block order.  Every sum has a fixed
-// order, as in the one-team finalisers.
+// posterior sums of all blocks (strided lane sums and a shuffle tree).
+// Every sum has a fixed order, as in the one-team finalisers.
 
 __device__ __forceinline__ double block_max_all(double v, double* scratch) {
     v = wave_max(v);
@@ -841,17 +841,29 @@ __global__ __launch_bounds__(kBlock) void k_fin_distribute_b(Ctx c, const DSepFi
         sepd[m] = (T)((den == 0.0 ? 0.0 : acc[m] / den) * scale);
     }
     if (b.begin != 0) return;
+    // the separator's first block adds every pair's shares over the blocks:
+    // tpp lanes of one wave per pair, combined by a fixed xor-shuffle tree
     const double* __restrict__ bm = c.bmarg + (uint64_t)slot * c.bmarg_stride + b.mbase;
     double* __restrict__ marg = c.marg + (uint64_t)slot * c.marg_stride;
-    uint32_t vo = 0;
-    for (uint32_t a = 0; a < f.nmv; a++) {
-        const DMargVar mv = c.mv[f.mv0 + a];
-        for (uint32_t x = threadIdx.x; x < mv.card; x += kBlock) {
-            double s = 0.0;
-            for (uint32_t j = 0; j < b.nblk; j++) s += bm[(uint64_t)j * b.mw + vo + x];
-            marg[mv.out + x] = s;
+    const uint32_t mw = b.mw;
+    uint32_t tpp = 1;
+    while (tpp < (uint32_t)kWave && tpp * 2 * mw <= (uint32_t)kBlock) tpp *= 2;
+    const uint32_t sub = threadIdx.x & (tpp - 1);
+    for (uint32_t base = 0; base < mw * tpp; base += kBlock) {
+        const uint32_t pidx = (base + threadIdx.x) / tpp;
+        double s = 0.0;
+        if (pidx < mw)
+            for (uint32_t j = sub; j < b.nblk; j += tpp) s += bm[(uint64_t)j * mw + pidx];
+        for (uint32_t o2 = tpp / 2; o2 > 0; o2 >>= 1) s += __shfl_xor(s, (int)o2, kWave);
+        if (pidx < mw && sub == 0) {
+            uint32_t vo = 0, a = 0;
+            DMargVar mv = c.mv[f.mv0];
+            while (pidx >= vo + mv.card) {
+                vo += mv.card;
+                mv = c.mv[f.mv0 + ++a];
+            }
+            marg[mv.out + pidx - vo] = s;
         }
-        vo += mv.card;
     }
 }
 
