@@ -371,7 +371,15 @@ template <typename T, typename F>
 __device__ __forceinline__ void finish_range(const DSepFin& f, T* acc, const T* part, uint32_t b, uint32_t e,
                                              uint32_t t, uint32_t nt, F fn) {
     if (!f.nchunk) {
-        for (uint32_t m = b + t; m < e; m += nt) fn(m, (double)acc[m]);
+        // four entries per thread at a time, their loads issued together
+        for (uint32_t m0 = b + t; m0 < e; m0 += 4 * nt) {
+            T x[4];
+#pragma unroll
+            for (uint32_t u = 0; u < 4; u++) x[u] = acc[min(m0 + u * nt, e - 1)];
+#pragma unroll
+            for (uint32_t u = 0; u < 4; u++)
+                if (m0 + u * nt < e) fn(m0 + u * nt, (double)x[u]);
+        }
         return;
     }
     uint32_t tpe = 1;
@@ -804,13 +812,22 @@ __global__ __launch_bounds__(kBlock) void k_fin_distribute_a(Ctx c, const DSepFi
     T* __restrict__ acc = static_cast<T*>(c.acc) + (uint64_t)slot * c.sep_stride + f.sep;
     const T* __restrict__ part = static_cast<const T*>(c.part) + (uint64_t)slot * c.part_stride + f.part0;
     const T* __restrict__ sepc = static_cast<const T*>(c.sepc) + (uint64_t)slot * c.sep_stride + f.sep;
+    const uint32_t end = b.begin + b.count;
+    finish_range(f, acc, part, b.begin, end, threadIdx.x, (uint32_t)kBlock,
+                 [&](uint32_t m, double v) { vals[m - b.begin] = v; });
+    __syncthreads();
     double mx = 0.0;
-    finish_range(f, acc, part, b.begin, b.begin + b.count, threadIdx.x, (uint32_t)kBlock, [&](uint32_t m, double v) {
-        vals[m - b.begin] = v;
-        const double den = (double)sepc[m];
-        mx = fmax(mx, den == 0.0 ? 0.0 : v / den);
-    });
-    mx = block_max_all(mx, red);  // (its barriers also publish vals)
+    for (uint32_t m0 = b.begin + threadIdx.x; m0 < end; m0 += 4 * kBlock) {
+        T d[4];
+#pragma unroll
+        for (uint32_t u = 0; u < 4; u++) d[u] = sepc[min(m0 + u * kBlock, end - 1)];
+#pragma unroll
+        for (uint32_t u = 0; u < 4; u++) {
+            const uint32_t m = m0 + u * kBlock;
+            if (m < end) mx = fmax(mx, d[u] == T(0) ? 0.0 : vals[m - b.begin] / (double)d[u]);
+        }
+    }
+    mx = block_max_all(mx, red);
     if (threadIdx.x == 0) c.bmax[(uint64_t)slot * c.bmax_stride + b.id] = mx;
     // this block's share of each posterior sum: the entries with digit x
     // are m = (o * card + x) * stride + r, enumerated by e = o * stride + r
