@@ -659,13 +659,24 @@ __global__ __launch_bounds__(kBlock) void k_dist_gather(Ctx c, const DWork* __re
             }
             const uint32_t lp = map[t2.lp + t];
             const uint32_t per = nk * t2.nQL;
-            for (uint32_t j = sub; j < per; j += tpo) {
-                const uint32_t k = mdiv(j, t2.qlmul, t2.qlsh);
-                const uint32_t u = j - k * t2.nQL;
-                const uint32_t row = packed ? map[t2.rg + g] + map[t2.rq + k] : rowbase + k;
-                const uint32_t idx = gofs + row * L + lp + map[t2.lq + u];
+            // four entries per lane at a time: their map lookups issued together
+            for (uint32_t j0 = sub; j0 < per; j0 += 4 * tpo) {
+                uint32_t idx[4];
 #pragma unroll
-                for (int b = 0; b < B; b++) s[b] += (double)vals[b * c.tile + idx];
+                for (uint32_t y = 0; y < 4; y++) {
+                    const uint32_t j = min(j0 + y * tpo, per - 1);
+                    const uint32_t k = mdiv(j, t2.qlmul, t2.qlsh);
+                    const uint32_t u = j - k * t2.nQL;
+                    const uint32_t row = packed ? map[t2.rg + g] + map[t2.rq + k] : rowbase + k;
+                    idx[y] = gofs + row * L + lp + map[t2.lq + u];
+                }
+#pragma unroll
+                for (uint32_t y = 0; y < 4; y++) {
+                    if (j0 + y * tpo < per) {
+#pragma unroll
+                        for (int b = 0; b < B; b++) s[b] += (double)vals[b * c.tile + idx[y]];
+                    }
+                }
             }
             sep = t2.sep;
             part0 = t2.part0;
