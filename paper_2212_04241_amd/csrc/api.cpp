@@ -888,22 +888,18 @@ static fbn_status enqueue_interleaved(fbn_jt* jt, int32_t n, double wn) {
     HIP_OK(launch_begin(c, sl, n, s));
     // the large separators' running maxima start at zero
     if (!p.finblks.empty()) HIP_OK(launch_zero(jt->d_bmax, 8ull * c.bmax_stride * (uint64_t)jt->opt.max_slots, s));
+    // a layer's finalisers: the small separators and the first phase of the
+    // large ones' blocks in one launch, then the blocks' second phase
     auto fins = [&](const Layer& ly, bool dist, int kind, double bytes) -> fbn_status {
         fbn_status r;
-        if (ly.nfin > ly.nbig) {
-            if ((r = timed(jt, kind, bytes, [&] {
-                     return launch_interleaved(c, prec, dist ? kIlFinDistribute : kIlFinCollect,
-                                               jt->d_fins + ly.fin0 + ly.nbig, ly.nfin - ly.nbig, jt->d_fins, sl, n, s);
-                 })))
-                return r;
-            bytes = 0.0;
-        }
+        if (ly.nfin == ly.nbig && !ly.nfb) return FBN_OK;
+        if ((r = timed(jt, kind, bytes, [&] {
+                 return launch_fin_interleaved(c, prec, dist, jt->d_fins + ly.fin0 + ly.nbig, ly.nfin - ly.nbig,
+                                               jt->d_finblks + ly.fb0, ly.nfb, jt->d_fins, sl, n, s);
+             })))
+            return r;
         if (ly.nfb) {
-            const int ka = dist ? kIlFinDistributeA : kIlFinCollectA, kb = dist ? kIlFinDistributeB : kIlFinCollectB;
-            if ((r = timed(jt, kind, bytes, [&] {
-                     return launch_interleaved(c, prec, ka, jt->d_finblks + ly.fb0, ly.nfb, jt->d_fins, sl, n, s);
-                 })))
-                return r;
+            const int kb = dist ? kIlFinDistributeB : kIlFinCollectB;
             if ((r = timed(jt, kind, 0.0, [&] {
                      return launch_interleaved(c, prec, kb, jt->d_finblks + ly.fb0, ly.nfb, jt->d_fins, sl, n, s);
                  })))

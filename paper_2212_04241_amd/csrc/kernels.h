@@ -73,14 +73,16 @@ hipError_t launch_expand_map(const uint32_t* map, uint32_t mh, uint32_t ml, uint
 hipError_t launch_zero(void* p, size_t bytes, hipStream_t s);
 
 // Slot-interleaved layout (kernels_interleaved.hip): one wave per work item,
-// lanes over the batch.  `items` is the layer's DGroup / DWork / DSepFin /
-// DFinBlk array by kind; `fins` is the whole finaliser array (block kinds).
-enum : int {
-    kIlCollect, kIlDistribute, kIlFinCollect, kIlFinDistribute,
-    kIlFinCollectA, kIlFinCollectB, kIlFinDistributeA, kIlFinDistributeB
-};
+// lanes over the batch.  `items` is the layer's DGroup / DWork / DFinBlk
+// array by kind; `fins` is the whole finaliser array (block kinds).
+enum : int { kIlCollect, kIlDistribute, kIlFinCollectB, kIlFinDistributeB };
 hipError_t launch_interleaved(const Ctx& c, int prec, int kind, const void* items, uint32_t nitems,
                               const DSepFin* fins, const int32_t* slots, int nslots, hipStream_t s);
+// A layer's small separators (`small`, nsmall of them) and the first phase of
+// its large separators' blocks (`blks`, nblks) in one launch.
+hipError_t launch_fin_interleaved(const Ctx& c, int prec, bool dist, const DSepFin* small, uint32_t nsmall,
+                                  const DFinBlk* blks, uint32_t nblks, const DSepFin* fins, const int32_t* slots,
+                                  int nslots, hipStream_t s);
 hipError_t launch_marginals_interleaved(const Ctx& c, const int32_t* slots, int nslots, hipStream_t s);
 
 }  // namespace fbn

@@ -373,10 +373,8 @@ __device__ __forceinline__ void shares_i(const DSepFin& f, const Ctx& c, uint32_
 // After a collect layer: finish, rescale to a max in [0.5, 1), store, and
 // keep the exponent; a root's entry flags impossible evidence.
 template <typename T>
-__global__ __launch_bounds__(kBlock) void k_fin_collect_i(Ctx c, const DSepFin* __restrict__ fins, uint32_t nfins,
-                                                          const int32_t* __restrict__ slots, int nslots) {
-    const uint32_t fi = wave_item();
-    if (fi >= nfins) return;
+__device__ __forceinline__ void fin_collect_small_i(const Ctx& c, const DSepFin* __restrict__ fins, uint32_t fi,
+                                                    const int32_t* __restrict__ slots, int nslots) {
     const int sl = lane_slot(slots, nslots);
     if (sl < 0) return;
     const uint64_t S = c.S, s = (uint64_t)sl;
@@ -404,11 +402,8 @@ __global__ __launch_bounds__(kBlock) void k_fin_collect_i(Ctx c, const DSepFin* 
 // After a distribute layer: finish the new separator, its posterior sums,
 // and for a real separator the ratio new/old (0/0 = 0) rescaled.
 template <typename T>
-__global__ __launch_bounds__(kBlock) void k_fin_distribute_i(Ctx c, const DSepFin* __restrict__ fins,
-                                                             uint32_t nfins, const int32_t* __restrict__ slots,
-                                                             int nslots) {
-    const uint32_t fi = wave_item();
-    if (fi >= nfins) return;
+__device__ __forceinline__ void fin_distribute_small_i(const Ctx& c, const DSepFin* __restrict__ fins, uint32_t fi,
+                                                       const int32_t* __restrict__ slots, int nslots) {
     const int sl = lane_slot(slots, nslots);
     if (sl < 0) return;
     const uint64_t S = c.S, s = (uint64_t)sl;
@@ -495,11 +490,9 @@ __device__ __forceinline__ double fin_max_i(const Ctx& c, const DFinBlk& b, uint
 }
 
 template <typename T>
-__global__ __launch_bounds__(kBlock) void k_fin_collect_ia(Ctx c, const DSepFin* __restrict__ fins,
-                                                           const DFinBlk* __restrict__ blks, uint32_t nblks,
-                                                           const int32_t* __restrict__ slots, int nslots) {
-    const uint32_t bi = wave_item();
-    if (bi >= nblks) return;
+__device__ __forceinline__ void fin_collect_a_i(const Ctx& c, const DSepFin* __restrict__ fins,
+                                                const DFinBlk* __restrict__ blks, uint32_t bi,
+                                                const int32_t* __restrict__ slots, int nslots) {
     const int sl = lane_slot(slots, nslots);
     if (sl < 0) return;
     const uint64_t S = c.S, s = (uint64_t)sl;
@@ -541,11 +534,9 @@ __global__ __launch_bounds__(kBlock) void k_fin_collect_ib(Ctx c, const DSepFin*
 }
 
 template <typename T>
-__global__ __launch_bounds__(kBlock) void k_fin_distribute_ia(Ctx c, const DSepFin* __restrict__ fins,
-                                                              const DFinBlk* __restrict__ blks, uint32_t nblks,
-                                                              const int32_t* __restrict__ slots, int nslots) {
-    const uint32_t bi = wave_item();
-    if (bi >= nblks) return;
+__device__ __forceinline__ void fin_distribute_a_i(const Ctx& c, const DSepFin* __restrict__ fins,
+                                                   const DFinBlk* __restrict__ blks, uint32_t bi,
+                                                   const int32_t* __restrict__ slots, int nslots) {
     const int sl = lane_slot(slots, nslots);
     if (sl < 0) return;
     const uint64_t S = c.S, s = (uint64_t)sl;
@@ -617,6 +608,29 @@ __global__ __launch_bounds__(kBlock) void k_fin_distribute_ib(Ctx c, const DSepF
     }
 }
 
+// A layer's finalisers in one launch: the first nsmall waves take the small
+// separators whole, the next nblks the first phase of the large separators'
+// blocks (their second phase is a launch of its own).
+template <typename T>
+__global__ __launch_bounds__(kBlock) void k_fin_collect_i(Ctx c, const DSepFin* __restrict__ sfins, uint32_t nsmall,
+                                                          const DFinBlk* __restrict__ blks, uint32_t nblks,
+                                                          const DSepFin* __restrict__ fins,
+                                                          const int32_t* __restrict__ slots, int nslots) {
+    const uint32_t wi = wave_item();
+    if (wi < nsmall) fin_collect_small_i<T>(c, sfins, wi, slots, nslots);
+    else if (wi - nsmall < nblks) fin_collect_a_i<T>(c, fins, blks, wi - nsmall, slots, nslots);
+}
+
+template <typename T>
+__global__ __launch_bounds__(kBlock) void k_fin_distribute_i(Ctx c, const DSepFin* __restrict__ sfins,
+                                                             uint32_t nsmall, const DFinBlk* __restrict__ blks,
+                                                             uint32_t nblks, const DSepFin* __restrict__ fins,
+                                                             const int32_t* __restrict__ slots, int nslots) {
+    const uint32_t wi = wave_item();
+    if (wi < nsmall) fin_distribute_small_i<T>(c, sfins, wi, slots, nslots);
+    else if (wi - nsmall < nblks) fin_distribute_a_i<T>(c, fins, blks, wi - nsmall, slots, nslots);
+}
+
 // ---------------------------------------------------------------- posteriors
 
 // Per slot: normalise every variable's marginal into the slot-major
@@ -661,7 +675,6 @@ hipError_t launch_interleaved(const Ctx& c, int prec, int kind, const void* item
     const dim3 block(kBlock);
     const auto* groups = static_cast<const DGroup*>(items);
     const auto* works = static_cast<const DWork*>(items);
-    const auto* sfins = static_cast<const DSepFin*>(items);
     const auto* blks = static_cast<const DFinBlk*>(items);
     switch (kind) {
     case kIlCollect:
@@ -672,27 +685,9 @@ hipError_t launch_interleaved(const Ctx& c, int prec, int kind, const void* item
         if (prec) hipLaunchKernelGGL(k_dist_i<float>, grid, block, 0, st, c, works, nitems, slots, nslots);
         else hipLaunchKernelGGL(k_dist_i<double>, grid, block, 0, st, c, works, nitems, slots, nslots);
         break;
-    case kIlFinCollect:
-        if (prec) hipLaunchKernelGGL(k_fin_collect_i<float>, grid, block, 0, st, c, sfins, nitems, slots, nslots);
-        else hipLaunchKernelGGL(k_fin_collect_i<double>, grid, block, 0, st, c, sfins, nitems, slots, nslots);
-        break;
-    case kIlFinDistribute:
-        if (prec) hipLaunchKernelGGL(k_fin_distribute_i<float>, grid, block, 0, st, c, sfins, nitems, slots, nslots);
-        else hipLaunchKernelGGL(k_fin_distribute_i<double>, grid, block, 0, st, c, sfins, nitems, slots, nslots);
-        break;
-    case kIlFinCollectA:
-        if (prec) hipLaunchKernelGGL(k_fin_collect_ia<float>, grid, block, 0, st, c, fins, blks, nitems, slots, nslots);
-        else hipLaunchKernelGGL(k_fin_collect_ia<double>, grid, block, 0, st, c, fins, blks, nitems, slots, nslots);
-        break;
     case kIlFinCollectB:
         if (prec) hipLaunchKernelGGL(k_fin_collect_ib<float>, grid, block, 0, st, c, fins, blks, nitems, slots, nslots);
         else hipLaunchKernelGGL(k_fin_collect_ib<double>, grid, block, 0, st, c, fins, blks, nitems, slots, nslots);
-        break;
-    case kIlFinDistributeA:
-        if (prec)
-            hipLaunchKernelGGL(k_fin_distribute_ia<float>, grid, block, 0, st, c, fins, blks, nitems, slots, nslots);
-        else
-            hipLaunchKernelGGL(k_fin_distribute_ia<double>, grid, block, 0, st, c, fins, blks, nitems, slots, nslots);
         break;
     case kIlFinDistributeB:
         if (prec)
@@ -702,6 +697,31 @@ hipError_t launch_interleaved(const Ctx& c, int prec, int kind, const void* item
         break;
     default:
         return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_fin_interleaved(const Ctx& c, int prec, bool dist, const DSepFin* small, uint32_t nsmall,
+                                  const DFinBlk* blks, uint32_t nblks, const DSepFin* fins, const int32_t* slots,
+                                  int nslots, hipStream_t st) {
+    const uint32_t n = nsmall + nblks;
+    if (!n || !nslots) return hipSuccess;
+    const dim3 grid((n + kWavesPerBlock - 1) / kWavesPerBlock, (unsigned)((nslots + kLanes - 1) / kLanes));
+    const dim3 block(kBlock);
+    if (dist) {
+        if (prec)
+            hipLaunchKernelGGL(k_fin_distribute_i<float>, grid, block, 0, st, c, small, nsmall, blks, nblks, fins,
+                               slots, nslots);
+        else
+            hipLaunchKernelGGL(k_fin_distribute_i<double>, grid, block, 0, st, c, small, nsmall, blks, nblks, fins,
+                               slots, nslots);
+    } else {
+        if (prec)
+            hipLaunchKernelGGL(k_fin_collect_i<float>, grid, block, 0, st, c, small, nsmall, blks, nblks, fins,
+                               slots, nslots);
+        else
+            hipLaunchKernelGGL(k_fin_collect_i<double>, grid, block, 0, st, c, small, nsmall, blks, nblks, fins,
+                               slots, nslots);
     }
     return hipGetLastError();
 }
