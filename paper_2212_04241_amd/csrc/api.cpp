@@ -939,28 +939,25 @@ static fbn_status enqueue_calibration(fbn_jt* jt, int32_t n) {
     HIP_OK(launch_begin(c, jt->d_slots, n, s));
     const double w = prec ? 4.0 : 8.0, nb = (double)n;
     if (p.interleaved) return enqueue_interleaved(jt, n, w * nb);
-    // a layer's finalisers: small separators one wave each, large ones in
-    // blocks over two launches; the layer's bytes are booked on its first
+    // a layer's finalisers: the small separators (a wave or a workgroup
+    // each) and the first phase of the large ones' blocks in one launch,
+    // then the blocks' second phase; the layer's bytes are booked on the first
     auto finalise = [&](const Layer& ly, bool dist, int kind, double bytes) -> fbn_status {
         fbn_status r;
-        if (ly.nfin > ly.nbig) {
-            const DSepFin* f = jt->d_fins + ly.fin0 + ly.nbig;
-            const uint32_t nf = ly.nfin - ly.nbig;
-            if ((r = timed(jt, kind, bytes, [&] {
-                     return dist ? launch_fin_distribute(c, prec, f, nf, ly.nteam, jt->d_slots, n, s)
-                                 : launch_fin_collect(c, prec, f, nf, ly.nteam, jt->d_slots, n, s);
-                 })))
-                return r;
-            bytes = 0.0;
-        }
-        for (int ph = 0; ph < 2 && ly.nfb; ph++) {
-            if ((r = timed(jt, kind, bytes, [&] {
-                     return launch_fin_blocks(c, prec, dist, ph, jt->d_fins, jt->d_finblks + ly.fb0, ly.nfb,
-                                              jt->d_slots, n, s);
-                 })))
-                return r;
-            bytes = 0.0;
-        }
+        if (ly.nfin == ly.nbig && !ly.nfb) return FBN_OK;
+        const DSepFin* f = jt->d_fins + ly.fin0 + ly.nbig;
+        const uint32_t nf = ly.nfin - ly.nbig;
+        const DFinBlk* fb = jt->d_finblks + ly.fb0;
+        if ((r = timed(jt, kind, bytes, [&] {
+                 return dist ? launch_fin_distribute(c, prec, f, nf, ly.nteam, jt->d_fins, fb, ly.nfb, jt->d_slots, n, s)
+                             : launch_fin_collect(c, prec, f, nf, ly.nteam, jt->d_fins, fb, ly.nfb, jt->d_slots, n, s);
+             })))
+            return r;
+        if (ly.nfb &&
+            (r = timed(jt, kind, 0.0, [&] {
+                 return launch_fin_blocks(c, prec, dist, jt->d_fins, fb, ly.nfb, jt->d_slots, n, s);
+             })))
+            return r;
         return FBN_OK;
     };
     for (size_t h = 0; h < p.collect.size(); h++) {

@@ -54,16 +54,22 @@ inline int slots_per_block(uint32_t tile, int w) {
 // prec: 0 = float64 tables, 1 = float32 tables
 hipError_t launch_collect(const Ctx& c, int prec, const DGroup* groups, uint32_t ngroups,
                           const int32_t* slots, int nslots, hipStream_t s);
-hipError_t launch_fin_collect(const Ctx& c, int prec, const DSepFin* fins, uint32_t nfins, uint32_t nbig,
-                              const int32_t* slots, int nslots, hipStream_t s);
-// Large separators in blocks: phase 0 then phase 1, for the collect
+// A layer's finalisers, first launch: the nsmall small separators `sfins`
+// (the first nbig of them a workgroup each, the rest a wave each) and the
+// first phase of the large separators' blocks `blks` (nblks; `fins` is the
+// whole finaliser array).
+hipError_t launch_fin_collect(const Ctx& c, int prec, const DSepFin* sfins, uint32_t nsmall, uint32_t nbig,
+                              const DSepFin* fins, const DFinBlk* blks, uint32_t nblks, const int32_t* slots,
+                              int nslots, hipStream_t s);
+// Second phase of the large separators' blocks, for the collect
 // (distribute = false) or distribute sweep.
-hipError_t launch_fin_blocks(const Ctx& c, int prec, bool distribute, int phase, const DSepFin* fins,
-                             const DFinBlk* blks, uint32_t nblks, const int32_t* slots, int nslots, hipStream_t s);
+hipError_t launch_fin_blocks(const Ctx& c, int prec, bool distribute, const DSepFin* fins, const DFinBlk* blks,
+                             uint32_t nblks, const int32_t* slots, int nslots, hipStream_t s);
 hipError_t launch_distribute(const Ctx& c, int prec, const DWork* works, uint32_t nworks,
                              const int32_t* slots, int nslots, hipStream_t s);
-hipError_t launch_fin_distribute(const Ctx& c, int prec, const DSepFin* fins, uint32_t nfins, uint32_t nbig,
-                                 const int32_t* slots, int nslots, hipStream_t s);
+hipError_t launch_fin_distribute(const Ctx& c, int prec, const DSepFin* sfins, uint32_t nsmall, uint32_t nbig,
+                                 const DSepFin* fins, const DFinBlk* blks, uint32_t nblks, const int32_t* slots,
+                                 int nslots, hipStream_t s);
 hipError_t launch_marginals(const Ctx& c, const int32_t* slots, int nslots, hipStream_t s);
 hipError_t launch_gather(const Ctx& c, const int32_t* slots, int nslots, double* post_out,
                          double* logpe_out, int32_t* flags_out, hipStream_t s);

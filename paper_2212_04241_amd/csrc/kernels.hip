@@ -349,13 +349,14 @@ struct Team {
     }
 };
 
-__device__ __forceinline__ bool team_of(uint32_t nbig, uint32_t nfins, double* red, Team& t, uint32_t& fi) {
-    if (blockIdx.x < nbig) {
-        fi = blockIdx.x;
+__device__ __forceinline__ bool team_of(uint32_t bx, uint32_t nbig, uint32_t nfins, double* red, Team& t,
+                                        uint32_t& fi) {
+    if (bx < nbig) {
+        fi = bx;
         t = Team{threadIdx.x, (uint32_t)kBlock, true, red};
         return true;
     }
-    fi = nbig + (blockIdx.x - nbig) * kWaves + threadIdx.x / kWave;
+    fi = nbig + (bx - nbig) * kWaves + threadIdx.x / kWave;
     t = Team{threadIdx.x & (kWave - 1), (uint32_t)kWave, false, red};
     return fi < nfins;
 }
@@ -455,12 +456,12 @@ __device__ __forceinline__ void shares_grouped(const DSepFin& f, const Ctx& c, u
 // and record the exponent.  A root's one-entry virtual separator holds its
 // tree's share of P(e); zero there means the evidence is impossible.
 template <typename T>
-__global__ __launch_bounds__(kBlock) void k_fin_collect(Ctx c, const DSepFin* __restrict__ fins, uint32_t nfins,
-                                                        uint32_t nbig, const int32_t* __restrict__ slots) {
+__device__ __forceinline__ void fin_collect_team(const Ctx& c, const DSepFin* __restrict__ fins, uint32_t nfins,
+                                                 uint32_t nbig, const int32_t* __restrict__ slots, uint32_t bx) {
     __shared__ double red[kWaves];
     Team tm;
     uint32_t fi;
-    if (!team_of(nbig, nfins, red, tm, fi)) return;
+    if (!team_of(bx, nbig, nfins, red, tm, fi)) return;
     const uint32_t lane = tm.lane;
     const DSepFin f = fins[fi];
     const int slot = slots[blockIdx.y];
@@ -701,12 +702,12 @@ __global__ __launch_bounds__(kBlock) void k_dist_gather(Ctx c, const DWork* __re
 // marginals of the variables assigned to it, and for a real separator form
 // the new/old ratio S*/S (0/0 = 0) rescaled by an exact power of two.
 template <typename T>
-__global__ __launch_bounds__(kBlock) void k_fin_distribute(Ctx c, const DSepFin* __restrict__ fins, uint32_t nfins,
-                                                           uint32_t nbig, const int32_t* __restrict__ slots) {
+__device__ __forceinline__ void fin_distribute_team(const Ctx& c, const DSepFin* __restrict__ fins, uint32_t nfins,
+                                                    uint32_t nbig, const int32_t* __restrict__ slots, uint32_t bx) {
     __shared__ double red[kWaves];
     Team tm;
     uint32_t fi;
-    if (!team_of(nbig, nfins, red, tm, fi)) return;
+    if (!team_of(bx, nbig, nfins, red, tm, fi)) return;
     const uint32_t lane = tm.lane;
     const DSepFin f = fins[fi];
     const int slot = slots[blockIdx.y];
@@ -775,11 +776,11 @@ __device__ __forceinline__ double fin_max(const Ctx& c, const DFinBlk& b, int sl
 }
 
 template <typename T>
-__global__ __launch_bounds__(kBlock) void k_fin_collect_a(Ctx c, const DSepFin* __restrict__ fins,
-                                                          const DFinBlk* __restrict__ blks,
-                                                          const int32_t* __restrict__ slots) {
+__device__ __forceinline__ void fin_collect_a(const Ctx& c, const DSepFin* __restrict__ fins,
+                                              const DFinBlk* __restrict__ blks, const int32_t* __restrict__ slots,
+                                              uint32_t bx) {
     __shared__ double red[kWaves];
-    const DFinBlk b = blks[blockIdx.x];
+    const DFinBlk b = blks[bx];
     const DSepFin f = fins[b.fin];
     const int slot = slots[blockIdx.y];
     T* __restrict__ acc = static_cast<T*>(c.acc) + (uint64_t)slot * c.sep_stride + f.sep;
@@ -812,31 +813,34 @@ __global__ __launch_bounds__(kBlock) void k_fin_collect_b(Ctx c, const DSepFin* 
 }
 
 template <typename T>
-__global__ __launch_bounds__(kBlock) void k_fin_distribute_a(Ctx c, const DSepFin* __restrict__ fins,
-                                                             const DFinBlk* __restrict__ blks,
-                                                             const int32_t* __restrict__ slots) {
+__device__ __forceinline__ void fin_distribute_a(const Ctx& c, const DSepFin* __restrict__ fins,
+                                                 const DFinBlk* __restrict__ blks, const int32_t* __restrict__ slots,
+                                                 uint32_t bx) {
     __shared__ double red[kWaves];
-    __shared__ double vals[kFinBlock];
-    const DFinBlk b = blks[blockIdx.x];
+    const DFinBlk b = blks[bx];
     const DSepFin f = fins[b.fin];
     const int slot = slots[blockIdx.y];
     T* __restrict__ acc = static_cast<T*>(c.acc) + (uint64_t)slot * c.sep_stride + f.sep;
     const T* __restrict__ part = static_cast<const T*>(c.part) + (uint64_t)slot * c.part_stride + f.part0;
     const T* __restrict__ sepc = static_cast<const T*>(c.sepc) + (uint64_t)slot * c.sep_stride + f.sep;
     const uint32_t end = b.begin + b.count;
-    finish_range(f, acc, part, b.begin, end, threadIdx.x, (uint32_t)kBlock,
-                 [&](uint32_t m, double v) { vals[m - b.begin] = v; });
-    __syncthreads();
+    // the block's new values are read back as stored (other lanes wrote them)
+    if (f.nchunk) {
+        finish_range(f, acc, part, b.begin, end, threadIdx.x, (uint32_t)kBlock, [](uint32_t, double) {});
+        __syncthreads();
+    }
     double mx = 0.0;
     for (uint32_t m0 = b.begin + threadIdx.x; m0 < end; m0 += 4 * kBlock) {
-        T d[4];
-#pragma unroll
-        for (uint32_t u = 0; u < 4; u++) d[u] = sepc[min(m0 + u * kBlock, end - 1)];
+        T d[4], v[4];
 #pragma unroll
         for (uint32_t u = 0; u < 4; u++) {
-            const uint32_t m = m0 + u * kBlock;
-            if (m < end) mx = fmax(mx, d[u] == T(0) ? 0.0 : vals[m - b.begin] / (double)d[u]);
+            const uint32_t m = min(m0 + u * kBlock, end - 1);
+            d[u] = sepc[m];
+            v[u] = acc[m];
         }
+#pragma unroll
+        for (uint32_t u = 0; u < 4; u++)
+            if (m0 + u * kBlock < end) mx = fmax(mx, d[u] == T(0) ? 0.0 : (double)v[u] / (double)d[u]);
     }
     mx = block_max_all(mx, red);
     if (threadIdx.x == 0) c.bmax[(uint64_t)slot * c.bmax_stride + b.id] = mx;
@@ -844,7 +848,7 @@ __global__ __launch_bounds__(kBlock) void k_fin_distribute_a(Ctx c, const DSepFi
     // are m = (o * card + x) * stride + r, enumerated by e = o * stride + r
     double* __restrict__ bm = c.bmarg + (uint64_t)slot * c.bmarg_stride + b.mbase + (b.id - b.blk0) * b.mw;
     shares_grouped(f, c, b.begin, b.begin + b.count, b.mw, threadIdx.x, (uint32_t)kBlock,
-                   [&](uint32_t m) { return vals[m - b.begin]; },
+                   [&](uint32_t m) { return (double)acc[m]; },
                    [&](uint32_t k, const DMargVar&, uint32_t, double s) { bm[k] = s; });
 }
 
@@ -1014,6 +1018,28 @@ void launch_gather_t(const Ctx& c, const DWork* works, uint32_t nworks, const in
     else launch_gather_b<T, 1>(c, works, nworks, slots, nslots, s);
 }
 
+// A layer's finalisers in one launch: the first nteam workgroups finish the
+// small separators (team per separator, as above), the next ones run the
+// first phase of the large separators' blocks, one workgroup per block.
+template <typename T>
+__global__ __launch_bounds__(kBlock) void k_fin_collect(Ctx c, const DSepFin* __restrict__ sfins, uint32_t nsmall,
+                                                        uint32_t nbig, uint32_t nteam, const DSepFin* __restrict__ fins,
+                                                        const DFinBlk* __restrict__ blks,
+                                                        const int32_t* __restrict__ slots) {
+    if (blockIdx.x < nteam) fin_collect_team<T>(c, sfins, nsmall, nbig, slots, blockIdx.x);
+    else fin_collect_a<T>(c, fins, blks, slots, blockIdx.x - nteam);
+}
+
+template <typename T>
+__global__ __launch_bounds__(kBlock) void k_fin_distribute(Ctx c, const DSepFin* __restrict__ sfins, uint32_t nsmall,
+                                                           uint32_t nbig, uint32_t nteam,
+                                                           const DSepFin* __restrict__ fins,
+                                                           const DFinBlk* __restrict__ blks,
+                                                           const int32_t* __restrict__ slots) {
+    if (blockIdx.x < nteam) fin_distribute_team<T>(c, sfins, nsmall, nbig, slots, blockIdx.x);
+    else fin_distribute_a<T>(c, fins, blks, slots, blockIdx.x - nteam);
+}
+
 }  // namespace
 
 hipError_t launch_collect(const Ctx& c, int prec, const DGroup* groups, uint32_t ngroups, const int32_t* slots,
@@ -1024,28 +1050,28 @@ hipError_t launch_collect(const Ctx& c, int prec, const DGroup* groups, uint32_t
     return hipGetLastError();
 }
 
-hipError_t launch_fin_collect(const Ctx& c, int prec, const DSepFin* fins, uint32_t nfins, uint32_t nbig,
-                              const int32_t* slots, int nslots, hipStream_t s) {
-    if (!nfins || !nslots) return hipSuccess;
-    dim3 grid(nbig + (nfins - nbig + kWaves - 1) / kWaves, (unsigned)nslots);
-    if (prec) hipLaunchKernelGGL(k_fin_collect<float>, grid, dim3(kBlock), 0, s, c, fins, nfins, nbig, slots);
-    else hipLaunchKernelGGL(k_fin_collect<double>, grid, dim3(kBlock), 0, s, c, fins, nfins, nbig, slots);
+hipError_t launch_fin_collect(const Ctx& c, int prec, const DSepFin* sfins, uint32_t nsmall, uint32_t nbig,
+                              const DSepFin* fins, const DFinBlk* blks, uint32_t nblks, const int32_t* slots,
+                              int nslots, hipStream_t s) {
+    const uint32_t nteam = nsmall ? nbig + (nsmall - nbig + kWaves - 1) / kWaves : 0;
+    if (!(nteam + nblks) || !nslots) return hipSuccess;
+    dim3 grid(nteam + nblks, (unsigned)nslots);
+    if (prec)
+        hipLaunchKernelGGL(k_fin_collect<float>, grid, dim3(kBlock), 0, s, c, sfins, nsmall, nbig, nteam, fins, blks,
+                           slots);
+    else
+        hipLaunchKernelGGL(k_fin_collect<double>, grid, dim3(kBlock), 0, s, c, sfins, nsmall, nbig, nteam, fins, blks,
+                           slots);
     return hipGetLastError();
 }
 
-hipError_t launch_fin_blocks(const Ctx& c, int prec, bool distribute, int phase, const DSepFin* fins,
-                             const DFinBlk* blks, uint32_t nblks, const int32_t* slots, int nslots, hipStream_t s) {
+hipError_t launch_fin_blocks(const Ctx& c, int prec, bool distribute, const DSepFin* fins, const DFinBlk* blks,
+                             uint32_t nblks, const int32_t* slots, int nslots, hipStream_t s) {
     if (!nblks || !nslots) return hipSuccess;
     const dim3 grid(nblks, (unsigned)nslots), block(kBlock);
-    if (!distribute && phase == 0) {
-        if (prec) hipLaunchKernelGGL(k_fin_collect_a<float>, grid, block, 0, s, c, fins, blks, slots);
-        else hipLaunchKernelGGL(k_fin_collect_a<double>, grid, block, 0, s, c, fins, blks, slots);
-    } else if (!distribute) {
+    if (!distribute) {
         if (prec) hipLaunchKernelGGL(k_fin_collect_b<float>, grid, block, 0, s, c, fins, blks, slots);
         else hipLaunchKernelGGL(k_fin_collect_b<double>, grid, block, 0, s, c, fins, blks, slots);
-    } else if (phase == 0) {
-        if (prec) hipLaunchKernelGGL(k_fin_distribute_a<float>, grid, block, 0, s, c, fins, blks, slots);
-        else hipLaunchKernelGGL(k_fin_distribute_a<double>, grid, block, 0, s, c, fins, blks, slots);
     } else {
         if (prec) hipLaunchKernelGGL(k_fin_distribute_b<float>, grid, block, 0, s, c, fins, blks, slots);
         else hipLaunchKernelGGL(k_fin_distribute_b<double>, grid, block, 0, s, c, fins, blks, slots);
@@ -1061,12 +1087,18 @@ hipError_t launch_distribute(const Ctx& c, int prec, const DWork* works, uint32_
     return hipGetLastError();
 }
 
-hipError_t launch_fin_distribute(const Ctx& c, int prec, const DSepFin* fins, uint32_t nfins, uint32_t nbig,
-                                 const int32_t* slots, int nslots, hipStream_t s) {
-    if (!nfins || !nslots) return hipSuccess;
-    dim3 grid(nbig + (nfins - nbig + kWaves - 1) / kWaves, (unsigned)nslots);
-    if (prec) hipLaunchKernelGGL(k_fin_distribute<float>, grid, dim3(kBlock), 0, s, c, fins, nfins, nbig, slots);
-    else hipLaunchKernelGGL(k_fin_distribute<double>, grid, dim3(kBlock), 0, s, c, fins, nfins, nbig, slots);
+hipError_t launch_fin_distribute(const Ctx& c, int prec, const DSepFin* sfins, uint32_t nsmall, uint32_t nbig,
+                                 const DSepFin* fins, const DFinBlk* blks, uint32_t nblks, const int32_t* slots,
+                                 int nslots, hipStream_t s) {
+    const uint32_t nteam = nsmall ? nbig + (nsmall - nbig + kWaves - 1) / kWaves : 0;
+    if (!(nteam + nblks) || !nslots) return hipSuccess;
+    dim3 grid(nteam + nblks, (unsigned)nslots);
+    if (prec)
+        hipLaunchKernelGGL(k_fin_distribute<float>, grid, dim3(kBlock), 0, s, c, sfins, nsmall, nbig, nteam, fins,
+                           blks, slots);
+    else
+        hipLaunchKernelGGL(k_fin_distribute<double>, grid, dim3(kBlock), 0, s, c, sfins, nsmall, nbig, nteam, fins,
+                           blks, slots);
     return hipGetLastError();
 }
 
