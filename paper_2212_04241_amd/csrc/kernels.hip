@@ -565,61 +565,85 @@ __global__ __launch_bounds__(kBlock) void k_dist_gather(Ctx c, const DWork* __re
         psi_b[b] = static_cast<const T*>(c.psi) + s * c.psi_stride;
         sepd_b[b] = static_cast<const T*>(c.sepd) + s * c.sep_stride;
     }
-    // packed: the current run's fields, reloaded only when the run changes
-    uint32_t p = 0, r_end = 0, r_gofs = 0, r_L = 1, r_Lmul = 0, r_Lsh = 0, r_psep = 0, r_pmh = 0, r_pml = 0;
-    uint64_t r_off = 0;
-    int32_t r_pedge = -1;
-    bool first = true;
-    for (uint32_t gi = threadIdx.x; gi < n; gi += kBlock) {
-        uint64_t off;
-        uint32_t row, l, ent;
-        int32_t pedge;
-        uint32_t pr = 0;
-        if (packed) {
+    if (!packed) {
+        // two entries per thread at a time, their map lookups and every
+        // slot's psi and ratio loads issued together (a slot past the batch
+        // reads slot 0's tables)
+        constexpr uint32_t U = 2;
+        const bool ratio = q.pedge >= 0;
+        for (uint32_t g0 = threadIdx.x; g0 < n; g0 += U * kBlock) {
+            uint32_t ent[U], row[U], lo[U], pr[U];
+#pragma unroll
+            for (uint32_t u = 0; u < U; u++) {
+                const uint32_t gi = min(g0 + u * kBlock, n - 1);
+                const uint32_t ri = mdiv(gi, q.Lmul, q.Lsh);
+                lo[u] = gi - ri * q.L;
+                const uint32_t gg = mdiv(ri, w.nkmul, w.nksh);
+                const uint32_t k = ri - gg * w.nk;
+                row[u] = map[tg.rg + w.g0 + gg] + map[tg.rq + w.k0 + k];
+                ent[u] = row[u] * q.L + lo[u];
+                pr[u] = 0u;
+            }
+            if (ratio) {
+#pragma unroll
+                for (uint32_t u = 0; u < U; u++) pr[u] = q.psep + map[q.pmh + row[u]] + map[q.pml + lo[u]];
+            }
+            T v[U][B], r[U][B];
+#pragma unroll
+            for (uint32_t u = 0; u < U; u++)
+#pragma unroll
+                for (int b = 0; b < B; b++) {
+                    v[u][b] = psi_b[b][q.off + ent[u]];
+                    r[u][b] = sepd_b[b][pr[u]];
+                }
+#pragma unroll
+            for (uint32_t u = 0; u < U; u++) {
+                const uint32_t gi = g0 + u * kBlock;
+                if (gi >= n) continue;
+#pragma unroll
+                for (int b = 0; b < B; b++)
+                    if (sl[b] >= 0) vals[b * c.tile + gi] = ratio ? v[u][b] * r[u][b] : v[u][b];
+            }
+        }
+    } else {
+        // packed: the current run's fields, reloaded only when the run changes
+        uint32_t p = 0, r_end = 0, r_gofs = 0, r_L = 1, r_Lmul = 0, r_Lsh = 0, r_psep = 0, r_pmh = 0, r_pml = 0;
+        uint64_t r_off = 0;
+        int32_t r_pedge = -1;
+        bool first = true;
+        for (uint32_t gi = threadIdx.x; gi < n; gi += kBlock) {
             if (first || gi >= r_end) {
                 if (!first) p++;
                 while (gi >= runs[p].gofs + runs[p].count) p++;
                 first = false;
-                const RunD& r = runs[p];
-                r_end = r.gofs + r.count;
-                r_gofs = r.gofs;
-                r_L = r.L;
-                r_Lmul = r.Lmul;
-                r_Lsh = r.Lsh;
-                r_off = r.off;
-                r_pedge = r.pedge;
-                r_psep = r.psep;
-                r_pmh = r.pmh;
-                r_pml = r.pml;
+                const RunD& rr = runs[p];
+                r_end = rr.gofs + rr.count;
+                r_gofs = rr.gofs;
+                r_L = rr.L;
+                r_Lmul = rr.Lmul;
+                r_Lsh = rr.Lsh;
+                r_off = rr.off;
+                r_pedge = rr.pedge;
+                r_psep = rr.psep;
+                r_pmh = rr.pmh;
+                r_pml = rr.pml;
             }
-            ent = gi - r_gofs;
-            row = mdiv(ent, r_Lmul, r_Lsh);
-            l = ent - row * r_L;
-            off = r_off;
-            pedge = r_pedge;
-            if (pedge >= 0) pr = r_psep + map[r_pmh + row] + map[r_pml + l];
-        } else {
-            const uint32_t ri = mdiv(gi, q.Lmul, q.Lsh);
-            l = gi - ri * q.L;
-            const uint32_t gg = mdiv(ri, w.nkmul, w.nksh);
-            const uint32_t k = ri - gg * w.nk;
-            row = map[tg.rg + w.g0 + gg] + map[tg.rq + w.k0 + k];
-            ent = row * q.L + l;
-            off = q.off;
-            pedge = q.pedge;
-            if (pedge >= 0) pr = q.psep + map[q.pmh + row] + map[q.pml + l];
-        }
-        // every slot's loads issued together (a slot past the batch reads
-        // slot 0's tables; a root clique reads ratio entry 0, unused)
-        T v[B], r[B];
+            const uint32_t ent = gi - r_gofs;
+            const uint32_t row = mdiv(ent, r_Lmul, r_Lsh);
+            const uint32_t l = ent - row * r_L;
+            const uint32_t pr = r_pedge >= 0 ? r_psep + map[r_pmh + row] + map[r_pml + l] : 0u;
+            // every slot's loads issued together (a slot past the batch reads
+            // slot 0's tables; a root clique reads ratio entry 0, unused)
+            T v[B], r[B];
 #pragma unroll
-        for (int b = 0; b < B; b++) {
-            v[b] = psi_b[b][off + ent];
-            r[b] = sepd_b[b][pr];
-        }
+            for (int b = 0; b < B; b++) {
+                v[b] = psi_b[b][r_off + ent];
+                r[b] = sepd_b[b][pr];
+            }
 #pragma unroll
-        for (int b = 0; b < B; b++)
-            if (sl[b] >= 0) vals[b * c.tile + gi] = pedge >= 0 ? v[b] * r[b] : v[b];
+            for (int b = 0; b < B; b++)
+                if (sl[b] >= 0) vals[b * c.tile + gi] = r_pedge >= 0 ? v[b] * r[b] : v[b];
+        }
     }
     __syncthreads();
 
