@@ -121,35 +121,77 @@ struct EntryC {
     uint32_t gi, child0, nchild;
 };
 
-template <typename T, int B, int NC>
-__device__ __forceinline__ void collect_entry(const Ctx& c, const EntryC<T, B>& e, const DEvidence (&ev)[B],
-                                              const int (&sl)[B], const uint32_t (&ksep)[kMaxKids],
-                                              const uint32_t (&kmh)[kMaxKids], const uint32_t (&kml)[kMaxKids],
-                                              T* const (&psi_b)[B], const T* const (&sepc_b)[B], T* vals) {
+template <typename T, int B, int NC, int U>
+__device__ __forceinline__ void collect_entries(const Ctx& c, const EntryC<T, B> (&e)[U], uint32_t nvalid,
+                                                const DEvidence (&ev)[B], const int (&sl)[B],
+                                                const uint32_t (&ksep)[kMaxKids], const uint32_t (&kmh)[kMaxKids],
+                                                const uint32_t (&kml)[kMaxKids], T* const (&psi_b)[B],
+                                                const T* const (&sepc_b)[B], T* vals) {
     constexpr int NW = NC > 0 ? NC : 1;
     const uint32_t* __restrict__ map = c.map;
-    uint32_t jk[NW];
+    uint32_t jk[U][NW];
 #pragma unroll
-    for (int k = 0; k < NC; k++) jk[k] = ksep[k] + map[kmh[k] + e.hi] + map[kml[k] + e.lo];
-    T w[B][NW];
+    for (int u = 0; u < U; u++)
 #pragma unroll
-    for (int b = 0; b < B; b++)
+        for (int k = 0; k < NC; k++) jk[u][k] = ksep[k] + map[kmh[k] + e[u].hi] + map[kml[k] + e[u].lo];
+    T w[U][B][NW];
 #pragma unroll
-        for (int k = 0; k < NC; k++) w[b][k] = sepc_b[b][jk[k]];  // a slot past the batch reads slot 0's
+    for (int u = 0; u < U; u++)
 #pragma unroll
-    for (int b = 0; b < B; b++) {
-        if (sl[b] < 0) continue;
-        T v = ((e.dig ^ ev[b].want) & ev[b].mask) ? T(0) : e.prior;
+        for (int b = 0; b < B; b++)
 #pragma unroll
-        for (int k = 0; k < NC; k++) v *= w[b][k];
-        if (NC == kMaxKids) {
-            for (uint32_t k = kMaxKids; k < e.nchild; k++) {
-                const DChild ch = c.ch[e.child0 + k];
-                v *= sepc_b[b][ch.sep + map[ch.mh + e.hi] + map[ch.ml + e.lo]];
+            for (int k = 0; k < NC; k++) w[u][b][k] = sepc_b[b][jk[u][k]];  // a slot past the batch reads slot 0's
+#pragma unroll
+    for (int u = 0; u < U; u++) {
+        if ((uint32_t)u >= nvalid) break;
+#pragma unroll
+        for (int b = 0; b < B; b++) {
+            if (sl[b] < 0) continue;
+            T v = ((e[u].dig ^ ev[b].want) & ev[b].mask) ? T(0) : e[u].prior;
+#pragma unroll
+            for (int k = 0; k < NC; k++) v *= w[u][b][k];
+            if (NC == kMaxKids) {
+                for (uint32_t k = kMaxKids; k < e[u].nchild; k++) {
+                    const DChild ch = c.ch[e[u].child0 + k];
+                    v *= sepc_b[b][ch.sep + map[ch.mh + e[u].hi] + map[ch.ml + e[u].lo]];
+                }
             }
+            psi_b[b][e[u].toff] = v;
+            vals[b * c.tile + e[u].gi] = v;
         }
-        psi_b[b][e.toff] = v;
-        vals[b * c.tile + e.gi] = v;
+    }
+}
+
+// A group that is one run of one clique: U entries per thread at a time
+// (as many as keep U x B x children loads in registers), their lookups and
+// loads issued together.
+template <typename T, int B, int NC>
+__device__ __forceinline__ void collect_run(const Ctx& c, uint32_t total, uint32_t r_base, uint32_t L, uint32_t Lmul,
+                                            uint32_t Lsh, uint32_t hdig, uint32_t ldig, bool anyev,
+                                            const T* r_prior, uint64_t poff, uint32_t child0, uint32_t nk,
+                                            const DEvidence (&ev)[B], const int (&sl)[B],
+                                            const uint32_t (&ksep)[kMaxKids], const uint32_t (&kmh)[kMaxKids],
+                                            const uint32_t (&kml)[kMaxKids], T* const (&psi_b)[B],
+                                            const T* const (&sepc_b)[B], T* vals) {
+    constexpr int NW = NC > 0 ? NC : 1;
+    constexpr int U = B * NW <= 8 ? 4 : (B * NW <= 16 ? 2 : 1);
+    for (uint32_t g0 = threadIdx.x; g0 < total; g0 += U * kBlock) {
+        EntryC<T, B> e[U];
+#pragma unroll
+        for (int u = 0; u < U; u++) {
+            const uint32_t gi = min(g0 + (uint32_t)u * kBlock, total - 1);
+            const uint32_t i = gi + r_base;
+            e[u].hi = mdiv(i, Lmul, Lsh);
+            e[u].lo = i - e[u].hi * L;
+            e[u].prior = r_prior[i];
+            e[u].dig = anyev ? (c.dig[hdig + e[u].hi] | c.dig[ldig + e[u].lo]) : 0;
+            e[u].toff = poff + i;
+            e[u].gi = gi;
+            e[u].child0 = child0;
+            e[u].nchild = nk;
+        }
+        const uint32_t nvalid = min((uint32_t)U, (total - g0 + kBlock - 1) / kBlock);
+        collect_entries<T, B, NC, U>(c, e, nvalid, ev, sl, ksep, kmh, kml, psi_b, sepc_b, vals);
     }
 }
 
@@ -228,52 +270,86 @@ __global__ __launch_bounds__(kBlock) void k_collect(Ctx c, const DGroup* __restr
     DEvidence ev[B];
     uint64_t anyev = 0;
     bool first = true;
-    for (uint32_t gi = threadIdx.x; gi < g.total; gi += kBlock) {
-        if (first || gi >= r_end) {
-            if (!first) p++;
-            while (gi >= runs[p].gofs + runs[p].count) p++;
-            first = false;
-            const RunC& r = runs[p];
-            r_end = r.gofs + r.count;
-            r_base = r.begin - r.gofs;     // entry = gi + r_base
-            r_L = r.L;
-            r_Lmul = r.Lmul;
-            r_Lsh = r.Lsh;
-            r_hdig = r.hdig;
-            r_ldig = r.ldig;
-            nk = r.nchild;
-            r_prior = prior + r.off;
+    if (g.npiece == 1) {
+        // one run: its fields once, several entries per thread at a time
+        const RunC& r = runs[0];
 #pragma unroll
-            for (int k = 0; k < kMaxKids; k++)
-                if (k < (int)nk) {
-                    ksep[k] = kids[p][k].sep;
-                    kmh[k] = kids[p][k].mh;
-                    kml[k] = kids[p][k].ml;
-                }
-            anyev = 0;
-#pragma unroll
-            for (int b = 0; b < B; b++) {
-                ev[b] = evs[p][b];
-                anyev |= ev[b].mask;
+        for (int k = 0; k < kMaxKids; k++)
+            if (k < (int)r.nchild) {
+                ksep[k] = kids[0][k].sep;
+                kmh[k] = kids[0][k].mh;
+                kml[k] = kids[0][k].ml;
             }
+#pragma unroll
+        for (int b = 0; b < B; b++) {
+            ev[b] = evs[0][b];
+            anyev |= ev[b].mask;
         }
-        const uint32_t i = gi + r_base;
-        const uint32_t hi = mdiv(i, r_Lmul, r_Lsh);
-        const uint32_t lo = i - hi * r_L;
-        const T pv = r_prior[i];
-        const uint64_t d = anyev ? (c.dig[r_hdig + hi] | c.dig[r_ldig + lo]) : 0;
-        const uint64_t toff = (uint64_t)(r_prior - prior) + i;
-        const EntryC<T, B> e{hi, lo, pv, d, toff, gi, runs[p].child0, nk};
-        switch (nk) {
-        case 0: collect_entry<T, B, 0>(c, e, ev, sl, ksep, kmh, kml, psi_b, sepc_b, vals); break;
-        case 1: collect_entry<T, B, 1>(c, e, ev, sl, ksep, kmh, kml, psi_b, sepc_b, vals); break;
-        case 2: collect_entry<T, B, 2>(c, e, ev, sl, ksep, kmh, kml, psi_b, sepc_b, vals); break;
-        case 3: collect_entry<T, B, 3>(c, e, ev, sl, ksep, kmh, kml, psi_b, sepc_b, vals); break;
-        case 4: collect_entry<T, B, 4>(c, e, ev, sl, ksep, kmh, kml, psi_b, sepc_b, vals); break;
-        case 5: collect_entry<T, B, 5>(c, e, ev, sl, ksep, kmh, kml, psi_b, sepc_b, vals); break;
-        case 6: collect_entry<T, B, 6>(c, e, ev, sl, ksep, kmh, kml, psi_b, sepc_b, vals); break;
-        case 7: collect_entry<T, B, 7>(c, e, ev, sl, ksep, kmh, kml, psi_b, sepc_b, vals); break;
-        default: collect_entry<T, B, kMaxKids>(c, e, ev, sl, ksep, kmh, kml, psi_b, sepc_b, vals); break;
+        const uint32_t rb = r.begin - r.gofs;
+        const T* rp = prior + r.off;
+        switch (r.nchild) {
+#define FBN_RUN(NC)                                                                                                   \
+    collect_run<T, B, NC>(c, g.total, rb, r.L, r.Lmul, r.Lsh, r.hdig, r.ldig, anyev != 0, rp, r.off, r.child0,      \
+                          r.nchild, ev, sl, ksep, kmh, kml, psi_b, sepc_b, vals)
+        case 0: FBN_RUN(0); break;
+        case 1: FBN_RUN(1); break;
+        case 2: FBN_RUN(2); break;
+        case 3: FBN_RUN(3); break;
+        case 4: FBN_RUN(4); break;
+        case 5: FBN_RUN(5); break;
+        case 6: FBN_RUN(6); break;
+        case 7: FBN_RUN(7); break;
+        default: FBN_RUN(kMaxKids); break;
+#undef FBN_RUN
+        }
+    } else {
+        for (uint32_t gi = threadIdx.x; gi < g.total; gi += kBlock) {
+            if (first || gi >= r_end) {
+                if (!first) p++;
+                while (gi >= runs[p].gofs + runs[p].count) p++;
+                first = false;
+                const RunC& r = runs[p];
+                r_end = r.gofs + r.count;
+                r_base = r.begin - r.gofs;     // entry = gi + r_base
+                r_L = r.L;
+                r_Lmul = r.Lmul;
+                r_Lsh = r.Lsh;
+                r_hdig = r.hdig;
+                r_ldig = r.ldig;
+                nk = r.nchild;
+                r_prior = prior + r.off;
+    #pragma unroll
+                for (int k = 0; k < kMaxKids; k++)
+                    if (k < (int)nk) {
+                        ksep[k] = kids[p][k].sep;
+                        kmh[k] = kids[p][k].mh;
+                        kml[k] = kids[p][k].ml;
+                    }
+                anyev = 0;
+    #pragma unroll
+                for (int b = 0; b < B; b++) {
+                    ev[b] = evs[p][b];
+                    anyev |= ev[b].mask;
+                }
+            }
+            const uint32_t i = gi + r_base;
+            const uint32_t hi = mdiv(i, r_Lmul, r_Lsh);
+            const uint32_t lo = i - hi * r_L;
+            const T pv = r_prior[i];
+            const uint64_t d = anyev ? (c.dig[r_hdig + hi] | c.dig[r_ldig + lo]) : 0;
+            const uint64_t toff = (uint64_t)(r_prior - prior) + i;
+            const EntryC<T, B> e[1] = {{hi, lo, pv, d, toff, gi, runs[p].child0, nk}};
+            switch (nk) {
+            case 0: collect_entries<T, B, 0, 1>(c, e, 1u, ev, sl, ksep, kmh, kml, psi_b, sepc_b, vals); break;
+            case 1: collect_entries<T, B, 1, 1>(c, e, 1u, ev, sl, ksep, kmh, kml, psi_b, sepc_b, vals); break;
+            case 2: collect_entries<T, B, 2, 1>(c, e, 1u, ev, sl, ksep, kmh, kml, psi_b, sepc_b, vals); break;
+            case 3: collect_entries<T, B, 3, 1>(c, e, 1u, ev, sl, ksep, kmh, kml, psi_b, sepc_b, vals); break;
+            case 4: collect_entries<T, B, 4, 1>(c, e, 1u, ev, sl, ksep, kmh, kml, psi_b, sepc_b, vals); break;
+            case 5: collect_entries<T, B, 5, 1>(c, e, 1u, ev, sl, ksep, kmh, kml, psi_b, sepc_b, vals); break;
+            case 6: collect_entries<T, B, 6, 1>(c, e, 1u, ev, sl, ksep, kmh, kml, psi_b, sepc_b, vals); break;
+            case 7: collect_entries<T, B, 7, 1>(c, e, 1u, ev, sl, ksep, kmh, kml, psi_b, sepc_b, vals); break;
+            default: collect_entries<T, B, kMaxKids, 1>(c, e, 1u, ev, sl, ksep, kmh, kml, psi_b, sepc_b, vals); break;
+            }
         }
     }
     __syncthreads();
@@ -566,10 +642,10 @@ __global__ __launch_bounds__(kBlock) void k_dist_gather(Ctx c, const DWork* __re
         sepd_b[b] = static_cast<const T*>(c.sepd) + s * c.sep_stride;
     }
     if (!packed) {
-        // two entries per thread at a time, their map lookups and every
+        // four entries per thread at a time, their map lookups and every
         // slot's psi and ratio loads issued together (a slot past the batch
         // reads slot 0's tables)
-        constexpr uint32_t U = 2;
+        constexpr uint32_t U = 4;
         const bool ratio = q.pedge >= 0;
         for (uint32_t g0 = threadIdx.x; g0 < n; g0 += U * kBlock) {
             uint32_t ent[U], row[U], lo[U], pr[U];
