@@ -333,7 +333,8 @@ SlotLayout slot_layout(const fbn_jt* jt) {
     L.kexp_stride = (uint32_t)((jt->tree.ne + 1 + 63) / 64 * 64);
     L.marg_stride = p.marg_total;
     L.ev_stride = (uint32_t)jt->tree.nc;
-    L.bmax_stride = (uint32_t)std::max<size_t>(p.finblks.size(), 1);
+    // per-slot layout: one maximum per block; interleaved: one per large separator
+    L.bmax_stride = (uint32_t)std::max<size_t>(p.interleaved ? p.n_bigfin : p.finblks.size(), 1);
     L.bmarg_stride = std::max<uint32_t>(p.n_bmarg, 1);
     // separator sums and partial sums are stored in table precision
     const size_t u[kSlotBuffers] = {w * L.psi_stride, w * p.sep_stride, w * p.sep_stride, w * p.sep_stride,

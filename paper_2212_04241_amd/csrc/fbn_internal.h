@@ -130,6 +130,7 @@ struct DFinBlk {
     uint32_t begin, count;
     uint32_t id, blk0, nblk;
     uint32_t mbase, mw;
+    uint32_t mx;  // the separator's index among the large ones (its running maximum, interleaved layout)
 };
 
 // A variable whose posterior is the marginal of a calibrated separator.

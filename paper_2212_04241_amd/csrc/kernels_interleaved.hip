@@ -482,11 +482,11 @@ __device__ __forceinline__ void fin_distribute_small_i(const Ctx& c, const DSepF
 // split its posterior sums between them, each adding one sum's block
 // shares in block order.
 __device__ __forceinline__ void fold_max(const Ctx& c, const DFinBlk& b, uint64_t S, uint64_t s, double mx) {
-    atomicMax(reinterpret_cast<unsigned long long*>(c.bmax) + (uint64_t)b.blk0 * S + s,
+    atomicMax(reinterpret_cast<unsigned long long*>(c.bmax) + (uint64_t)b.mx * S + s,
               (unsigned long long)__double_as_longlong(mx));
 }
 __device__ __forceinline__ double fin_max_i(const Ctx& c, const DFinBlk& b, uint64_t S, uint64_t s) {
-    return c.bmax[(uint64_t)b.blk0 * S + s];
+    return c.bmax[(uint64_t)b.mx * S + s];
 }
 
 template <typename T>

@@ -133,13 +133,14 @@ void finish_layer(Plan& p, Layer& ly, std::vector<DSepFin>& fins) {
         uint32_t mw = 0;
         for (uint32_t k = 0; k < F.nmv; k++) mw += p.margvars[F.mv0 + k].card;
         const uint32_t blk0 = (uint32_t)p.finblks.size();
+        const uint32_t mx = p.n_bigfin++;
         const uint32_t mbase = p.n_bmarg;
         if ((uint64_t)p.n_bmarg + (uint64_t)mw * nblk > 0x7fffffffull) throw std::runtime_error("finaliser scratch");
         p.n_bmarg += mw * nblk;
         for (uint32_t j = 0; j < nblk; j++) {
             const uint32_t b = (uint32_t)((uint64_t)j * F.size / nblk);
             const uint32_t e = (uint32_t)((uint64_t)(j + 1) * F.size / nblk);
-            p.finblks.push_back({f, b, e - b, blk0 + j, blk0, nblk, mbase, mw});
+            p.finblks.push_back({f, b, e - b, blk0 + j, blk0, nblk, mbase, mw, mx});
         }
     }
     ly.nfb = (uint32_t)p.finblks.size() - ly.fb0;
@@ -303,6 +304,7 @@ std::string check_plan(const Tree& t, const Plan& p) {
                         B.count > kFinBlock)
                         return "fin block layout";
                     if (B.mw != mw || (uint64_t)B.mbase + (uint64_t)B.nblk * mw > p.n_bmarg) return "fin block scratch";
+                    if (B.mx != p.finblks[blk0].mx || B.mx >= p.n_bigfin) return "fin block maximum slot";
                     end += B.count;
                 }
                 if (end != F.size || b - blk0 != p.finblks[blk0].nblk) return "fin block cover";

@@ -42,6 +42,7 @@ struct Plan {
     std::vector<DGroup> groups;
     std::vector<DSepFin> fins;
     std::vector<DFinBlk> finblks;     // blocks of the large separators, layer by layer
+    uint32_t n_bigfin = 0;            // large separators (finalised in blocks), both sweeps
     uint32_t n_bmarg = 0;             // per slot: partial posterior sums of the blocks
     std::vector<DTarget> targets;     // distribute marginalisations
     std::vector<DWork> works;         // distribute workgroups
