@@ -46,12 +46,31 @@ __device__ __forceinline__ T* partp(const Ctx& c) {
 // Wave-uniform value in a scalar register.
 __device__ __forceinline__ uint32_t uniform(uint32_t x) { return __builtin_amdgcn_readfirstlane(x); }
 
-// The wave's work item (blockIdx.x * waves + wave) and the lane's slot.
-__device__ __forceinline__ uint32_t wave_item() {
-    return uniform(blockIdx.x * kWavesPerBlock + threadIdx.x / kLanes);
+// The wave's work item and slot group on a one-dimensional grid.  Workgroup
+// w (four waves: four consecutive items of one slot group) is dispatched to
+// XCD w % 8; each XCD takes one contiguous range of the (slot group, item
+// quad) cells, so the waves that read one clique's tables and messages
+// share that XCD's L2.
+constexpr uint32_t kXcds = 8;
+struct WaveCell {
+    uint32_t item, group;
+};
+__device__ __forceinline__ WaveCell wave_cell(uint32_t nitems, int nslots) {
+    const uint32_t nq = (nitems + kWavesPerBlock - 1) / kWavesPerBlock;
+    const uint32_t ng = ((uint32_t)nslots + kLanes - 1) / kLanes;
+    const uint32_t total = nq * ng;
+    const uint32_t w = blockIdx.x, x = w % kXcds, k = w / kXcds;
+    const uint32_t base = total / kXcds, extra = total % kXcds;
+    const uint32_t idx = x * base + min(x, extra) + k;
+    return WaveCell{uniform((idx % nq) * kWavesPerBlock + threadIdx.x / kLanes), uniform(idx / nq)};
 }
-__device__ __forceinline__ int lane_slot(const int32_t* slots, int nslots) {
-    const int b = (int)blockIdx.y * kLanes + (int)(threadIdx.x & (kLanes - 1));
+// Workgroups of a launch over nitems items and nslots slots.
+inline uint32_t cell_blocks(uint32_t nitems, int nslots) {
+    return ((nitems + kWavesPerBlock - 1) / kWavesPerBlock) * (((uint32_t)nslots + kLanes - 1) / kLanes);
+}
+// The lane's slot in slot group g, or -1 past the batch.
+__device__ __forceinline__ int lane_slot(const int32_t* slots, int nslots, uint32_t g) {
+    const int b = (int)g * kLanes + (int)(threadIdx.x & (kLanes - 1));
     return b < nslots ? slots[b] : -1;
 }
 
@@ -159,10 +178,11 @@ __device__ __forceinline__ void collect_piece_i(const Ctx& c, const DPiece& pc, 
 template <typename T>
 __global__ __launch_bounds__(kBlock) void k_collect_i(Ctx c, const DGroup* __restrict__ groups, uint32_t ngroups,
                                                       const int32_t* __restrict__ slots, int nslots) {
-    const uint32_t gi = wave_item();
+    const WaveCell wc = wave_cell(ngroups, nslots);
+    const uint32_t gi = wc.item;
     if (gi >= ngroups) return;
     const uint32_t lane = threadIdx.x & (kLanes - 1);
-    const int sl = lane_slot(slots, nslots);
+    const int sl = lane_slot(slots, nslots, wc.group);
     const bool act = sl >= 0;                  // lanes past the batch still help with metadata
     const uint64_t S = c.S;
     const uint64_t s = act ? (uint64_t)sl : 0;
@@ -198,10 +218,11 @@ __global__ __launch_bounds__(kBlock) void k_collect_i(Ctx c, const DGroup* __res
 template <typename T>
 __global__ __launch_bounds__(kBlock) void k_dist_i(Ctx c, const DWork* __restrict__ works, uint32_t nworks,
                                                    const int32_t* __restrict__ slots, int nslots) {
-    const uint32_t wi = wave_item();
+    const WaveCell wc = wave_cell(nworks, nslots);
+    const uint32_t wi = wc.item;
     if (wi >= nworks) return;
     const uint32_t lane = threadIdx.x & (kLanes - 1);
-    const int sl = lane_slot(slots, nslots);
+    const int sl = lane_slot(slots, nslots, wc.group);
     const bool act = sl >= 0;
     const uint64_t S = c.S;
     const uint64_t s = act ? (uint64_t)sl : 0;
@@ -374,8 +395,7 @@ __device__ __forceinline__ void shares_i(const DSepFin& f, const Ctx& c, uint32_
 // keep the exponent; a root's entry flags impossible evidence.
 template <typename T>
 __device__ __forceinline__ void fin_collect_small_i(const Ctx& c, const DSepFin* __restrict__ fins, uint32_t fi,
-                                                    const int32_t* __restrict__ slots, int nslots) {
-    const int sl = lane_slot(slots, nslots);
+                                                    int sl) {
     if (sl < 0) return;
     const uint64_t S = c.S, s = (uint64_t)sl;
     const DSepFin f = fins[fi];
@@ -403,8 +423,7 @@ __device__ __forceinline__ void fin_collect_small_i(const Ctx& c, const DSepFin*
 // and for a real separator the ratio new/old (0/0 = 0) rescaled.
 template <typename T>
 __device__ __forceinline__ void fin_distribute_small_i(const Ctx& c, const DSepFin* __restrict__ fins, uint32_t fi,
-                                                       const int32_t* __restrict__ slots, int nslots) {
-    const int sl = lane_slot(slots, nslots);
+                                                       int sl) {
     if (sl < 0) return;
     const uint64_t S = c.S, s = (uint64_t)sl;
     const DSepFin f = fins[fi];
@@ -492,8 +511,7 @@ __device__ __forceinline__ double fin_max_i(const Ctx& c, const DFinBlk& b, uint
 template <typename T>
 __device__ __forceinline__ void fin_collect_a_i(const Ctx& c, const DSepFin* __restrict__ fins,
                                                 const DFinBlk* __restrict__ blks, uint32_t bi,
-                                                const int32_t* __restrict__ slots, int nslots) {
-    const int sl = lane_slot(slots, nslots);
+                                                int sl) {
     if (sl < 0) return;
     const uint64_t S = c.S, s = (uint64_t)sl;
     const DFinBlk b = blks[bi];
@@ -507,9 +525,10 @@ template <typename T>
 __global__ __launch_bounds__(kBlock) void k_fin_collect_ib(Ctx c, const DSepFin* __restrict__ fins,
                                                            const DFinBlk* __restrict__ blks, uint32_t nblks,
                                                            const int32_t* __restrict__ slots, int nslots) {
-    const uint32_t bi = wave_item();
+    const WaveCell wc = wave_cell(nblks, nslots);
+    const uint32_t bi = wc.item;
     if (bi >= nblks) return;
-    const int sl = lane_slot(slots, nslots);
+    const int sl = lane_slot(slots, nslots, wc.group);
     if (sl < 0) return;
     const uint64_t S = c.S, s = (uint64_t)sl;
     const DFinBlk b = blks[bi];
@@ -536,8 +555,7 @@ __global__ __launch_bounds__(kBlock) void k_fin_collect_ib(Ctx c, const DSepFin*
 template <typename T>
 __device__ __forceinline__ void fin_distribute_a_i(const Ctx& c, const DSepFin* __restrict__ fins,
                                                    const DFinBlk* __restrict__ blks, uint32_t bi,
-                                                   const int32_t* __restrict__ slots, int nslots) {
-    const int sl = lane_slot(slots, nslots);
+                                                   int sl) {
     if (sl < 0) return;
     const uint64_t S = c.S, s = (uint64_t)sl;
     const DFinBlk b = blks[bi];
@@ -567,9 +585,10 @@ template <typename T>
 __global__ __launch_bounds__(kBlock) void k_fin_distribute_ib(Ctx c, const DSepFin* __restrict__ fins,
                                                               const DFinBlk* __restrict__ blks, uint32_t nblks,
                                                               const int32_t* __restrict__ slots, int nslots) {
-    const uint32_t bi = wave_item();
+    const WaveCell wc = wave_cell(nblks, nslots);
+    const uint32_t bi = wc.item;
     if (bi >= nblks) return;
-    const int sl = lane_slot(slots, nslots);
+    const int sl = lane_slot(slots, nslots, wc.group);
     if (sl < 0) return;
     const uint64_t S = c.S, s = (uint64_t)sl;
     const DFinBlk b = blks[bi];
@@ -616,9 +635,12 @@ __global__ __launch_bounds__(kBlock) void k_fin_collect_i(Ctx c, const DSepFin* 
                                                           const DFinBlk* __restrict__ blks, uint32_t nblks,
                                                           const DSepFin* __restrict__ fins,
                                                           const int32_t* __restrict__ slots, int nslots) {
-    const uint32_t wi = wave_item();
-    if (wi < nsmall) fin_collect_small_i<T>(c, sfins, wi, slots, nslots);
-    else if (wi - nsmall < nblks) fin_collect_a_i<T>(c, fins, blks, wi - nsmall, slots, nslots);
+    const WaveCell wc = wave_cell(nsmall + nblks, nslots);
+    const uint32_t wi = wc.item;
+    if (wi >= nsmall + nblks) return;
+    const int sl = lane_slot(slots, nslots, wc.group);
+    if (wi < nsmall) fin_collect_small_i<T>(c, sfins, wi, sl);
+    else fin_collect_a_i<T>(c, fins, blks, wi - nsmall, sl);
 }
 
 template <typename T>
@@ -626,9 +648,12 @@ __global__ __launch_bounds__(kBlock) void k_fin_distribute_i(Ctx c, const DSepFi
                                                              uint32_t nsmall, const DFinBlk* __restrict__ blks,
                                                              uint32_t nblks, const DSepFin* __restrict__ fins,
                                                              const int32_t* __restrict__ slots, int nslots) {
-    const uint32_t wi = wave_item();
-    if (wi < nsmall) fin_distribute_small_i<T>(c, sfins, wi, slots, nslots);
-    else if (wi - nsmall < nblks) fin_distribute_a_i<T>(c, fins, blks, wi - nsmall, slots, nslots);
+    const WaveCell wc = wave_cell(nsmall + nblks, nslots);
+    const uint32_t wi = wc.item;
+    if (wi >= nsmall + nblks) return;
+    const int sl = lane_slot(slots, nslots, wc.group);
+    if (wi < nsmall) fin_distribute_small_i<T>(c, sfins, wi, sl);
+    else fin_distribute_a_i<T>(c, fins, blks, wi - nsmall, sl);
 }
 
 // ---------------------------------------------------------------- posteriors
@@ -638,8 +663,8 @@ __global__ __launch_bounds__(kBlock) void k_fin_distribute_i(Ctx c, const DSepFi
 // sums and the exponents (fixed order per lane).
 __global__ __launch_bounds__(kBlock) void k_marginals_i(Ctx c, const int32_t* __restrict__ slots, int nslots,
                                                         uint32_t vars_per_wave) {
-    const uint32_t wi = wave_item();
-    const int sl = lane_slot(slots, nslots);
+    const uint32_t wi = uniform(blockIdx.x * kWavesPerBlock + threadIdx.x / kLanes);
+    const int sl = lane_slot(slots, nslots, blockIdx.y);
     if (sl < 0) return;
     const uint64_t S = c.S, s = (uint64_t)sl;
     const uint32_t v0 = wi * vars_per_wave;
@@ -671,7 +696,7 @@ __global__ __launch_bounds__(kBlock) void k_marginals_i(Ctx c, const int32_t* __
 hipError_t launch_interleaved(const Ctx& c, int prec, int kind, const void* items, uint32_t nitems,
                               const DSepFin* fins, const int32_t* slots, int nslots, hipStream_t st) {
     if (!nitems || !nslots) return hipSuccess;
-    const dim3 grid((nitems + kWavesPerBlock - 1) / kWavesPerBlock, (unsigned)((nslots + kLanes - 1) / kLanes));
+    const dim3 grid(cell_blocks(nitems, nslots));
     const dim3 block(kBlock);
     const auto* groups = static_cast<const DGroup*>(items);
     const auto* works = static_cast<const DWork*>(items);
@@ -706,7 +731,7 @@ hipError_t launch_fin_interleaved(const Ctx& c, int prec, bool dist, const DSepF
                                   int nslots, hipStream_t st) {
     const uint32_t n = nsmall + nblks;
     if (!n || !nslots) return hipSuccess;
-    const dim3 grid((n + kWavesPerBlock - 1) / kWavesPerBlock, (unsigned)((nslots + kLanes - 1) / kLanes));
+    const dim3 grid(cell_blocks(n, nslots));
     const dim3 block(kBlock);
     if (dist) {
         if (prec)
