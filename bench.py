@@ -161,6 +161,28 @@ def workload_config(key, W, jt_stats, n_slots):
     }
 
 
+def copy_gbps(mib=1024, reps=5):
+    """Achievable HBM bandwidth of a plain device-to-device copy (read +
+    write bytes over the median copy time), the ceiling shown beside the
+    peak."""
+    import torch
+    n = (mib << 20) // 4
+    src = torch.ones(n, dtype=torch.float32, device="cuda")
+    dst = torch.empty_like(src)
+    dst.copy_(src)
+    times = []
+    for _ in range(reps):
+        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        a.record()
+        dst.copy_(src)
+        b.record()
+        b.synchronize()
+        times.append(a.elapsed_time(b) * 1e-3)
+    del src, dst
+    torch.cuda.empty_cache()
+    return 2 * (mib << 20) / float(np.median(times)) / 1e9
+
+
 def fitting_slots(fbn, W, precision, layout, tile, frac=0.9):
     """How many of the workload's slots a device build of this precision and
     layout can hold in `frac` of the free device memory (host-only build
@@ -392,6 +414,7 @@ def bench_served(args, fbn):
     roofline = roofline_of({k: tuple(v) for k, v in prof.items()}, "C5", args.layout, args.tile,
                            "one full batch per resident tree, eager launches, HIP events",
                            interleaved=args.layout == 2)
+    roofline["stream_copy_GBps"] = round(copy_gbps(), 1)
 
     def lat(r):
         return {"queries_per_s": round(r.qps, 1), "p50_ms": round(1e3 * r.percentile(50), 3),
@@ -537,6 +560,8 @@ def main():
         torch.cuda.synchronize()
         log("[bench] copy calibration: 3 x 512 MiB device copies")
     roofline = roofline_of(prof32, key, args.layout, args.tile, interleaved=bool(stats["interleaved"]))
+    if not args.fp32_only:
+        roofline["stream_copy_GBps"] = round(copy_gbps(), 1)
     if args.fp32_only:
         # profiling runs: the headline path alone
         print(json.dumps({"value": round(qps32, 1), "unit": "queries/s", "ms_per_step": 1e3 * dt32 / args.steps,
