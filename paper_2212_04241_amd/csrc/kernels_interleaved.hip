@@ -13,8 +13,10 @@
 //   * each lane does only its own slot's arithmetic, and every table load or
 //     store of the wave touches one contiguous run of slots;
 //   * every sum runs in a fixed order within its lane, so a slot's result
-//     does not depend on which other slots share the launch (no atomics on
-//     data, no cross-lane reductions).
+//     does not depend on which other slots share the launch: no
+//     floating-point atomics and no cross-lane reductions (the only atomics
+//     are an integer max on the bit pattern of a non-negative double and an
+//     integer sum of exponents, both exact).
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -280,7 +282,7 @@ __global__ __launch_bounds__(kBlock) void k_dist_i(Ctx c, const DWork* __restric
 
 // Finish the entries [b, e) of separator f: with partial sums, an entry's
 // value is the sum of its chunks in order.  The partials of consecutive
-// entries are contiguous, so the whole range is read as one run, eight
+// entries are contiguous, so the whole range is read as one run, sixteen
 // loads in flight, each entry's sum closed and stored as its last chunk
 // comes in.  fn(m, v) is called once per entry in entry order.
 template <typename T, typename F>
@@ -495,7 +497,8 @@ __device__ __forceinline__ void fin_distribute_small_i(const Ctx& c, const DSepF
 // wave per block.  Phase a finishes the block's entries and folds its
 // maximum into the separator's maximum with an integer atomic max on the
 // bit pattern (exact and order-independent for non-negative doubles; the
-// slot, the block's first id, is cleared before every calibration); in the
+// separator's slot, its index among the large separators, is cleared before
+// every calibration); in the
 // distribute sweep it also writes the block's share of every posterior sum.
 // Phase b rescales with the separator's maximum; the separator's blocks
 // split its posterior sums between them, each adding one sum's block
