@@ -203,9 +203,16 @@ def time_batched(fbn, W, precision, steps, warmup, profile, layout=0, tile=0, ev
     launches of the kind with the most time only, in one step of every
     `event_every` (each event pair is a marker on the stream that costs a
     few microseconds, so the other steps run without them)."""
+    import torch
     cases = W.slot_cases[:n_cases] if n_cases else W.slot_cases
     n = len(cases)
-    jt = fbn.JT(W.handles(fbn), precision=precision, max_slots=n, layout=layout, tile_entries=tile)
+    # the layer sequence replayed as one captured graph (steps that record
+    # kernel events run it eagerly)
+    stream = torch.cuda.Stream()
+    jt = fbn.JT(W.handles(fbn), precision=precision, max_slots=n, layout=layout, tile_entries=tile,
+                stream=stream.cuda_stream)
+    fbn.set_graph_mode(jt, True)
+    jt._bench_stream = stream           # keeps the stream alive as long as the tree
     slots = list(range(n))
     fbn.set_evidence_batch(jt, slots, cases)
     for _ in range(max(warmup, 1)):
