@@ -209,8 +209,12 @@ def time_batched(fbn, W, precision, steps, warmup, profile, layout=0, tile=0, ev
     # the layer sequence replayed as one captured graph (steps that record
     # kernel events run it eagerly)
     stream = torch.cuda.Stream()
-    jt = fbn.JT(W.handles(fbn), precision=precision, max_slots=n, layout=layout, tile_entries=tile,
+    handles = W.handles(fbn)
+    t0 = time.perf_counter()
+    jt = fbn.JT(handles, precision=precision, max_slots=n, layout=layout, tile_entries=tile,
                 stream=stream.cuda_stream)
+    stream.synchronize()
+    jt._build_s = time.perf_counter() - t0  # compile, plan, device allocation and upload
     fbn.set_graph_mode(jt, True)
     jt._bench_stream = stream           # keeps the stream alive as long as the tree
     slots = list(range(n))
@@ -365,7 +369,8 @@ def bench_served(args, fbn):
     t0 = time.perf_counter()
     srv = Server(nets, budget_bytes=int(args.budget_gb * (1 << 30)), max_batch=args.max_batch, tile=args.tile,
                  layout=args.layout)
-    log(f"[bench] server up in {time.perf_counter() - t0:.1f} s: {srv.slots} slots per tree, "
+    server_s = time.perf_counter() - t0
+    log(f"[bench] server up in {server_s:.1f} s: {srv.slots} slots per tree, "
         f"{srv.device_bytes / 2**30:.2f} GiB resident, plan {srv.planned_bytes / 2**30:.2f} GiB of "
         f"{args.budget_gb} GiB")
     keep = list(range(min(200, n)))
@@ -440,6 +445,7 @@ def bench_served(args, fbn):
         "vs_baseline": None,
         "dtype": "f32",
         "data": "synthetic",
+        "setup_s": {"server_compile_build_upload_warm": round(server_s, 3)},
         "config": {"workload": f"C5: {fbngen.CONFIGS['C5'].description}", "networks": 8,
                    "trace_queries": n, "budget_GiB": args.budget_gb, "slots_per_tree": slots,
                    "resident_GiB": round(resident / 2**30, 3), "max_batch": args.max_batch,
@@ -548,11 +554,18 @@ def main():
         args.layout, args.tile = tuned["layout"], tuned["tile"]
         log(f"[bench] tuned in {time.perf_counter() - t0:.1f} s: layout {args.layout}, tile {args.tile} "
             f"({tuned['ms']:.3f} ms per calibration)")
+    # junction-tree compile alone (host: triangulation, tree, layouts, maps,
+    # plan), timed apart from the device build and upload
+    t0 = time.perf_counter()
+    fbn.JT(W.handles(fbn), precision=fbn.FBN_FP32_RESCALED, max_slots=n, layout=args.layout,
+           tile_entries=args.tile, host_only=True).free()
+    compile_s = time.perf_counter() - t0
     # FP32 batched (the headline path), kernel timing by HIP events
     jt32, dt32, (prof32, kinds32), post32, lp32, st32 = time_batched(fbn, W, fbn.FBN_FP32_RESCALED, args.steps,
                                                                      args.warmup, True, args.layout, args.tile,
                                                                      args.event_every)
     stats = jt32.stats
+    build_s = jt32._build_s
     qps32 = q * args.steps / dt32
     log(f"[bench] fp32 batched: {qps32:.1f} q/s, {1e3 * dt32 / args.steps:.3f} ms/step")
     jt32.free()
@@ -612,6 +625,7 @@ def main():
             "layout": "interleaved" if stats["interleaved"] else "per-slot", "tile": args.tile,
             "tuner_trials_ms": tuned["trials"] if tuned else None},
         "roofline": roofline,
+        "setup_s": {"jt_compile_host": round(compile_s, 3), "jt_build_and_upload": round(build_s, 3)},
         "paths": {
             "fp32_batched": {"queries_per_s": round(qps32, 1),
                              "useful_GBps": round(n * args.steps / dt32 * 3 * T * 4 / 1e9, 1),
