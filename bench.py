@@ -445,7 +445,7 @@ def bench_served(args, fbn):
         "vs_baseline": None,
         "dtype": "f32",
         "data": "synthetic",
-        "setup_s": {"server_compile_build_upload_warm": round(server_s, 3)},
+        "setup_ms": {"server_compile_build_upload_warm": round(1e3 * server_s, 3)},
         "config": {"workload": f"C5: {fbngen.CONFIGS['C5'].description}", "networks": 8,
                    "trace_queries": n, "budget_GiB": args.budget_gb, "slots_per_tree": slots,
                    "resident_GiB": round(resident / 2**30, 3), "max_batch": args.max_batch,
@@ -625,7 +625,7 @@ def main():
             "layout": "interleaved" if stats["interleaved"] else "per-slot", "tile": args.tile,
             "tuner_trials_ms": tuned["trials"] if tuned else None},
         "roofline": roofline,
-        "setup_s": {"jt_compile_host": round(compile_s, 3), "jt_build_and_upload": round(build_s, 3)},
+        "setup_ms": {"jt_compile_host": round(1e3 * compile_s, 3), "jt_build_and_upload": round(1e3 * build_s, 3)},
         "paths": {
             "fp32_batched": {"queries_per_s": round(qps32, 1),
                              "useful_GBps": round(n * args.steps / dt32 * 3 * T * 4 / 1e9, 1),
