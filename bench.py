@@ -367,8 +367,9 @@ def bench_served(args, fbn):
     queries = trace_queries(times[:n], which[:n], cases)
     log(f"[bench] C5: 8 networks, {n} trace queries")
     t0 = time.perf_counter()
-    srv = Server(nets, budget_bytes=int(args.budget_gb * (1 << 30)), max_batch=args.max_batch, tile=args.tile,
-                 layout=args.layout)
+    # tile per tree: --tile, else the tuner's pick for a full batch of each tree
+    srv = Server(nets, budget_bytes=int(args.budget_gb * (1 << 30)), max_batch=args.max_batch,
+                 tile=args.tile or None, layout=args.layout)
     server_s = time.perf_counter() - t0
     log(f"[bench] server up in {server_s:.1f} s: {srv.slots} slots per tree, "
         f"{srv.device_bytes / 2**30:.2f} GiB resident, plan {srv.planned_bytes / 2**30:.2f} GiB of "
@@ -418,7 +419,7 @@ def bench_served(args, fbn):
         f"{1e3 * srv_2.percentile(99):.2f}; plain p50 {1e3 * plain_2.percentile(50):.2f} p99 "
         f"{1e3 * plain_2.percentile(99):.2f}; open loop {lam3:.0f}/s: served p50 {1e3 * srv_3.percentile(50):.2f} "
         f"p99 {1e3 * srv_3.percentile(99):.2f}")
-    slots, resident = srv.slots, srv.device_bytes
+    slots, resident, srv_tiles = srv.slots, srv.device_bytes, list(srv.tiles)
     status_nonzero = int(np.count_nonzero(sat.status)) + int(np.count_nonzero(plain_sat.status))
     fallbacks = int(np.count_nonzero(sat.precision == fbn.FBN_FP64))
     srv.close()
@@ -449,7 +450,7 @@ def bench_served(args, fbn):
         "config": {"workload": f"C5: {fbngen.CONFIGS['C5'].description}", "networks": 8,
                    "trace_queries": n, "budget_GiB": args.budget_gb, "slots_per_tree": slots,
                    "resident_GiB": round(resident / 2**30, 3), "max_batch": args.max_batch,
-                   "layout": "interleaved" if args.layout == 2 else "per-slot", "tile": args.tile,
+                   "layout": "interleaved" if args.layout == 2 else "per-slot", "tile_per_tree": srv_tiles,
                    "step": "one closed-loop replay of the trace"},
         "roofline": roofline,
         "paths": {

@@ -80,22 +80,33 @@ class Server:
     .card), one stream each, sized by `budget_bytes`."""
 
     def __init__(self, nets, budget_bytes: int = 32 << 30, max_batch: int = 32, depth: int = 2,
-                 graph: bool = True, tile: int = 0, warm: bool = True, layout: int = 0):
+                 graph: bool = True, tile: int | None = 0, warm: bool = True, layout: int = 0,
+                 tile_candidates=(0, 2048)):
         import torch
         self._torch = torch
         self.nets = list(nets)
         self.card_sum = [int(np.sum(n.card)) for n in self.nets]
-        self.tile = tile
         self.layout = layout
         self.depth = max(1, depth)
         handles = [fbn.net_from_spec(n) for n in self.nets]
+        # tile per tree: fixed, or (tile=None) the fastest of tile_candidates
+        # for a full batch of max_batch cases, timed on the device
+        if tile is None:
+            from . import tune
+            empty = (np.zeros(0, np.int32), np.zeros(0, np.int32))
+            self.tiles = [int(tune.tune(n, [empty] * max_batch, fbn.FBN_FP32_RESCALED, max_batch,
+                                        [(layout or tune.PER_SLOT, t) for t in tile_candidates],
+                                        reps=3)["tile"]) for n in self.nets]
+        else:
+            self.tiles = [int(tile)] * len(self.nets)
+        self.tile = self.tiles[0]
         fixed, slot, fb = [], [], []
-        for h in handles:
-            a = fbn.JT(h, host_only=True, precision=fbn.FBN_FP32_RESCALED, max_slots=1, tile_entries=tile,
+        for h, t in zip(handles, self.tiles):
+            a = fbn.JT(h, host_only=True, precision=fbn.FBN_FP32_RESCALED, max_slots=1, tile_entries=t,
                        layout=layout)
             fixed.append(a.stats["device_bytes"] - a.stats["slot_bytes"])
             slot.append(a.stats["slot_bytes"])
-            b = fbn.JT(h, host_only=True, precision=fbn.FBN_FP64, max_slots=1, tile_entries=tile)
+            b = fbn.JT(h, host_only=True, precision=fbn.FBN_FP64, max_slots=1, tile_entries=t)
             fb.append(b.stats["device_bytes"])
         self.fallback_reserve = max(fb)
         avail = budget_bytes - sum(fixed) - self.fallback_reserve
@@ -107,8 +118,8 @@ class Server:
         self.budget_bytes = budget_bytes
         self.streams = [torch.cuda.Stream() for _ in self.nets]
         self.jts = []
-        for h, s in zip(handles, self.streams):
-            jt = fbn.JT(h, precision=fbn.FBN_FP32_RESCALED, max_slots=self.slots, tile_entries=tile,
+        for h, s, t in zip(handles, self.streams, self.tiles):
+            jt = fbn.JT(h, precision=fbn.FBN_FP32_RESCALED, max_slots=self.slots, tile_entries=t,
                         stream=s.cuda_stream, layout=layout)
             if graph:
                 fbn.set_graph_mode(jt, True)
@@ -143,7 +154,8 @@ class Server:
             if self._fb is not None:
                 self._fb[1].free()
             self._fb = None
-            self._fb = (net, fbn.JT(self._handles[net], precision=fbn.FBN_FP64, max_slots=1, tile_entries=self.tile))
+            self._fb = (net, fbn.JT(self._handles[net], precision=fbn.FBN_FP64, max_slots=1,
+                                    tile_entries=self.tiles[net]))
         return self._fb[1]
 
     def run(self, queries, rate: float | None = None, keep=None) -> ServeResult:

@@ -89,3 +89,27 @@ def test_plain_fp64_engine_agrees_with_served(c5):
     for i in range(len(qs)):
         assert np.max(np.abs(plain.post[i] - served.post[i])) <= FP32_ATOL, i
         assert abs(plain.log_pe[i] - served.log_pe[i]) <= FP32_LOGPE_ATOL * max(1.0, abs(plain.log_pe[i])), i
+
+
+@pytest.mark.timeout(600)
+def test_server_tuned_tiles(c5):
+    """Tile per tree picked by timing a full batch of each tree; results are
+    bitwise those of a one-slot tree of the same network and tile."""
+    nets, queries = c5
+    qs = queries[:40]
+    srv = Server(nets, budget_bytes=8 << 30, max_batch=4, tile=None, tile_candidates=(0, 2048))
+    say("tuned tiles", srv.tiles)
+    assert len(srv.tiles) == len(nets) and all(t in (0, 2048) for t in srv.tiles)
+    res = srv.run(qs, None, keep=range(len(qs)))
+    srv.close()
+    assert np.all(res.status == 0)
+    for i, q in enumerate(qs):
+        jt = fbn.JT(fbn.net_from_spec(nets[q.net]), precision=fbn.FBN_FP32_RESCALED, max_slots=1,
+                    tile_entries=srv.tiles[q.net])
+        fbn.set_evidence(jt, 0, q.vars, q.states)
+        lp, st = fbn.calibrate(jt, [0], want_results=True)
+        post, _, _ = fbn.query_all(jt, [0], int(np.sum(nets[q.net].card)))
+        jt.free()
+        assert st[0] == 0
+        assert np.array_equal(res.post[i], post[0]), i
+        assert res.log_pe[i] == lp[0], i
