@@ -165,6 +165,24 @@ def test_plan_bounds_check_large_workloads(key, j, precision):
     _host_jt(net, precision=precision)
 
 
+@pytest.mark.parametrize("tile", [1, 16, 64, 128, 256, 1000])
+@pytest.mark.parametrize("key,j", [("C1", 0), ("C2", 0), ("C3", 0), ("C5", 7)])
+def test_plan_bounds_check_interleaved(key, j, tile):
+    # slot-interleaved plans (finaliser blocks of 16 entries, small
+    # separators held in registers, one running maximum per large separator)
+    # pass the plan checker for any tile and a batch wider than one wave
+    net = fbngen.make_net(key, j)
+    jt = _host_jt(net, tile_entries=tile, layout=fbn.FBN_LAYOUT_INTERLEAVED, max_slots=130)
+    assert jt.stats["interleaved"] == 1
+
+
+@settings(max_examples=30, deadline=None, suppress_health_check=[HealthCheck.too_slow])
+@given(seed=st.integers(0, 2**31 - 1), n=st.integers(1, 30), tile=st.sampled_from([1, 5, 64, 129, 2048]))
+def test_plan_bounds_check_interleaved_random(seed, n, tile):
+    net = fbngen.random_small_net(seed, n, max_card=6, p_max=3, window=5)
+    _host_jt(net, tile_entries=tile, max_clique_entries=1 << 24, layout=fbn.FBN_LAYOUT_INTERLEAVED)
+
+
 # ---------------------------------------------------------------- forests
 
 def _forest_parts():
