@@ -328,7 +328,7 @@ SlotLayout slot_layout(const fbn_jt* jt) {
     const Plan& p = jt->plan;
     const size_t w = jt->opt.precision == FBN_FP32_RESCALED ? 4 : 8;
     SlotLayout L{};
-    L.psi_stride = (p.T + 63) / 64 * 64;
+    L.psi_stride = std::max<uint64_t>((p.psi_total + 63) / 64 * 64, 64);
     L.part_stride = (p.n_parts + 63) / 64 * 64 + 64;
     L.kexp_stride = (uint32_t)((jt->tree.ne + 1 + 63) / 64 * 64);
     L.marg_stride = p.marg_total;

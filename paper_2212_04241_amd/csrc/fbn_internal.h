@@ -68,7 +68,7 @@ struct DClique {
     uint32_t child0;     // first DChild record
     uint32_t home0;      // first DHome record
     uint16_t nchild, nhome;
-    uint32_t pad;
+    uint32_t psi;        // slot-interleaved: offset in the compact working-table arena (only cliques that store psi)
 };
 
 // A child edge seen from its parent clique: where its separator lives and
@@ -195,6 +195,10 @@ constexpr int kTileMax = 4096;    // entries per workgroup tile
 constexpr int kMaxPieces = 32;    // runs (and packed targets) per workgroup
 constexpr uint32_t kFinBlock = 4096;  // separator entries per finaliser block at most
 constexpr uint32_t kFinBlockInterleaved = 16;  // the same with slot-interleaved tables
-constexpr uint32_t kBigSeparatorInterleaved = 8;  // slot-interleaved: larger separators are split into blocks
+constexpr uint32_t kBigSeparatorInterleaved = 8;
+// Slot-interleaved: a clique with at most this many children stores no
+// working table; the distribute rebuilds it from the prior, the evidence and
+// the child messages.
+constexpr uint32_t kRebuildKidsInterleaved = 6;  // slot-interleaved: larger separators are split into blocks
 
 }  // namespace fbn

@@ -158,7 +158,7 @@ __device__ __forceinline__ void collect_piece_i(const Ctx& c, const DPiece& pc, 
 #pragma unroll
             for (uint32_t x = 0; x < U; x++) {
                 if (u0 + x < cnt) {
-                    if (act) psi[(q.off + i0 + u0 + x) * S + s] = v[x];
+                    if (nch > kRebuildKidsInterleaved && act) psi[((uint64_t)q.psi + i0 + u0 + x) * S + s] = v[x];
                     acc += (double)v[x];
                     if (--seg_left == 0) {
                         if (partial) part += acc;
@@ -217,20 +217,99 @@ __global__ __launch_bounds__(kBlock) void k_collect_i(Ctx c, const DGroup* __res
 // works out pair j's table entry, ratio entry and output index, and the
 // wave then sums with those broadcast, writing each output when its last
 // entry is in.
+// The pairs of one work item, for a clique with NC children (NC == kKids:
+// further children read per pair).  phi* at an entry is rebuilt exactly as
+// the collect formed psi there -- prior, evidence mask, then the child
+// messages in child order -- times the parent ratio, so it is bitwise the
+// value the collect computed; the collect stores no psi.
+template <typename T, int NC>
+__device__ __forceinline__ void dist_pairs_i(const Ctx& c, const DWork& w, const DTarget& tg, const DClique& q,
+                                             const DEvidence& ev, uint32_t lane, bool act, uint64_t S,
+                                             uint64_t s) {
+    constexpr int NW = NC > 0 ? NC : 1;
+    constexpr uint32_t U = NC <= 1 ? kDistBatch : (NC <= 3 ? kDistBatch / 2 : kDistBatch / 4);
+    const T* __restrict__ prior = static_cast<const T*>(c.prior);
+    const T* __restrict__ sepc = static_cast<const T*>(c.sepc);
+    const T* __restrict__ sepd = static_cast<const T*>(c.sepd);
+    const uint32_t* __restrict__ map = c.map;
+    const bool ratio = q.pedge >= 0;
+    const uint32_t per = w.nk * tg.nQL;  // entries summed per output
+    const uint32_t total = w.ng * tg.nPL * per;
+    double acc = 0.0;
+    uint32_t left = per;
+    for (uint32_t f0 = 0; f0 < total; f0 += kLanes) {
+        const uint32_t cnt = min((uint32_t)kLanes, total - f0);
+        // lane j: pair f0 + j -- its entry's digits, prior, child message
+        // indices, ratio index and output
+        const uint32_t f = f0 + min(lane, cnt - 1);
+        const uint32_t o = f / per, j = f - o * per;
+        const uint32_t gg = o / tg.nPL, t = o - gg * tg.nPL;
+        const uint32_t k = j / tg.nQL, u = j - k * tg.nQL;
+        const uint32_t row = map[tg.rg + w.g0 + gg] + map[tg.rq + w.k0 + k];
+        const uint32_t l = map[tg.lp + t] + map[tg.lq + u];
+        const uint64_t dj = c.dig[q.hdig + row] | c.dig[q.ldig + l];
+        const T pj = prior[q.off + row * q.L + l];
+        uint32_t xj[NW];
+#pragma unroll
+        for (int ch = 0; ch < NC; ch++) {
+            const DChild cd = c.ch[q.child0 + ch];
+            xj[ch] = cd.sep + map[cd.mh + row] + map[cd.ml + l];
+        }
+        const uint32_t rj = ratio ? q.psep + map[q.pmh + row] + map[q.pml + l] : 0u;
+        const uint32_t mj = map[tg.tb + w.g0 + gg] + map[tg.tv + t];
+        for (uint32_t x0 = 0; x0 < cnt; x0 += U) {
+            T m[U][NW], r[U];
+#pragma unroll
+            for (uint32_t x = 0; x < U; x++) {
+                const uint32_t b = min(x0 + x, cnt - 1);
+#pragma unroll
+                for (int ch = 0; ch < NC; ch++) m[x][ch] = sepc[(uint64_t)bcast(xj[ch], b) * S + s];
+                r[x] = ratio ? sepd[(uint64_t)bcast(rj, b) * S + s] : T(1);
+            }
+            T v[U];
+#pragma unroll
+            for (uint32_t x = 0; x < U; x++) {
+                const uint32_t b = min(x0 + x, cnt - 1);
+                v[x] = ((bcast(dj, b) ^ ev.want) & ev.mask) ? T(0) : bcast(pj, b);
+#pragma unroll
+                for (int ch = 0; ch < NC; ch++) v[x] *= m[x][ch];
+            }
+            if (NC == kKids) {
+                for (uint32_t ch = kKids; ch < q.nchild; ch++) {
+                    const DChild cd = c.ch[q.child0 + ch];
+#pragma unroll
+                    for (uint32_t x = 0; x < U; x++) {
+                        const uint32_t b = min(x0 + x, cnt - 1);
+                        const uint32_t idx = cd.sep + map[cd.mh + bcast(row, b)] + map[cd.ml + bcast(l, b)];
+                        v[x] *= sepc[(uint64_t)idx * S + s];
+                    }
+                }
+            }
+#pragma unroll
+            for (uint32_t x = 0; x < U; x++) {
+                if (x0 + x < cnt) {
+                    acc += (double)(ratio ? v[x] * r[x] : v[x]);
+                    if (--left == 0) {
+                        const uint32_t mo = bcast(mj, x0 + x);
+                        if (act) {
+                            if (tg.part0 < 0) accp<T>(c)[(uint64_t)(tg.sep + mo) * S + s] = acc;
+                            else partp<T>(c)[(uint64_t)((uint32_t)tg.part0 + mo * tg.nchunk + w.chunk) * S + s] = acc;
+                        }
+                        acc = 0.0;
+                        left = per;
+                    }
+                }
+            }
+        }
+    }
+}
+
+// The pairs of one work item of a clique whose psi the collect stored (one
+// with more than kRebuildKidsInterleaved children, in the compact arena):
+// phi* = stored psi times the parent ratio.
 template <typename T>
-__global__ __launch_bounds__(kBlock) void k_dist_i(Ctx c, const DWork* __restrict__ works, uint32_t nworks,
-                                                   const int32_t* __restrict__ slots, int nslots) {
-    const WaveCell wc = wave_cell(nworks, nslots);
-    const uint32_t wi = wc.item;
-    if (wi >= nworks) return;
-    const uint32_t lane = threadIdx.x & (kLanes - 1);
-    const int sl = lane_slot(slots, nslots, wc.group);
-    const bool act = sl >= 0;
-    const uint64_t S = c.S;
-    const uint64_t s = act ? (uint64_t)sl : 0;
-    const DWork w = works[wi];
-    const DTarget tg = c.tg[w.target];
-    const DClique q = c.cl[tg.clique];
+__device__ __forceinline__ void dist_pairs_psi_i(const Ctx& c, const DWork& w, const DTarget& tg, const DClique& q,
+                                                 uint32_t lane, bool act, uint64_t S, uint64_t s) {
     const T* __restrict__ psi = static_cast<const T*>(c.psi);
     const T* __restrict__ sepd = static_cast<const T*>(c.sepd);
     const uint32_t* __restrict__ map = c.map;
@@ -256,7 +335,7 @@ __global__ __launch_bounds__(kBlock) void k_dist_i(Ctx c, const DWork* __restric
 #pragma unroll
             for (uint32_t x = 0; x < kDistBatch; x++) {
                 const uint32_t b = min(x0 + x, cnt - 1);
-                v[x] = psi[(q.off + bcast(ej, b)) * S + s];
+                v[x] = psi[((uint64_t)q.psi + bcast(ej, b)) * S + s];
                 r[x] = ratio ? sepd[(uint64_t)bcast(rj, b) * S + s] : T(1);
             }
 #pragma unroll
@@ -275,6 +354,36 @@ __global__ __launch_bounds__(kBlock) void k_dist_i(Ctx c, const DWork* __restric
                 }
             }
         }
+    }
+}
+
+template <typename T>
+__global__ __launch_bounds__(kBlock) void k_dist_i(Ctx c, const DWork* __restrict__ works, uint32_t nworks,
+                                                   const int32_t* __restrict__ slots, int nslots) {
+    const WaveCell wc = wave_cell(nworks, nslots);
+    const uint32_t wi = wc.item;
+    if (wi >= nworks) return;
+    const uint32_t lane = threadIdx.x & (kLanes - 1);
+    const int sl = lane_slot(slots, nslots, wc.group);
+    const bool act = sl >= 0;
+    const uint64_t S = c.S;
+    const uint64_t s = act ? (uint64_t)sl : 0;
+    const DWork w = works[wi];
+    const DTarget tg = c.tg[w.target];
+    const DClique q = c.cl[tg.clique];
+    const DEvidence ev = c.ev[s * c.ev_stride + tg.clique];
+    if (q.nchild > kRebuildKidsInterleaved) {
+        dist_pairs_psi_i<T>(c, w, tg, q, lane, act, S, s);
+        return;
+    }
+    switch (q.nchild) {
+    case 0: dist_pairs_i<T, 0>(c, w, tg, q, ev, lane, act, S, s); break;
+    case 1: dist_pairs_i<T, 1>(c, w, tg, q, ev, lane, act, S, s); break;
+    case 2: dist_pairs_i<T, 2>(c, w, tg, q, ev, lane, act, S, s); break;
+    case 3: dist_pairs_i<T, 3>(c, w, tg, q, ev, lane, act, S, s); break;
+    case 4: dist_pairs_i<T, 4>(c, w, tg, q, ev, lane, act, S, s); break;
+    case 5: dist_pairs_i<T, 5>(c, w, tg, q, ev, lane, act, S, s); break;
+    default: dist_pairs_i<T, kKids>(c, w, tg, q, ev, lane, act, S, s); break;
     }
 }
 

@@ -176,6 +176,8 @@ std::string check_plan(const Tree& t, const Plan& p) {
             return "root separator";
         if (!is_root && !check_map(d.pmh, d.pml, psize)) return "parent map range";
         if ((uint64_t)d.child0 + d.nchild > p.children.size() || d.nchild != t.children[c].size()) return "children";
+        if (p.interleaved && d.nchild > kRebuildKidsInterleaved && (uint64_t)d.psi + d.size > p.psi_total)
+            return "working-table arena";
         for (uint32_t k = 0; k < d.nchild; k++) {
             const DChild& r = p.children[d.child0 + k];
             if ((uint64_t)r.sep + r.size > p.sep_total) return "child separator offset";
@@ -512,6 +514,22 @@ void build_plan(const Tree& t, int tile, uint32_t max_stage, Plan& p, bool inter
         p.kappa_total += kap;
     }
     p.T = off;
+    // working tables: per-slot layout, the prior's arena layout; interleaved,
+    // only the cliques with more than kRebuildKidsInterleaved children store
+    // one (the distribute rebuilds the others), packed in clique order
+    p.psi_total = p.T;
+    if (interleaved) {
+        uint64_t po = 0;
+        for (DClique& d : p.cliques) {
+            d.psi = 0;
+            if (d.nchild > kRebuildKidsInterleaved) {
+                if (po + d.size > 0xffffffffull) throw std::runtime_error("working-table arena");
+                d.psi = (uint32_t)po;
+                po += d.size;
+            }
+        }
+        p.psi_total = po;
+    }
     p.prior.resize(off);
     for (int c = 0; c < nc; c++) {
         const auto& src = t.prior[(size_t)c];

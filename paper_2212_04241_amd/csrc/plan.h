@@ -28,6 +28,7 @@ struct Plan {
     uint32_t stage = 0;               // LDS entries per slot: largest collect tile or distribute block
     uint32_t max_stage = 0;           // bound on stage
     uint64_t T = 0;                   // prior / working-table entries
+    uint64_t psi_total = 0;           // working-table entries per slot (interleaved: storing cliques only)
     uint32_t sep_total = 0;           // separator entries over all edges
     uint32_t n_roots = 0;             // trees of the forest; virtual entries follow sep_total
     uint32_t sep_stride = 0;          // per slot: separators, root entries, virtual separators, rounded
