@@ -28,7 +28,7 @@ PER_SLOT, INTERLEAVED = fbn.FBN_LAYOUT_PER_SLOT, fbn.FBN_LAYOUT_INTERLEAVED
 
 # (layout, tile entries); tile 0 is the library's default for the layout
 DEFAULT_CANDIDATES = [(PER_SLOT, 0), (PER_SLOT, 512), (PER_SLOT, 2048), (PER_SLOT, 4096),
-                      (INTERLEAVED, 0), (INTERLEAVED, 128), (INTERLEAVED, 256)]
+                      (INTERLEAVED, 0), (INTERLEAVED, 32), (INTERLEAVED, 128), (INTERLEAVED, 256)]
 
 
 def network_key(nets, precision: int, max_slots: int, batch: int) -> str:
