@@ -265,7 +265,7 @@ def test_tuner_picks_the_fastest_and_caches(tmp_path):
             raise fbn.FbnError(fbn.FBN_E_INVALID_ARG, "fake")
         if layout == tune.INTERLEAVED and tile == 0:
             return 7.0
-        return {0: 5.0, 2048: 3.0, 4096: 4.0, 128: 9.0, 256: 2.5}[tile]
+        return {0: 5.0, 2048: 3.0, 4096: 4.0, 32: 6.0, 128: 9.0, 256: 2.5}[tile]
 
     path = str(tmp_path / "tune.json")
     r = tune.tune(net, cases, cache=path, measure=fake)
