@@ -68,7 +68,7 @@ struct DClique {
     uint32_t child0;     // first DChild record
     uint32_t home0;      // first DHome record
     uint16_t nchild, nhome;
-    uint32_t psi;        // slot-interleaved: offset in the compact working-table arena (only cliques that store psi)
+    uint32_t psi;        // offset in the compact working-table arena, or kNoPsi: psi is rebuilt in the distribute
 };
 
 // A child edge seen from its parent clique: where its separator lives and
@@ -197,8 +197,11 @@ constexpr uint32_t kFinBlock = 4096;  // separator entries per finaliser block a
 constexpr uint32_t kFinBlockInterleaved = 16;  // the same with slot-interleaved tables
 constexpr uint32_t kBigSeparatorInterleaved = 8;
 // Slot-interleaved: a clique with at most this many children stores no
-// working table; the distribute rebuilds it from the prior, the evidence and
-// the child messages.
-constexpr uint32_t kRebuildKidsInterleaved = 6;  // slot-interleaved: larger separators are split into blocks
+// working table (DClique::psi = kNoPsi); the distribute rebuilds it from the
+// prior, the evidence and the child messages.  The per-slot layout stores
+// every working table: there a rebuild gathers each slot's messages apart,
+// which measured slower than reading the stored table.
+constexpr uint32_t kRebuildKidsInterleaved = 6;
+constexpr uint32_t kNoPsi = 0xffffffffu;  // slot-interleaved: larger separators are split into blocks
 
 }  // namespace fbn

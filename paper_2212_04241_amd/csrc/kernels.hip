@@ -103,7 +103,7 @@ struct RunC {
     uint32_t seg, out0;  // segment length; separator entry of the run's first segment
     uint32_t nchild, child0;
     uint32_t seg0;       // segments of the tile before this run
-    uint32_t pad;
+    uint32_t psi;        // the clique's working-table offset
 };
 
 struct KidC {
@@ -168,7 +168,7 @@ __device__ __forceinline__ void collect_entries(const Ctx& c, const EntryC<T, B>
 template <typename T, int B, int NC>
 __device__ __forceinline__ void collect_run(const Ctx& c, uint32_t total, uint32_t r_base, uint32_t L, uint32_t Lmul,
                                             uint32_t Lsh, uint32_t hdig, uint32_t ldig, bool anyev,
-                                            const T* r_prior, uint64_t poff, uint32_t child0, uint32_t nk,
+                                            const T* r_prior, uint32_t psi0, uint32_t child0, uint32_t nk,
                                             const DEvidence (&ev)[B], const int (&sl)[B],
                                             const uint32_t (&ksep)[kMaxKids], const uint32_t (&kmh)[kMaxKids],
                                             const uint32_t (&kml)[kMaxKids], T* const (&psi_b)[B],
@@ -185,7 +185,7 @@ __device__ __forceinline__ void collect_run(const Ctx& c, uint32_t total, uint32
             e[u].lo = i - e[u].hi * L;
             e[u].prior = r_prior[i];
             e[u].dig = anyev ? (c.dig[hdig + e[u].hi] | c.dig[ldig + e[u].lo]) : 0;
-            e[u].toff = poff + i;
+            e[u].toff = (uint64_t)psi0 + i;
             e[u].gi = gi;
             e[u].child0 = child0;
             e[u].nchild = nk;
@@ -232,7 +232,7 @@ __global__ __launch_bounds__(kBlock) void k_collect(Ctx c, const DGroup* __restr
         r.nchild = q.nchild;
         r.child0 = q.child0;
         r.seg0 = 0;
-        r.pad = 0;
+        r.psi = q.psi;
         runs[threadIdx.x] = r;
 #pragma unroll
         for (int b = 0; b < B; b++)
@@ -289,7 +289,7 @@ __global__ __launch_bounds__(kBlock) void k_collect(Ctx c, const DGroup* __restr
         const T* rp = prior + r.off;
         switch (r.nchild) {
 #define FBN_RUN(NC)                                                                                                   \
-    collect_run<T, B, NC>(c, g.total, rb, r.L, r.Lmul, r.Lsh, r.hdig, r.ldig, anyev != 0, rp, r.off, r.child0,      \
+    collect_run<T, B, NC>(c, g.total, rb, r.L, r.Lmul, r.Lsh, r.hdig, r.ldig, anyev != 0, rp, r.psi, r.child0,      \
                           r.nchild, ev, sl, ksep, kmh, kml, psi_b, sepc_b, vals)
         case 0: FBN_RUN(0); break;
         case 1: FBN_RUN(1); break;
@@ -337,7 +337,7 @@ __global__ __launch_bounds__(kBlock) void k_collect(Ctx c, const DGroup* __restr
             const uint32_t lo = i - hi * r_L;
             const T pv = r_prior[i];
             const uint64_t d = anyev ? (c.dig[r_hdig + hi] | c.dig[r_ldig + lo]) : 0;
-            const uint64_t toff = (uint64_t)(r_prior - prior) + i;
+            const uint64_t toff = (uint64_t)runs[p].psi + i;
             const EntryC<T, B> e[1] = {{hi, lo, pv, d, toff, gi, runs[p].child0, nk}};
             switch (nk) {
             case 0: collect_entries<T, B, 0, 1>(c, e, 1u, ev, sl, ksep, kmh, kml, psi_b, sepc_b, vals); break;
@@ -582,7 +582,7 @@ struct RunD {
     uint32_t count, gofs;
     uint32_t L, Lmul, Lsh;
     int32_t pedge;
-    uint32_t psep, pmh, pml, pad;
+    uint32_t psep, pmh, pml, psi;  // psi: working-table offset
 };
 
 struct TgtD {
@@ -618,7 +618,7 @@ __global__ __launch_bounds__(kBlock) void k_dist_gather(Ctx c, const DWork* __re
             const DPiece pc = c.pc[w.piece0 + threadIdx.x];
             const DClique cq = c.cl[pc.clique];
             runs[threadIdx.x] = RunD{cq.off, pc.count, pc.gofs, cq.L, cq.Lmul, cq.Lsh, cq.pedge, cq.psep, cq.pmh,
-                                     cq.pml, 0u};
+                                     cq.pml, cq.psi};
         }
         if (threadIdx.x >= 64 && threadIdx.x - 64 < w.nwt) {
             const uint32_t k = threadIdx.x - 64;
@@ -669,7 +669,7 @@ __global__ __launch_bounds__(kBlock) void k_dist_gather(Ctx c, const DWork* __re
             for (uint32_t u = 0; u < U; u++)
 #pragma unroll
                 for (int b = 0; b < B; b++) {
-                    v[u][b] = psi_b[b][q.off + ent[u]];
+                    v[u][b] = psi_b[b][(uint64_t)q.psi + ent[u]];
                     r[u][b] = sepd_b[b][pr[u]];
                 }
 #pragma unroll
@@ -684,7 +684,7 @@ __global__ __launch_bounds__(kBlock) void k_dist_gather(Ctx c, const DWork* __re
     } else {
         // packed: the current run's fields, reloaded only when the run changes
         uint32_t p = 0, r_end = 0, r_gofs = 0, r_L = 1, r_Lmul = 0, r_Lsh = 0, r_psep = 0, r_pmh = 0, r_pml = 0;
-        uint64_t r_off = 0;
+        uint32_t r_psi = 0;
         int32_t r_pedge = -1;
         bool first = true;
         for (uint32_t gi = threadIdx.x; gi < n; gi += kBlock) {
@@ -698,11 +698,11 @@ __global__ __launch_bounds__(kBlock) void k_dist_gather(Ctx c, const DWork* __re
                 r_L = rr.L;
                 r_Lmul = rr.Lmul;
                 r_Lsh = rr.Lsh;
-                r_off = rr.off;
                 r_pedge = rr.pedge;
                 r_psep = rr.psep;
                 r_pmh = rr.pmh;
                 r_pml = rr.pml;
+                r_psi = rr.psi;
             }
             const uint32_t ent = gi - r_gofs;
             const uint32_t row = mdiv(ent, r_Lmul, r_Lsh);
@@ -713,7 +713,7 @@ __global__ __launch_bounds__(kBlock) void k_dist_gather(Ctx c, const DWork* __re
             T v[B], r[B];
 #pragma unroll
             for (int b = 0; b < B; b++) {
-                v[b] = psi_b[b][r_off + ent];
+                v[b] = psi_b[b][(uint64_t)r_psi + ent];
                 r[b] = sepd_b[b][pr];
             }
 #pragma unroll

@@ -158,7 +158,7 @@ __device__ __forceinline__ void collect_piece_i(const Ctx& c, const DPiece& pc, 
 #pragma unroll
             for (uint32_t x = 0; x < U; x++) {
                 if (u0 + x < cnt) {
-                    if (nch > kRebuildKidsInterleaved && act) psi[((uint64_t)q.psi + i0 + u0 + x) * S + s] = v[x];
+                    if (q.psi != kNoPsi && act) psi[((uint64_t)q.psi + i0 + u0 + x) * S + s] = v[x];
                     acc += (double)v[x];
                     if (--seg_left == 0) {
                         if (partial) part += acc;
@@ -372,7 +372,7 @@ __global__ __launch_bounds__(kBlock) void k_dist_i(Ctx c, const DWork* __restric
     const DTarget tg = c.tg[w.target];
     const DClique q = c.cl[tg.clique];
     const DEvidence ev = c.ev[s * c.ev_stride + tg.clique];
-    if (q.nchild > kRebuildKidsInterleaved) {
+    if (q.psi != kNoPsi) {
         dist_pairs_psi_i<T>(c, w, tg, q, lane, act, S, s);
         return;
     }

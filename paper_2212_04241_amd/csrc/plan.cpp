@@ -176,8 +176,8 @@ std::string check_plan(const Tree& t, const Plan& p) {
             return "root separator";
         if (!is_root && !check_map(d.pmh, d.pml, psize)) return "parent map range";
         if ((uint64_t)d.child0 + d.nchild > p.children.size() || d.nchild != t.children[c].size()) return "children";
-        if (p.interleaved && d.nchild > kRebuildKidsInterleaved && (uint64_t)d.psi + d.size > p.psi_total)
-            return "working-table arena";
+        if (d.psi != kNoPsi && (uint64_t)d.psi + d.size > p.psi_total) return "working-table arena";
+        if (d.psi == kNoPsi && (!p.interleaved || d.nchild > kRebuildKidsInterleaved)) return "rebuilt working table";
         for (uint32_t k = 0; k < d.nchild; k++) {
             const DChild& r = p.children[d.child0 + k];
             if ((uint64_t)r.sep + r.size > p.sep_total) return "child separator offset";
@@ -517,19 +517,8 @@ void build_plan(const Tree& t, int tile, uint32_t max_stage, Plan& p, bool inter
     // working tables: per-slot layout, the prior's arena layout; interleaved,
     // only the cliques with more than kRebuildKidsInterleaved children store
     // one (the distribute rebuilds the others), packed in clique order
-    p.psi_total = p.T;
-    if (interleaved) {
-        uint64_t po = 0;
-        for (DClique& d : p.cliques) {
-            d.psi = 0;
-            if (d.nchild > kRebuildKidsInterleaved) {
-                if (po + d.size > 0xffffffffull) throw std::runtime_error("working-table arena");
-                d.psi = (uint32_t)po;
-                po += d.size;
-            }
-        }
-        p.psi_total = po;
-    }
+    // working tables: which cliques store one is settled with the distribute
+    // items below (assign_psi)
     p.prior.resize(off);
     for (int c = 0; c < nc; c++) {
         const auto& src = t.prior[(size_t)c];
@@ -580,6 +569,7 @@ void build_plan(const Tree& t, int tile, uint32_t max_stage, Plan& p, bool inter
         finish_layer(p, ly, fins);
     }
 
+    std::vector<char> rebuilt((size_t)nc, 0);
     // ---- distribute layers (depth): marginalise each clique onto each child
     // separator and onto the virtual separator of each private variable
     p.distribute.assign((size_t)D + 1, Layer());
@@ -626,6 +616,7 @@ void build_plan(const Tree& t, int tile, uint32_t max_stage, Plan& p, bool inter
                 if (p.post_sep[(size_t)v] < 0) tgts.push_back({{v}, vsep_off[(size_t)v], -2});
             const uint32_t dtile_c = std::min<uint32_t>(max_stage, std::max(dtile_base, d.L));
             const bool packed = !interleaved && d.size <= dtile_c && tgts.size() <= (size_t)kMaxPieces;
+            rebuilt[(size_t)c] = interleaved && d.nchild <= kRebuildKidsInterleaved;
             if (packed) {
                 if (open_w >= 0) {
                     const DWork& W = p.works[(size_t)open_w];
@@ -769,6 +760,19 @@ void build_plan(const Tree& t, int tile, uint32_t max_stage, Plan& p, bool inter
         finish_layer(p, ly, fins);
     }
     p.n_parts = parts;
+    // the cliques that store a working table, packed in clique order
+    uint64_t po = 0;
+    for (int c = 0; c < nc; c++) {
+        DClique& d = p.cliques[(size_t)c];
+        if (rebuilt[(size_t)c]) {
+            d.psi = kNoPsi;
+            continue;
+        }
+        if (po + d.size >= (uint64_t)kNoPsi) throw std::runtime_error("working-table arena");
+        d.psi = (uint32_t)po;
+        po += d.size;
+    }
+    p.psi_total = po;
     p.stage = (uint32_t)tile;
     for (const DGroup& g : p.groups) p.stage = std::max(p.stage, g.total);
     for (const DWork& w : p.works) {
