@@ -69,8 +69,11 @@ enum { FBN_FP64 = 0, FBN_FP32_RESCALED = 1 };
  * long sums run across lanes.  INTERLEAVED stores entry x of slot s at
  * x * max_slots + s and gives each lane one slot, with every index
  * computation shared by the wave: gathers onto large separators are cheaper,
- * but every long sum runs within one lane.  AUTO is PER_SLOT; the Python
- * autotuner measures both.  Results are the same to rounding. */
+ * but every long sum runs within one lane.  INTERLEAVED also keeps no
+ * working table for a clique with at most six children (the distribute
+ * rebuilds it from the prior, the evidence and the child messages, to the
+ * same bits), so its slots take far less device memory.  AUTO is PER_SLOT;
+ * the Python autotuner measures both.  Results are the same to rounding. */
 enum { FBN_LAYOUT_AUTO = 0, FBN_LAYOUT_PER_SLOT = 1, FBN_LAYOUT_INTERLEAVED = 2 };
 
 /* Device memory comes from the caller when alloc is set (e.g. PyTorch's
