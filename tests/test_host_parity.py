@@ -176,6 +176,17 @@ def test_plan_bounds_check_interleaved(key, j, tile):
     assert jt.stats["interleaved"] == 1
 
 
+@pytest.mark.parametrize("key", ["C2", "C3"])
+def test_interleaved_slots_hold_no_rebuilt_working_tables(key):
+    # the interleaved layout stores psi only for cliques with more than six
+    # children: a whole slot then takes less than its T table entries alone
+    # would, while a per-slot slot holds all of them
+    net = fbngen.make_net(key, 0)
+    ps = _host_jt(net, precision=fbn.FBN_FP32_RESCALED, max_slots=64, layout=fbn.FBN_LAYOUT_PER_SLOT).stats
+    il = _host_jt(net, precision=fbn.FBN_FP32_RESCALED, max_slots=64, layout=fbn.FBN_LAYOUT_INTERLEAVED).stats
+    assert ps["slot_bytes"] > 4 * ps["T"] > il["slot_bytes"]
+
+
 @settings(max_examples=30, deadline=None, suppress_health_check=[HealthCheck.too_slow])
 @given(seed=st.integers(0, 2**31 - 1), n=st.integers(1, 30), tile=st.sampled_from([1, 5, 64, 129, 2048]))
 def test_plan_bounds_check_interleaved_random(seed, n, tile):
