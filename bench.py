@@ -34,7 +34,8 @@ HBM_PEAK_GBS = 8000.0   # MI355X HBM3E, published
 PROFILES = os.path.join(ROOT, "profiles")
 # the sources a kernel's byte counters depend on: counters taken before a
 # change to any of them no longer describe the kernel
-KERNEL_SOURCES = ["paper_2212_04241_amd/csrc/kernels.hip", "paper_2212_04241_amd/csrc/kernels.h",
+KERNEL_SOURCES = ["paper_2212_04241_amd/csrc/kernels.hip", "paper_2212_04241_amd/csrc/kernels_interleaved.hip",
+                  "paper_2212_04241_amd/csrc/kernels.h", "paper_2212_04241_amd/csrc/api.cpp",
                   "paper_2212_04241_amd/csrc/plan.cpp", "paper_2212_04241_amd/csrc/plan.h",
                   "paper_2212_04241_amd/csrc/fbn_internal.h"]
 

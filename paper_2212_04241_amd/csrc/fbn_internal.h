@@ -195,7 +195,7 @@ constexpr int kTileMax = 4096;    // entries per workgroup tile
 constexpr int kMaxPieces = 32;    // runs (and packed targets) per workgroup
 constexpr uint32_t kFinBlock = 4096;  // separator entries per finaliser block at most
 constexpr uint32_t kFinBlockInterleaved = 16;  // the same with slot-interleaved tables
-constexpr uint32_t kBigSeparatorInterleaved = 8;
+constexpr uint32_t kBigSeparatorInterleaved = 16;
 // Slot-interleaved: a clique with at most this many children stores no
 // working table (DClique::psi = kNoPsi); the distribute rebuilds it from the
 // prior, the evidence and the child messages.  The per-slot layout stores
