@@ -359,7 +359,6 @@ def bench_served(args, fbn):
     the plain engine's saturation rate for both; open loop at 0.8 x the
     served saturation rate for the served path."""
     import fbngen
-    import oracle
     from paper_2212_04241_amd.serve import Server, serve_plain, trace_queries
     nets = [fbngen.make_net("C5", j) for j in range(8)]
     times, which, fracs, seeds = fbngen.make_arrivals("C5")
@@ -467,6 +466,8 @@ def bench_served(args, fbn):
         "status_nonzero": status_nonzero,
     }
     if not args.no_cpu_baseline:
+        # the oracle's leg: the CPU baseline and the accuracy check
+        import oracle
         sample = keep
         threads = max(1, min(16, os.cpu_count() or 1))
         t1 = time.perf_counter()
