@@ -386,6 +386,64 @@ def test_minfill_hand_worked_diamond():
     assert jt.root == 0
 
 
+def test_minfill_golden_cycle_with_pendants():
+    # a chordless 4-cycle with two pendant-like vertices, derived by hand in
+    # tests/golden/minfill/expected.json: min-fill, min-weight and min-fill
+    # without the weight term choose different first vertices, and the chord
+    # of the cycle is placed by the id tie-break
+    gdir = os.path.join(os.path.dirname(__file__), "golden", "minfill")
+    with open(os.path.join(gdir, "expected.json")) as f:
+        want = json.load(f)
+    with open(os.path.join(gdir, want["net"])) as f:
+        net = fbngen.net_from_text(f.read())
+    jt = oracle.compile_net(net)
+    assert [int(x) for x in jt.elim_order()] == want["elim_order"]
+    assert [[int(x) for x in jt.clique(c)[0]] for c in range(jt.n_cliques)] == want["cliques"]
+    assert jt.root == want["root"]
+    assert [jt.clique(c)[1] for c in range(jt.n_cliques)] == want["height"]
+    assert [jt.clique(c)[2] for c in range(jt.n_cliques)] == want["depth"]
+    for e, (p, ch, sv) in enumerate(want["edges"]):
+        gp, gc, gs = jt.edge(e)
+        assert (gp, gc, [int(x) for x in gs]) == (p, ch, sv)
+        assert [int(x) for x in jt.index_map(e)] == want["maps"][e]
+    ch, vh = jt.homes()
+    assert [int(x) for x in ch] == want["cpt_home"]
+    assert [int(x) for x in vh] == want["var_home"]
+
+
+def _tiny_mass_net():
+    # X (4097 states) -> Y (2) -> Z (2).  P(X=0) = 1 - 2^-48 and each of the
+    # other 4096 states has 2^-60, so the stored CPT sums to exactly 1.  In
+    # ascending order every 2^-60 (or 2^-61 after halving) is below half an
+    # ulp of the running sum and a plain left-to-right sum loses all of them.
+    big, tiny = 1.0 - 2.0 ** -48, 2.0 ** -60
+    px = np.array([big] + [tiny] * 4096)
+    net = fbngen.Net(card=np.array([4097, 2, 2], dtype=np.int32), parents=[[], [0], [1]],
+                     cpt=[px, np.full(2 * 4097, 0.5), np.array([0.25, 0.75, 0.5, 0.5])])
+    return net, big, tiny
+
+
+def test_compensated_sums_are_exact_where_plain_summation_is_not():
+    # Every table sum of the oracle is compensated (Neumaier 1974), so on this
+    # input the collect message onto Y, P(e) and the normaliser of X's
+    # posterior are the exact sums of the stored values.
+    net, big, tiny = _tiny_mass_net()
+    exact = Fraction(big) + 4096 * Fraction(tiny)
+    assert exact == 1
+    plain = 0.0
+    for x in [big] + [tiny] * 4096:
+        plain += x
+    assert plain == big != 1.0          # what an uncompensated sum returns
+    jt = oracle.compile_net(net)
+    lp, post = jt.query([], [])
+    assert lp == 0.0                    # log of the exact P(e) = 1
+    assert post[0] == big and np.all(post[1:4097] == tiny)
+    # observing Z = 1: P(e) = sum_y P(y) P(Z=1|y) with P(y) = 1/2 exactly
+    lp, post = jt.query([2], [1])
+    assert abs(lp - float(np.log(0.625))) <= 2e-16     # uncompensated: off by 3.6e-15
+    assert post[0] == big
+
+
 # ---------------------------------------------------------------- errors
 
 @pytest.mark.parametrize("text,code", [
