@@ -60,6 +60,7 @@ def _load():
     lib.orc_jt_homes.argtypes = [C.c_void_p, i32p, i32p]
     lib.orc_jt_prior.argtypes = [C.c_void_p, f64p, C.c_size_t]
     lib.orc_query.argtypes = [C.c_void_p, C.c_int, i32p, i32p, f64p, f64p, f64p, f64p]
+    lib.orc_query_joint.argtypes = [C.c_void_p, C.c_int, i32p, i32p, C.c_int, i32p, f64p]
     _lib = lib
     return lib
 
@@ -204,6 +205,23 @@ class OracleJT:
         if seps:
             out.append(sp)
         return tuple(out)
+
+
+def query_joint(ojt: OracleJT, vars_, states, qvars):
+    """Joint posterior P(qvars | evidence) for query variables lying together
+    in one clique (paper Section 1: the conditional probability of the query
+    variables given the evidence), qvars[0] slowest, qvars[-1] fastest."""
+    lib = _load()
+    v = np.ascontiguousarray(vars_, dtype=np.int32)
+    s = np.ascontiguousarray(states, dtype=np.int32)
+    q = np.ascontiguousarray(qvars, dtype=np.int32)
+    out = np.zeros(int(np.prod([int(ojt.card[x]) for x in q], dtype=np.int64)) if q.size else 1, dtype=np.float64)
+    rc = lib.orc_query_joint(ojt._h, v.size, _ptr(v if v.size else np.zeros(1, np.int32), C.c_int32),
+                             _ptr(s if s.size else np.zeros(1, np.int32), C.c_int32), q.size,
+                             _ptr(q if q.size else np.zeros(1, np.int32), C.c_int32), _ptr(out, C.c_double))
+    if rc:
+        raise OracleError(rc, "joint query")
+    return out
 
 
 def compile_net(net, max_entries: int = 0, structure_only: bool = False) -> OracleJT:

@@ -889,3 +889,63 @@ done:
     free(phi); free(sep); free(ord); free(obs);
     return rc;
 }
+
+/* ------------------------------------------------------------------ */
+/* joint posterior of several query variables                          */
+/* ------------------------------------------------------------------ */
+
+/* The problem statement asks for the conditional probability of the query
+ * variables (plural) given the evidence.  For query variables that lie
+ * together in one clique this is read from that clique's calibrated table,
+ * which holds P(X_C, e): sum it over the clique's other variables and
+ * normalise.  The clique is the smallest one holding every query variable
+ * (lowest id on ties).  out has prod card[q] entries, q[0] slowest and
+ * q[nq-1] fastest. */
+int orc_query_joint(const orc_jt* jt, int n_obs, const int32_t* vars, const int32_t* states,
+                    int nq, const int32_t* q, double* out) {
+    if (nq <= 0) return ORC_E_INVALID;
+    for (int a = 0; a < nq; a++) {
+        if (q[a] < 0 || q[a] >= jt->n) return ORC_E_INVALID;
+        for (int b = 0; b < a; b++) if (q[b] == q[a]) return ORC_E_INVALID;
+    }
+    int home = -1;
+    for (int c = 0; c < jt->nc; c++) {
+        int all = 1;
+        for (int a = 0; a < nq && all; a++) all = contains(jt->cvars[c], jt->cn[c], q[a]);
+        if (all && (home < 0 || jt->csize[c] < jt->csize[home])) home = c;
+    }
+    if (home < 0) return ORC_E_INVALID;
+    int64_t total = 0;
+    for (int c = 0; c < jt->nc; c++) total += jt->csize[c];
+    double* tables = malloc(sizeof(double) * (size_t)total);
+    if (!tables) return ORC_E_NOMEM;
+    int rc = orc_query(jt, n_obs, vars, states, NULL, NULL, tables, NULL);
+    if (rc) { free(tables); return rc; }
+    int64_t off = 0;
+    for (int c = 0; c < home; c++) off += jt->csize[c];
+    const double* phi = tables + off;
+    /* position of each query variable in the clique layout, and its stride
+     * in the output (last listed fastest) */
+    int64_t* cs = malloc(sizeof(int64_t) * (size_t)nq);
+    int64_t* os = malloc(sizeof(int64_t) * (size_t)nq);
+    int64_t nout = 1;
+    for (int a = nq - 1; a >= 0; a--) {
+        int k = 0;
+        while (jt->cvars[home][k] != q[a]) k++;
+        cs[a] = jt->cstride[home][k];
+        os[a] = nout;
+        nout *= jt->card[q[a]];
+    }
+    nsum_t* acc = calloc((size_t)nout, sizeof(nsum_t));
+    for (int64_t i = 0; i < jt->csize[home]; i++) {
+        int64_t o = 0;
+        for (int a = 0; a < nq; a++) o += ((i / cs[a]) % jt->card[q[a]]) * os[a];
+        nsum_add(&acc[o], phi[i]);
+    }
+    nsum_t z = { 0, 0 };
+    for (int64_t o = 0; o < nout; o++) nsum_add(&z, nsum_get(&acc[o]));
+    const double zt = nsum_get(&z);
+    for (int64_t o = 0; o < nout; o++) out[o] = nsum_get(&acc[o]) / zt;
+    free(acc); free(cs); free(os); free(tables);
+    return ORC_OK;
+}

@@ -87,6 +87,14 @@ int  orc_jt_prior(const orc_jt* jt, double* out, size_t cap);
 int  orc_query(const orc_jt* jt, int n_obs, const int32_t* vars, const int32_t* states,
                double* log_pe, double* post, double* tables_out, double* seps_out);
 
+/* Joint posterior P(q | e) of nq distinct query variables that lie together
+ * in one clique: the calibrated table of the smallest such clique (lowest id
+ * on ties) summed onto them and normalised.  out: prod card[q] entries, q[0]
+ * slowest, q[nq-1] fastest.  ORC_E_INVALID when q is empty, repeats a
+ * variable or shares no clique; ORC_E_ZERO_EVIDENCE as orc_query. */
+int  orc_query_joint(const orc_jt* jt, int n_obs, const int32_t* vars, const int32_t* states,
+                     int nq, const int32_t* q, double* out);
+
 #ifdef __cplusplus
 }
 #endif

@@ -55,6 +55,23 @@ def brute_force(net, vars_, states):
     return pe, np.concatenate(post)
 
 
+def brute_force_joint(net, vars_, states, qvars):
+    """P(qvars | e) by enumeration of the joint: the evidence-masked joint
+    summed over every other variable, qvars[0] the slowest axis."""
+    P = joint(net)
+    for v, s in zip(vars_, states):
+        m = np.zeros(int(net.card[v]))
+        m[int(s)] = 1.0
+        bshape = [1] * net.n
+        bshape[int(v)] = int(net.card[v])
+        P = P * m.reshape(bshape)
+    q = [int(x) for x in qvars]
+    m = P.sum(axis=tuple(a for a in range(net.n) if a not in q))
+    # remaining axes are in ascending variable order; put them in q's order
+    m = np.transpose(m, [sorted(q).index(x) for x in q])
+    return (m / m.sum()).ravel()
+
+
 def chain_forward_backward(prior0, trans, obs):
     """Smoothing on a chain X0 -> X1 -> ... -> X_{n-1}.
     prior0[r], trans[t][a, b] = P(X_{t+1}=b | X_t=a), obs = {t: state}.

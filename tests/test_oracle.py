@@ -444,6 +444,73 @@ def test_compensated_sums_are_exact_where_plain_summation_is_not():
     assert post[0] == big
 
 
+# ---------------------------------------------------------------- joint queries
+
+def test_joint_posteriors_diamond_exact_fractions():
+    # P(A,B,C,D=1) of the diamond in 512ths (tests/golden/micro/expected.json,
+    # derived by hand from the joint): A0: 000:12 001:24 010:16 011:28; A1:
+    # 100:1 101:14 110:12 111:147, bits A,B,C; total 254.  Summing over A gives
+    # P(B,C | D=1) = (13, 38, 28, 175)/254; over C, P(A,B | D=1) = (36, 44, 15, 159)/254.
+    net = fbngen.net_from_text(_read("diamond.fbn"))
+    jt = oracle.compile_net(net)
+    cases = {(1, 2): [13, 38, 28, 175], (2, 1): [13, 28, 38, 175], (0, 1): [36, 44, 15, 159],
+             (3, 2, 1): [0, 0, 0, 0, 13, 28, 38, 175]}
+    for q, num in cases.items():
+        got = oracle.query_joint(jt, [3], [1], list(q))
+        want = np.array([float(Fraction(x, 254)) for x in num])
+        assert np.max(np.abs(got - want)) <= 1e-15, (q, got, want)
+    # without evidence, P(A,B) = P(A) P(B|A) from the CPTs
+    got = oracle.query_joint(jt, [], [], [0, 1])
+    assert np.max(np.abs(got - np.array([0.375, 0.125, 0.125, 0.375]))) <= 1e-16
+
+
+def test_joint_errors():
+    net = fbngen.net_from_text(_read("diamond.fbn"))
+    jt = oracle.compile_net(net)
+    for q in ([0, 3], [1, 1], []):        # no common clique, repeated, empty
+        with pytest.raises(oracle.OracleError) as ei:
+            oracle.query_joint(jt, [], [], q)
+        assert ei.value.code == oracle.E_INVALID
+
+
+@settings(max_examples=60, deadline=None, suppress_health_check=[HealthCheck.too_slow])
+@given(seed=st.integers(0, 2**31 - 1), n=st.integers(2, 10), pick=st.integers(0, 10**6))
+def test_joint_posteriors_match_brute_force(seed, n, pick):
+    net = fbngen.random_small_net(seed, n, max_card=3, p_max=3)
+    jt = oracle.compile_net(net)
+    rng = np.random.default_rng(pick)
+    c = int(rng.integers(0, jt.n_cliques))
+    cv = jt.clique(c)[0]
+    q = [int(x) for x in rng.permutation(cv)[: int(rng.integers(1, len(cv) + 1))]]
+    m = int(rng.integers(0, max(1, n // 3) + 1))
+    obs = [int(x) for x in rng.choice(n, size=m, replace=False)]
+    states = [int(rng.integers(0, int(net.card[v]))) for v in obs]
+    pe, _ = refmath.brute_force(net, obs, states)
+    if pe <= 0:
+        return
+    got = oracle.query_joint(jt, obs, states, q)
+    want = refmath.brute_force_joint(net, obs, states, q)
+    assert np.max(np.abs(got - want)) <= 1e-13, (q, obs)
+
+
+@pytest.mark.parametrize("seed", range(3))
+def test_joint_marginals_are_the_posteriors(seed):
+    # the marginal of a joint onto one member equals that member's posterior
+    net = fbngen.random_small_net(700 + seed, 30, max_card=4, p_max=3, window=6)
+    jt = oracle.compile_net(net)
+    rng = np.random.default_rng(seed)
+    obs = [int(x) for x in rng.choice(net.n, size=4, replace=False)]
+    states = [int(rng.integers(0, int(net.card[v]))) for v in obs]
+    _, post = jt.query(obs, states)
+    off = np.concatenate([[0], np.cumsum(net.card)])
+    for c in range(jt.n_cliques):
+        q = [int(x) for x in jt.clique(c)[0]][:3]
+        j = oracle.query_joint(jt, obs, states, q).reshape([int(net.card[v]) for v in q])
+        for a, v in enumerate(q):
+            m = j.sum(axis=tuple(b for b in range(len(q)) if b != a))
+            assert np.max(np.abs(m - post[off[v]:off[v + 1]])) <= 1e-13, (c, v)
+
+
 # ---------------------------------------------------------------- errors
 
 @pytest.mark.parametrize("text,code", [
