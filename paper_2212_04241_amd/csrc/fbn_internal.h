@@ -34,7 +34,7 @@ struct Tree {
     std::vector<std::vector<int>> children;      // ascending id
     int ne = 0;                                  // edges, by ascending child id
     std::vector<int> e_parent, e_child;
-    std::vector<std::vector<int>> e_sep;         // ascending variable id
+    std::vector<std::vector<int>> e_sep;         // in the order they take in the parent's layout
     std::vector<uint64_t> e_size;
     std::vector<int> cpt_home, var_home;
     std::vector<std::vector<double>> prior;      // per clique, layout order, unscaled

@@ -11,8 +11,10 @@
 //   -> maximum-weight spanning tree over all clique pairs by Kruskal, key
 //      (-|separator|, product of separator cardinalities, i, j)
 //   -> root: a centre of the tree (minimum eccentricity), lowest id on ties
-//   -> layouts: root ascending; other cliques [parent separator ascending]
-//      ++ [remaining variables ascending]; last variable fastest
+//   -> layouts: root ascending; a separator's variables in the order they
+//      take in the parent clique's layout; other cliques [parent separator,
+//      in that order] ++ [remaining variables ascending]; last variable
+//      fastest
 //   -> CPT homes and posterior homes: smallest containing clique, lowest id.
 #include <algorithm>
 #include <cmath>
