@@ -112,12 +112,38 @@ typedef struct {
 void fbn_default_options(fbn_jt_options* opt);
 
 /* --- networks (Section 1) -------------------------------------------------
- * .fbn text: "fbn 1", "vars n", then per variable "var v r k p1..pk", then per
- * variable "cpt v m x1..xm" (parents in listed order, v fastest; values as C99
- * hexadecimal or decimal floats), then "end".  Validation: acyclic, r >= 2,
- * entries finite and >= 0, each row summing to 1 within 1e-9. */
+ * Two text formats, told apart by the first word:
+ *  .fbn: "fbn 1", "vars n", then per variable "var v r k p1..pk", then per
+ *    variable "cpt v m x1..xm" (parents in listed order, v fastest; values as
+ *    C99 hexadecimal or decimal floats), then "end".
+ *  BIF (Bayesian Interchange Format, the format of the public networks the
+ *    paper evaluates on, Section 3 and Table 1): "network", "variable NAME {
+ *    type discrete [r] { states }; }" and "probability ( NAME | PARENTS ) {
+ *    (parent states) p..; default p..; }" blocks ("table p..;" for a variable
+ *    without parents); comments and property lines are skipped.  Variables
+ *    are numbered in declaration order, parents kept in the listed order.  A
+ *    conditional distribution given as one flat table is refused as
+ *    ambiguous (FBN_E_PARSE); a row summing to within 1e-3 of one is divided
+ *    by its sum (rounded decimals), larger deviations are FBN_E_PARSE.
+ * Validation (both): acyclic, 2 <= r <= 65535, entries finite and >= 0,
+ * each row summing to 1 within 1e-9.  Errors: FBN_E_IO (file), FBN_E_PARSE
+ * (syntax, names, missing rows; fbn_last_error() gives the line),
+ * FBN_E_INVALID_ARG (a parsed network that fails validation). */
 fbn_status fbn_load_net(const char* path, fbn_net** out);
 fbn_status fbn_load_net_mem(const char* text, size_t len, fbn_net** out);
+/* Names and tables of a loaded network.  A BIF network keeps its declared
+ * variable and state names; an .fbn one is named by decimal ids ("0", "1",
+ * ...).  Name buffers are caller-owned, NUL-terminated (FBN_E_INVALID_ARG if
+ * cap is too small).  fbn_net_cpt gives v's cardinality, its parents (at
+ * most par_cap written) and its CPT in the layout above (at most cpt_cap
+ * doubles); any output pointer may be NULL. */
+fbn_status fbn_net_n_vars(const fbn_net* net, int32_t* n);
+fbn_status fbn_net_var_name(const fbn_net* net, int32_t v, char* buf, size_t cap);
+fbn_status fbn_net_state_name(const fbn_net* net, int32_t v, int32_t s, char* buf, size_t cap);
+fbn_status fbn_net_find_var(const fbn_net* net, const char* name, int32_t* v);
+fbn_status fbn_net_find_state(const fbn_net* net, int32_t v, const char* name, int32_t* s);
+fbn_status fbn_net_cpt(const fbn_net* net, int32_t v, int32_t* card, int32_t* parents, int32_t par_cap,
+                       int32_t* n_parents, double* cpt, size_t cpt_cap, size_t* cpt_len);
 /* The same network from arrays: card[n], n_parents[n], parents concatenated,
  * cpt concatenated per variable in the layout above. */
 fbn_status fbn_net_from_arrays(int32_t n_vars, const int32_t* card, const int32_t* n_parents,
@@ -181,6 +207,24 @@ fbn_status fbn_query_all(fbn_jt* jt, int32_t n_slots, const int32_t* slots, doub
  * 1 zero evidence, 2 FP32 underflow. */
 fbn_status fbn_fetch_async(fbn_jt* jt, int32_t n_slots, const int32_t* slots, double* post_out,
                            double* log_pe_out, int32_t* flags_out);
+
+/* Joint posterior P(Q | e) of n_q distinct query variables that lie together
+ * in one clique (Section 1: the conditional probability of the query
+ * variables -- plural -- given the evidence).  Reads what the slot's last
+ * fbn_calibrate left on the device: the calibrated table of the smallest
+ * clique holding every query variable (lowest id on ties) is rebuilt entry
+ * by entry (prior, evidence, child messages, parent ratio), summed onto Q in
+ * float64 in a fixed order and normalised.  out (host memory, out_len >=
+ * prod card[q] doubles) receives the joint with q_vars[0] slowest and
+ * q_vars[n_q-1] fastest.  Errors: FBN_E_INVALID_ARG for an empty, repeated
+ * or out-of-range Q, Q spanning no single clique, or out_len too small;
+ * FBN_E_NOMEM_DEVICE if its scratch (about prod card[q] doubles plus one
+ * per 16 clique entries when Q is small) cannot be allocated; the slot's
+ * FBN_E_ZERO_EVIDENCE / FBN_E_UNDERFLOW as in fbn_query_marginals (out then
+ * unspecified).  Allocates device scratch per call (the jt's allocator
+ * when set) and synchronises the jt's stream. */
+fbn_status fbn_query_joint(fbn_jt* jt, int32_t slot, int32_t n_q, const int32_t* q_vars, double* out,
+                           size_t out_len);
 
 /* --- kernel timing ----------------------------------------------------------
  * When enabled, every kernel launch of fbn_calibrate is bracketed by HIP

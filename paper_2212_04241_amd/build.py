@@ -15,7 +15,7 @@ CSRC = os.path.join(HERE, "csrc")
 BUILD = os.path.join(ROOT, "_build")
 LIB = os.path.join(HERE, "libfbn.so")
 
-SOURCES = ["kernels.hip", "kernels_interleaved.hip", "api.cpp", "tree.cpp", "plan.cpp"]
+SOURCES = ["kernels.hip", "kernels_interleaved.hip", "kernels_query.hip", "api.cpp", "tree.cpp", "plan.cpp", "bif.cpp"]
 ARCH = os.environ.get("FBN_OFFLOAD_ARCH", "gfx950")
 
 

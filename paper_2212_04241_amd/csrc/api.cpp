@@ -173,6 +173,10 @@ fbn_status parse_net(const char* text, size_t len, Net& net) {
 
 struct fbn_net {
     Net net;
+    // declared names (BIF); empty for .fbn text, whose variables are named
+    // by their ids and states by their indices
+    std::vector<std::string> names;
+    std::vector<std::vector<std::string>> states;
 };
 
 // ------------------------------------------------------------------ jt state
@@ -222,6 +226,7 @@ struct fbn_jt {
     int32_t* h_slots = nullptr;
     bool h_pinned = false;
     std::vector<char> dirty;
+    std::vector<int32_t> staged_slots;  // the slot list now in d_slots
     hipEvent_t staged = nullptr;
     bool staged_pending = false;
     // evidence lookup: for each variable, the (clique, layout position) pairs
@@ -491,7 +496,18 @@ fbn_status stage_slots(fbn_jt* jt, int32_t n, const int32_t* slots) {
     }
     HIP_OK(hipEventRecord(jt->staged, jt->stream));
     jt->staged_pending = true;
+    jt->staged_slots.assign(slots, slots + n);
     return FBN_OK;
+}
+
+// d_slots for a read-back of n slots: reused as is when it already holds
+// this list (the usual calibrate-then-fetch), so the read-back records no
+// new staging event and a following fbn_set_evidence does not wait for
+// the calibration in flight.
+fbn_status slots_for_fetch(fbn_jt* jt, int32_t n, const int32_t* slots) {
+    if (jt->staged_slots.size() == (size_t)n && std::equal(slots, slots + n, jt->staged_slots.begin()))
+        return FBN_OK;
+    return stage_slots(jt, n, slots);
 }
 
 template <class F>
@@ -576,7 +592,16 @@ fbn_status fbn_load_net_mem(const char* text, size_t len, fbn_net** out) {
     *out = nullptr;
     try {
         auto* h = new fbn_net();
-        fbn_status st = parse_net(text, len, h->net);
+        // .fbn text opens with "fbn"; anything else is read as BIF
+        size_t k = 0;
+        while (k < len && (text[k] == ' ' || text[k] == '\t' || text[k] == '\n' || text[k] == '\r')) k++;
+        fbn_status st;
+        if (len - k >= 3 && std::strncmp(text + k, "fbn", 3) == 0) {
+            st = parse_net(text, len, h->net);
+        } else {
+            const std::string err = parse_bif(text, len, h->net, h->names, h->states);
+            st = err.empty() ? check_net(h->net) : fail(FBN_E_PARSE, "BIF: " + err);
+        }
         if (st) {
             delete h;
             return st;
@@ -645,6 +670,64 @@ fbn_status fbn_net_from_arrays(int32_t n, const int32_t* card, const int32_t* np
 }
 
 void fbn_free_net(fbn_net* net) { delete net; }
+
+fbn_status fbn_net_n_vars(const fbn_net* net, int32_t* n) {
+    if (!net || !n) return fail(FBN_E_INVALID_ARG, "null argument");
+    *n = net->net.n;
+    return FBN_OK;
+}
+
+static fbn_status copy_name(const std::string& s, char* buf, size_t cap) {
+    if (!buf || cap < s.size() + 1) return fail(FBN_E_INVALID_ARG, "name buffer too small");
+    std::memcpy(buf, s.c_str(), s.size() + 1);
+    return FBN_OK;
+}
+
+fbn_status fbn_net_var_name(const fbn_net* net, int32_t v, char* buf, size_t cap) {
+    if (!net || v < 0 || v >= net->net.n) return fail(FBN_E_INVALID_ARG, "bad variable");
+    return copy_name(net->names.empty() ? std::to_string(v) : net->names[(size_t)v], buf, cap);
+}
+
+fbn_status fbn_net_state_name(const fbn_net* net, int32_t v, int32_t s, char* buf, size_t cap) {
+    if (!net || v < 0 || v >= net->net.n || s < 0 || s >= net->net.card[(size_t)v])
+        return fail(FBN_E_INVALID_ARG, "bad variable or state");
+    return copy_name(net->states.empty() ? std::to_string(s) : net->states[(size_t)v][(size_t)s], buf, cap);
+}
+
+fbn_status fbn_net_find_var(const fbn_net* net, const char* name, int32_t* v) {
+    if (!net || !name || !v) return fail(FBN_E_INVALID_ARG, "null argument");
+    for (int x = 0; x < net->net.n; x++)
+        if ((net->names.empty() ? std::to_string(x) : net->names[(size_t)x]) == name) {
+            *v = x;
+            return FBN_OK;
+        }
+    return fail(FBN_E_INVALID_ARG, std::string("no variable named ") + name);
+}
+
+fbn_status fbn_net_find_state(const fbn_net* net, int32_t v, const char* name, int32_t* s) {
+    if (!net || !name || !s || v < 0 || v >= net->net.n) return fail(FBN_E_INVALID_ARG, "bad argument");
+    for (int x = 0; x < net->net.card[(size_t)v]; x++)
+        if ((net->states.empty() ? std::to_string(x) : net->states[(size_t)v][(size_t)x]) == name) {
+            *s = x;
+            return FBN_OK;
+        }
+    return fail(FBN_E_INVALID_ARG, std::string("no state named ") + name);
+}
+
+fbn_status fbn_net_cpt(const fbn_net* net, int32_t v, int32_t* card, int32_t* parents, int32_t par_cap,
+                       int32_t* n_parents, double* cpt, size_t cpt_cap, size_t* cpt_len) {
+    if (!net || v < 0 || v >= net->net.n) return fail(FBN_E_INVALID_ARG, "bad variable");
+    const auto& par = net->net.parents[(size_t)v];
+    const auto& tab = net->net.cpt[(size_t)v];
+    if ((parents && par_cap < (int32_t)par.size()) || (cpt && cpt_cap < tab.size()))
+        return fail(FBN_E_INVALID_ARG, "output too small");
+    if (card) *card = net->net.card[(size_t)v];
+    if (n_parents) *n_parents = (int32_t)par.size();
+    if (cpt_len) *cpt_len = tab.size();
+    if (parents) std::copy(par.begin(), par.end(), parents);
+    if (cpt) std::copy(tab.begin(), tab.end(), cpt);
+    return FBN_OK;
+}
 
 static fbn_status build_jt_impl(const std::vector<const fbn_net*>& nets, const fbn_jt_options* opt_in, fbn_jt** out) {
     *out = nullptr;
@@ -1004,7 +1087,7 @@ fbn_status fbn_query_all(fbn_jt* jt, int32_t n, const int32_t* slots, double* ou
     const size_t per = jt->ctx.marg_stride;
     if (out && out_len < per * (size_t)n) return fail(FBN_E_INVALID_ARG, "output too small");
     HIP_OK(hipSetDevice(jt->device));
-    if ((st = stage_slots(jt, n, slots))) return st;
+    if ((st = slots_for_fetch(jt, n, slots))) return st;
     std::vector<double> lp((size_t)n);
     std::vector<int32_t> fl((size_t)n);
     if ((st = fetch(jt, n, out, lp.data(), fl.data()))) return st;
@@ -1024,7 +1107,7 @@ fbn_status fbn_fetch_async(fbn_jt* jt, int32_t n, const int32_t* slots, double* 
     if (st) return st;
     if (n == 0) return FBN_OK;
     HIP_OK(hipSetDevice(jt->device));
-    if ((st = stage_slots(jt, n, slots))) return st;
+    if ((st = slots_for_fetch(jt, n, slots))) return st;
     return fetch(jt, n, post_out, log_pe_out, flags_out);
 }
 
@@ -1052,6 +1135,121 @@ fbn_status fbn_query_marginals(fbn_jt* jt, int32_t slot, int32_t n_vars, const i
         for (uint32_t x = 0; x < h.card; x++) out[o++] = all[h.out + x];
     }
     return FBN_OK;
+}
+
+}  // extern "C"
+
+namespace {
+
+// The read-out plan of a joint query: the smallest clique holding every
+// query variable (lowest id on ties), and how its entries split into the
+// outputs' chunks.
+fbn_status joint_plan(const fbn_jt* jt, int32_t slot, int32_t nq, const int32_t* q, size_t out_len, JointArgs& a,
+                      int& home) {
+    const Tree& t = jt->tree;
+    if (slot < 0 || slot >= jt->opt.max_slots) return fail(FBN_E_INVALID_ARG, "slot out of range");
+    if (nq < 1 || !q) return fail(FBN_E_INVALID_ARG, "no query variables");
+    for (int32_t k = 0; k < nq; k++) {
+        if (q[k] < 0 || q[k] >= t.n) return fail(FBN_E_INVALID_ARG, "query variable out of range");
+        for (int32_t j = 0; j < k; j++)
+            if (q[j] == q[k]) return fail(FBN_E_INVALID_ARG, "query variable repeated");
+    }
+    home = -1;
+    for (int c = 0; c < t.nc; c++) {
+        const auto& vs = t.vars[(size_t)c];
+        bool all = true;
+        for (int32_t k = 0; k < nq && all; k++) all = std::find(vs.begin(), vs.end(), q[k]) != vs.end();
+        if (all && (home < 0 || t.size[(size_t)c] < t.size[(size_t)home])) home = c;
+    }
+    if (home < 0) return fail(FBN_E_INVALID_ARG, "the query variables share no clique");
+    const auto& vs = t.vars[(size_t)home];
+    std::vector<uint32_t> stride(vs.size());
+    uint64_t st = 1;
+    for (size_t k = vs.size(); k-- > 0;) {
+        stride[k] = (uint32_t)st;
+        st *= (uint64_t)t.card[(size_t)vs[k]];
+    }
+    std::memset(&a, 0, sizeof(a));
+    a.clique = (uint32_t)home;
+    a.slot = slot;
+    uint64_t n_out = 1;
+    auto var = [&](size_t k) {
+        JointVar jv{};
+        jv.card = (uint32_t)t.card[(size_t)vs[k]];
+        magic_u32(jv.card, jv.cmul, jv.csh);
+        jv.stride = stride[k];
+        return jv;
+    };
+    for (int32_t j = nq; j-- > 0;) {
+        const size_t k = (size_t)(std::find(vs.begin(), vs.end(), q[j]) - vs.begin());
+        a.qv[a.nq++] = var(k);
+        n_out *= (uint64_t)t.card[(size_t)q[j]];
+    }
+    for (size_t k = vs.size(); k-- > 0;)
+        if (std::find(q, q + nq, vs[k]) == q + nq) a.ov[a.no++] = var(k);
+    if (out_len < n_out) return fail(FBN_E_INVALID_ARG, "output too small");
+    a.n_out = (uint32_t)n_out;
+    a.n_r = (uint32_t)(t.size[(size_t)home] / n_out);
+    a.tpo = 1;
+    while (a.tpo < 64 && a.tpo < a.n_r) a.tpo *= 2;
+    a.chunk = a.tpo * 16;
+    a.nchunk = (a.n_r + a.chunk - 1) / a.chunk;
+    return FBN_OK;
+}
+
+// Device memory for one call's scratch, from the jt's allocator when it has
+// one; released with temp_free on the same stream.
+void* temp_alloc(fbn_jt* jt, size_t bytes) {
+    void* p = nullptr;
+    if (jt->opt.allocator.alloc) return jt->opt.allocator.alloc(jt->opt.allocator.ctx, bytes, jt->stream);
+    return hipMalloc(&p, bytes) == hipSuccess ? p : nullptr;
+}
+
+void temp_free(fbn_jt* jt, void* p) {
+    if (!p) return;
+    if (jt->opt.allocator.alloc) {
+        if (jt->opt.allocator.free) jt->opt.allocator.free(jt->opt.allocator.ctx, p, jt->stream);
+    } else {
+        hipFree(p);
+    }
+}
+
+// Launch the read-out into dev (joint_scratch_doubles(a) doubles), copy the
+// outputs and the slot's flags back, and wait.
+fbn_status joint_run(fbn_jt* jt, int home, const JointArgs& a, double* dev, double* out) {
+    const int prec = jt->opt.precision == FBN_FP32_RESCALED ? 1 : 0;
+    HIP_OK(launch_joint(jt->ctx, prec, jt->plan.cliques[(size_t)home], a, dev, jt->stream));
+    int32_t flag = 0;
+    HIP_OK(hipMemcpyAsync(out, dev, 8ull * a.n_out, hipMemcpyDeviceToHost, jt->stream));
+    HIP_OK(hipMemcpyAsync(&flag, jt->d_flags + a.slot, 4, hipMemcpyDeviceToHost, jt->stream));
+    HIP_OK(hipStreamSynchronize(jt->stream));
+    const fbn_status ps = status_of_flag(flag);
+    if (ps) return fail(ps, fbn_status_str(ps));
+    return FBN_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+fbn_status fbn_query_joint(fbn_jt* jt, int32_t slot, int32_t n_q, const int32_t* q_vars, double* out,
+                           size_t out_len) {
+    if (!jt || !out) return fail(FBN_E_INVALID_ARG, "null argument");
+    if (jt->opt.host_only) return fail(FBN_E_STATE, "host-only jt");
+    JointArgs a;
+    int home = -1;
+    fbn_status st = joint_plan(jt, slot, n_q, q_vars, out_len, a, home);
+    if (st) return st;
+    HIP_OK(hipSetDevice(jt->device));
+    if ((st = wait_staged(jt))) return st;
+    void* dev = temp_alloc(jt, 8 * joint_scratch_doubles(a));
+    if (!dev) return fail(FBN_E_NOMEM_DEVICE, "device allocation failed");
+    st = joint_run(jt, home, a, static_cast<double*>(dev), out);
+    const std::string keep = g_err;
+    hipStreamSynchronize(jt->stream);
+    temp_free(jt, dev);
+    g_err = keep;
+    return st;
 }
 
 fbn_status fbn_jt_stats(const fbn_jt* jt, fbn_jt_stats_t* out) {

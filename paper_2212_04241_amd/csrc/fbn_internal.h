@@ -40,6 +40,12 @@ struct Tree {
     std::vector<std::vector<double>> prior;      // per clique, layout order, unscaled
 };
 
+// Parse a network in the Bayesian Interchange Format (bif.cpp): variables in
+// declaration order, CPTs with the listed parents and the variable fastest.
+// Returns "" or the error text; names and states receive the declared names.
+std::string parse_bif(const char* text, size_t len, Net& net, std::vector<std::string>& names,
+                      std::vector<std::vector<std::string>>& states);
+
 // Returns an empty string on success, else the error text.  code receives
 // an fbn_status value.
 std::string compile_tree(const Net& net, uint64_t max_entries, Tree& out, int& code);

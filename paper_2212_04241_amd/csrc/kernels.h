@@ -91,4 +91,31 @@ hipError_t launch_fin_interleaved(const Ctx& c, int prec, bool dist, const DSepF
                                   int nslots, hipStream_t s);
 hipError_t launch_marginals_interleaved(const Ctx& c, const int32_t* slots, int nslots, hipStream_t s);
 
+// Joint posterior read-out (kernels_query.hip).  A clique variable as the
+// read-out enumerates it: its cardinality (with the multiply-high constants
+// of a division by it) and its stride in the clique table.
+constexpr int kJointMaxVars = 32;
+struct JointVar {
+    uint32_t card, cmul, csh, stride;
+};
+struct JointArgs {
+    uint32_t clique;     // the clique read (its evidence record)
+    int32_t slot;
+    uint32_t n_out;      // joint assignments of the query variables
+    uint32_t n_r;        // clique entries per assignment: |C| / n_out
+    uint32_t nchunk;     // chunks per assignment
+    uint32_t chunk;      // entries per chunk
+    uint32_t tpo;        // lanes per chunk (a power of two, at most 64)
+    uint32_t nq, no;     // query variables, other variables of the clique
+    JointVar qv[kJointMaxVars];  // query variables, the last listed (fastest) first
+    JointVar ov[kJointMaxVars];  // the clique's other variables, fastest first
+};
+// Device doubles the read-out needs: the outputs, one sum per block of 256
+// outputs and, when an output has several chunks, the chunk sums.
+size_t joint_scratch_doubles(const JointArgs& a);
+// Normalised P(Q | e) of slot a.slot into scratch[0 .. a.n_out), from the
+// calibrated tables of clique q; scratch holds joint_scratch_doubles(a).
+hipError_t launch_joint(const Ctx& c, int prec, const DClique& q, const JointArgs& a, double* scratch,
+                        hipStream_t s);
+
 }  // namespace fbn

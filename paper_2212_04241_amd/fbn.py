@@ -78,6 +78,13 @@ def lib():
         "fbn_load_net_mem": (C.c_int32, [C.c_char_p, C.c_size_t, vpp]),
         "fbn_net_from_arrays": (C.c_int32, [C.c_int32, i32p, i32p, i32p, f64p, vpp]),
         "fbn_free_net": (None, [C.c_void_p]),
+        "fbn_net_n_vars": (C.c_int32, [C.c_void_p, i32p]),
+        "fbn_net_var_name": (C.c_int32, [C.c_void_p, C.c_int32, C.c_char_p, C.c_size_t]),
+        "fbn_net_state_name": (C.c_int32, [C.c_void_p, C.c_int32, C.c_int32, C.c_char_p, C.c_size_t]),
+        "fbn_net_find_var": (C.c_int32, [C.c_void_p, C.c_char_p, i32p]),
+        "fbn_net_find_state": (C.c_int32, [C.c_void_p, C.c_int32, C.c_char_p, i32p]),
+        "fbn_net_cpt": (C.c_int32, [C.c_void_p, C.c_int32, i32p, i32p, C.c_int32, i32p, f64p, C.c_size_t,
+                                    P(C.c_size_t)]),
         "fbn_build_jt": (C.c_int32, [C.c_void_p, P(fbn_jt_options), vpp]),
         "fbn_build_forest": (C.c_int32, [P(C.c_void_p), C.c_int32, P(fbn_jt_options), vpp]),
         "fbn_free_jt": (None, [C.c_void_p]),
@@ -89,6 +96,7 @@ def lib():
         "fbn_query_marginals": (C.c_int32, [C.c_void_p, C.c_int32, C.c_int32, i32p, f64p, C.c_size_t]),
         "fbn_query_all": (C.c_int32, [C.c_void_p, C.c_int32, i32p, f64p, C.c_size_t, f64p, i32p]),
         "fbn_fetch_async": (C.c_int32, [C.c_void_p, C.c_int32, i32p, f64p, f64p, i32p]),
+        "fbn_query_joint": (C.c_int32, [C.c_void_p, C.c_int32, C.c_int32, i32p, f64p, C.c_size_t]),
         "fbn_status_str": (C.c_char_p, [C.c_int32]),
         "fbn_last_error": (C.c_char_p, []),
         "fbn_jt_stats": (C.c_int32, [C.c_void_p, P(fbn_jt_stats_t)]),
@@ -130,6 +138,47 @@ class Net:
         if getattr(self, "_h", None) and _lib is not None:
             _lib.fbn_free_net(self._h)
             self._h = None
+
+
+def net_n_vars(net: Net) -> int:
+    n = C.c_int32()
+    _check(lib().fbn_net_n_vars(net._h, C.byref(n)), "fbn_net_n_vars")
+    return n.value
+
+
+def net_var_name(net: Net, v: int) -> str:
+    buf = C.create_string_buffer(4096)
+    _check(lib().fbn_net_var_name(net._h, v, buf, len(buf)), "fbn_net_var_name")
+    return buf.value.decode()
+
+
+def net_state_name(net: Net, v: int, s: int) -> str:
+    buf = C.create_string_buffer(4096)
+    _check(lib().fbn_net_state_name(net._h, v, s, buf, len(buf)), "fbn_net_state_name")
+    return buf.value.decode()
+
+
+def net_find_var(net: Net, name: str) -> int:
+    v = C.c_int32()
+    _check(lib().fbn_net_find_var(net._h, name.encode(), C.byref(v)), "fbn_net_find_var")
+    return v.value
+
+
+def net_find_state(net: Net, v: int, name: str) -> int:
+    s = C.c_int32()
+    _check(lib().fbn_net_find_state(net._h, v, name.encode(), C.byref(s)), "fbn_net_find_state")
+    return s.value
+
+
+def net_cpt(net: Net, v: int):
+    """(card, parents, cpt) of variable v: parents in listed order, v fastest."""
+    card, npar, ln = C.c_int32(), C.c_int32(), C.c_size_t()
+    _check(lib().fbn_net_cpt(net._h, v, C.byref(card), None, 0, C.byref(npar), None, 0, C.byref(ln)), "fbn_net_cpt")
+    par = np.zeros(max(npar.value, 1), dtype=np.int32)
+    cpt = np.zeros(max(ln.value, 1), dtype=np.float64)
+    _check(lib().fbn_net_cpt(net._h, v, None, par.ctypes.data_as(C.POINTER(C.c_int32)), par.size, None,
+                             cpt.ctypes.data_as(C.POINTER(C.c_double)), cpt.size, None), "fbn_net_cpt")
+    return card.value, par[:npar.value].copy(), cpt[:ln.value].copy()
 
 
 def load_net(path: str) -> Net:
@@ -296,6 +345,17 @@ def query_all(jt: JT, slots, marg_total: int):
                                lp.ctypes.data_as(C.POINTER(C.c_double)), st.ctypes.data_as(C.POINTER(C.c_int32))),
            "fbn_query_all")
     return out, lp, st
+
+
+def query_joint(jt: JT, slot: int, qvars, card) -> np.ndarray:
+    """Joint posterior P(qvars | e) of a calibrated slot, qvars[0] slowest
+    (qvars must lie together in one clique)."""
+    q, pq = _i32(qvars)
+    n = int(np.prod([int(card[x]) for x in q], dtype=np.int64)) if q.size else 0
+    out = np.zeros(max(n, 1), dtype=np.float64)
+    _check(lib().fbn_query_joint(jt._h, slot, q.size, pq, out.ctypes.data_as(C.POINTER(C.c_double)), n),
+           "fbn_query_joint")
+    return out[:n]
 
 
 def fetch_async(jt: JT, slots, post_out, log_pe_out, flags_out) -> None:

@@ -103,16 +103,18 @@ def test_forest_fp64_mixed_shapes():
 
 
 @pytest.mark.timeout(600)
-def test_forest_c4_full_batch_fp32_graph():
+@pytest.mark.parametrize("layout,tile", [(fbn.FBN_LAYOUT_PER_SLOT, 0), (fbn.FBN_LAYOUT_INTERLEAVED, 128)])
+def test_forest_c4_full_batch_fp32_graph(layout, tile):
     # the full batch: 256 networks x 64 cases in one calibration, FP32,
     # replayed from a captured graph; posteriors of a sample of 16 networks
-    # (every case), log P(e) of three slots over all 256 networks
+    # (every case), log P(e) of three slots over all 256 networks.  The
+    # interleaved layout at tile 128 is the configuration the bench times.
     import torch
     nets, cases, off = _forest(256)
-    say("forest fp32, 256 networks x 64 cases, graph")
+    say("forest fp32, 256 networks x 64 cases, graph, layout", layout, "tile", tile)
     s = torch.cuda.Stream()
     jt = fbn.JT([fbn.net_from_spec(n) for n in nets], precision=fbn.FBN_FP32_RESCALED, max_slots=64,
-                stream=s.cuda_stream)
+                stream=s.cuda_stream, layout=layout, tile_entries=tile)
     fbn.set_graph_mode(jt, True)
     ids = list(range(64))
     for rep in range(2):

@@ -85,6 +85,22 @@ def test_c3_huge_clique():
 
 
 @pytest.mark.timeout(600)
+def test_c3_bench_subset_fp32():
+    # the bench's C3 configuration (interleaved, tile 256, FP32) on the first
+    # 20 cases, every posterior entry against the oracle
+    from concurrent.futures import ThreadPoolExecutor
+    import oracle
+    net = fbngen.make_net("C3", 0)
+    cases = fbngen.make_cases("C3", net)[:20]
+    ojt = oracle.compile_net(net)
+    say("interleaved C3 fp32, 20 cases, tile 256")
+    with ThreadPoolExecutor(8) as ex:
+        ref = list(ex.map(lambda c: ojt.query(*c), cases))
+    post, lp, st, _ = gpu_run(net, cases, precision=fbn.FBN_FP32_RESCALED, layout=IL, tile=256)
+    say("worst fp32", check_fp32(post, lp, st, ref, "il C3 fp32 bench subset"))
+
+
+@pytest.mark.timeout(600)
 def test_c5_network():
     net = fbngen.make_net("C5", 7)
     rng = np.random.default_rng(11)

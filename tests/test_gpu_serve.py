@@ -113,3 +113,92 @@ def test_server_tuned_tiles(c5):
         assert st[0] == 0
         assert np.array_equal(res.post[i], post[0]), i
         assert res.log_pe[i] == lp[0], i
+
+
+def _tiny(text):
+    return fbngen.net_from_text(text)
+
+
+# A -> B with P(B = 1 | A) = 1e-60: observing B = 1 leaves every FP32 table
+# entry of the evidence at zero (5e-61 is below float32's range), so the FP32
+# path flags underflow and the server reruns the query on an FP64 tree.
+_UNDERFLOW_NET = ("fbn 1\nvars 2\nvar 0 2 0\nvar 1 2 1 0\ncpt 0 2\n0.25 0.75\n"
+                  "cpt 1 4\n1 1e-60 1 1e-60\nend\n")
+# C with P(C = 1) = 0: observing C = 1 has probability zero in any precision.
+_ZERO_NET = ("fbn 1\nvars 2\nvar 0 2 0\nvar 1 3 1 0\ncpt 0 2\n1 0\n"
+             "cpt 1 6\n0.2 0.3 0.5 0.1 0.1 0.8\nend\n")
+
+
+@pytest.mark.timeout(600)
+def test_served_fp64_fallback():
+    from paper_2212_04241_amd.serve import Query
+    nets = [_tiny(_UNDERFLOW_NET), _tiny(_ZERO_NET), fbngen.make_net("C1", 0)]
+    c1 = fbngen.make_cases("C1", nets[2])[:6]
+    qs = [Query(0, 0, np.array([1], np.int32), np.array([1], np.int32)),      # FP32 underflow -> FP64
+          Query(1, 2, c1[0][0], c1[0][1]),
+          Query(2, 1, np.array([0], np.int32), np.array([1], np.int32)),      # zero evidence
+          Query(3, 0, np.array([1], np.int32), np.array([0], np.int32)),      # fine in FP32
+          Query(4, 1, np.array([1], np.int32), np.array([2], np.int32))]      # fine in FP32
+    qs += [Query(5 + k, 2, c1[k][0], c1[k][1]) for k in range(1, 6)]
+    say("served mix with FP64 fallbacks")
+    srv = Server(nets, budget_bytes=1 << 30, max_batch=4)
+    res = srv.run(qs, None, keep=range(len(qs)))
+    tiles = list(srv.tiles)
+    srv.close()
+    assert res.precision[0] == fbn.FBN_FP64 and res.status[0] == fbn.FBN_OK
+    assert res.precision[2] == fbn.FBN_FP64 and res.status[2] == fbn.FBN_E_ZERO_EVIDENCE
+    for i in (1, 3, 4) + tuple(range(5, 10)):
+        assert res.precision[i] == fbn.FBN_FP32_RESCALED and res.status[i] == fbn.FBN_OK, i
+    # the rerun is bitwise the FP64 engine's result for that query alone
+    jt = fbn.JT(fbn.net_from_spec(nets[0]), precision=fbn.FBN_FP64, max_slots=1, tile_entries=tiles[0])
+    fbn.set_evidence(jt, 0, qs[0].vars, qs[0].states)
+    lp, st = fbn.calibrate(jt, [0], want_results=True)
+    post, _, _ = fbn.query_all(jt, [0], int(np.sum(nets[0].card)))
+    assert st[0] == 0
+    assert np.array_equal(res.post[0], post[0]) and res.log_pe[0] == lp[0]
+    # and the oracle's: P(A | B = 1) = P(A), P(e) = 1e-60
+    ojt = oracle.compile_net(nets[0])
+    olp, opost = ojt.query(qs[0].vars, qs[0].states)
+    assert np.all(np.abs(res.post[0] - opost) <= 1e-12 * np.abs(opost))
+    assert abs(res.log_pe[0] - olp) <= 1e-12 * abs(olp)
+    assert abs(olp - np.log(1e-60)) <= 1e-12 * abs(olp)
+
+
+@pytest.mark.timeout(600)
+def test_second_batch_of_a_tree_is_enqueued_while_the_first_runs():
+    """After calibrate + fetch_async of one batch, entering the next batch's
+    evidence returns without waiting for the first calibration."""
+    import torch
+    net = fbngen.make_net("C3", 0)
+    cases = fbngen.make_cases("C3", net)[:8]
+    s = torch.cuda.Stream()
+    jt = fbn.JT(fbn.net_from_spec(net), precision=fbn.FBN_FP32_RESCALED, max_slots=8, stream=s.cuda_stream)
+    cs = int(np.sum(net.card))
+    bufs = [(torch.empty((4, cs), dtype=torch.float64, pin_memory=True).numpy(),
+             torch.empty(4, dtype=torch.float64, pin_memory=True).numpy(),
+             torch.empty(4, dtype=torch.int32, pin_memory=True).numpy()) for _ in range(2)]
+    a, b = [0, 1, 2, 3], [4, 5, 6, 7]
+    for _ in range(2):     # warm up, then the timed pattern
+        fbn.set_evidence_batch(jt, a, cases[:4])
+        fbn.calibrate(jt, a)
+        fbn.fetch_async(jt, a, *bufs[0])
+        e1 = torch.cuda.Event()
+        e1.record(s)
+        fbn.set_evidence_batch(jt, b, cases[4:])
+        queued = not e1.query()
+        fbn.calibrate(jt, b)
+        fbn.fetch_async(jt, b, *bufs[1])
+        s.synchronize()
+    say("second batch entered while the first ran:", queued)
+    assert queued
+    # results of both batches are those of the same cases run alone
+    for buf, ids in ((bufs[0], range(4)), (bufs[1], range(4, 8))):
+        assert not buf[2].any()
+        one = fbn.JT(fbn.net_from_spec(net), precision=fbn.FBN_FP32_RESCALED, max_slots=1)
+        for r, k in enumerate(ids):
+            fbn.set_evidence(one, 0, *cases[k])
+            fbn.calibrate(one, [0])
+            post, lp, _ = fbn.query_all(one, [0], cs)
+            assert np.array_equal(buf[0][r], post[0]) and buf[1][r] == lp[0], k
+        one.free()
+    jt.free()
