@@ -225,6 +225,19 @@ fbn_status fbn_fetch_async(fbn_jt* jt, int32_t n_slots, const int32_t* slots, do
  * when set) and synchronises the jt's stream. */
 fbn_status fbn_query_joint(fbn_jt* jt, int32_t slot, int32_t n_q, const int32_t* q_vars, double* out,
                            size_t out_len);
+/* fbn_query_joint for callers that cannot allocate device memory (code under
+ * graph capture, tight serving loops, hosts that forbid allocation): the same
+ * read-out, bitwise the same result, with its scratch in a static device
+ * array of 2^22 doubles (32 MiB) that each GPU the library runs on holds
+ * until the process ends.  Calls no allocator.  A read-out needing more
+ * scratch than that (about n_out + n_out / 256 doubles, plus n_out * chunks
+ * when each joint assignment covers more than 16 * 64 clique entries) fails
+ * with FBN_E_TOO_LARGE and changes nothing.  All calls on one GPU share that
+ * GPU's array: calls that overlap in time on one GPU (other host threads,
+ * other jts' streams) race and must be serialised by the caller.  Other
+ * errors as fbn_query_joint. */
+fbn_status fbn_query_joint_noalloc(fbn_jt* jt, int32_t slot, int32_t n_q, const int32_t* q_vars, double* out,
+                                   size_t out_len);
 
 /* --- kernel timing ----------------------------------------------------------
  * When enabled, every kernel launch of fbn_calibrate is bracketed by HIP

@@ -1252,6 +1252,25 @@ fbn_status fbn_query_joint(fbn_jt* jt, int32_t slot, int32_t n_q, const int32_t*
     return st;
 }
 
+fbn_status fbn_query_joint_noalloc(fbn_jt* jt, int32_t slot, int32_t n_q, const int32_t* q_vars, double* out,
+                                   size_t out_len) {
+    if (!jt || !out) return fail(FBN_E_INVALID_ARG, "null argument");
+    if (jt->opt.host_only) return fail(FBN_E_STATE, "host-only jt");
+    JointArgs a;
+    int home = -1;
+    fbn_status st = joint_plan(jt, slot, n_q, q_vars, out_len, a, home);
+    if (st) return st;
+    if (joint_scratch_doubles(a) > kJointScratchDoubles)
+        return fail(FBN_E_TOO_LARGE, "the joint read-out needs " + std::to_string(joint_scratch_doubles(a)) +
+                                         " scratch doubles, more than the " + std::to_string(kJointScratchDoubles) +
+                                         " of the static buffer");
+    HIP_OK(hipSetDevice(jt->device));
+    if ((st = wait_staged(jt))) return st;
+    double* dev = nullptr;
+    HIP_OK(joint_static_scratch(&dev));
+    return joint_run(jt, home, a, dev, out);
+}
+
 fbn_status fbn_jt_stats(const fbn_jt* jt, fbn_jt_stats_t* out) {
     if (!jt || !out) return fail(FBN_E_INVALID_ARG, "null argument");
     const Tree& t = jt->tree;

@@ -117,5 +117,11 @@ size_t joint_scratch_doubles(const JointArgs& a);
 // calibrated tables of clique q; scratch holds joint_scratch_doubles(a).
 hipError_t launch_joint(const Ctx& c, int prec, const DClique& q, const JointArgs& a, double* scratch,
                         hipStream_t s);
+// The allocation-free read-out's scratch: a device array of
+// kJointScratchDoubles doubles (32 MiB) per GPU, held until the process
+// ends.  *ptr receives its address on the current device, looked up once per
+// device.
+constexpr size_t kJointScratchDoubles = size_t(1) << 22;
+hipError_t joint_static_scratch(double** ptr);
 
 }  // namespace fbn

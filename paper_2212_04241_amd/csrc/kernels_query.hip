@@ -24,12 +24,23 @@
 //
 // Scratch: the chunk sums (when an output has more than one chunk), the
 // unnormalised outputs and the block sums live in a device buffer that the
-// caller provides.
+// caller provides -- allocated per call by the library, or, for callers
+// that cannot allocate, the file-scope array `scratch` below.  Every value
+// the kernels read from it is written earlier in the same call, so nothing
+// needs clearing between calls.
 #include <hip/hip_runtime.h>
+
+#include <mutex>
 
 #include "kernels.h"
 
 namespace fbn {
+
+// Device memory for the allocation-free joint read-out: one copy per GPU,
+// held until the process ends.  Host code never passes this name to a
+// kernel or a copy; it uses the address hipGetSymbolAddress returns for the
+// current device (joint_static_scratch).
+static __device__ __align__(256) double scratch[kJointScratchDoubles];
 
 namespace {
 
@@ -145,6 +156,10 @@ __global__ __launch_bounds__(kBlockQ) void k_joint_norm(double* __restrict__ out
     if (o < n_out) out[o] = z > 0.0 ? out[o] / z : 0.0;
 }
 
+std::mutex g_scratch_mu;
+constexpr int kMaxDevices = 64;
+double* g_scratch_ptr[kMaxDevices] = {};
+
 }  // namespace
 
 size_t joint_scratch_doubles(const JointArgs& a) {
@@ -172,6 +187,22 @@ hipError_t launch_joint(const Ctx& c, int prec, const DClique& q, const JointArg
     if ((e = hipGetLastError()) != hipSuccess) return e;
     hipLaunchKernelGGL(k_joint_norm, dim3(nb), dim3(kBlockQ), 0, s, out, zb, a.n_out, nb);
     return hipGetLastError();
+}
+
+hipError_t joint_static_scratch(double** ptr) {
+    int dev = -1;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return e;
+    if (dev < 0 || dev >= kMaxDevices) return hipErrorInvalidDevice;
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+        void* p = nullptr;
+        e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess) return e;
+        g_scratch_ptr[dev] = static_cast<double*>(p);
+    }
+    *ptr = g_scratch_ptr[dev];
+    return hipSuccess;
 }
 
 }  // namespace fbn

@@ -97,6 +97,7 @@ def lib():
         "fbn_query_all": (C.c_int32, [C.c_void_p, C.c_int32, i32p, f64p, C.c_size_t, f64p, i32p]),
         "fbn_fetch_async": (C.c_int32, [C.c_void_p, C.c_int32, i32p, f64p, f64p, i32p]),
         "fbn_query_joint": (C.c_int32, [C.c_void_p, C.c_int32, C.c_int32, i32p, f64p, C.c_size_t]),
+        "fbn_query_joint_noalloc": (C.c_int32, [C.c_void_p, C.c_int32, C.c_int32, i32p, f64p, C.c_size_t]),
         "fbn_status_str": (C.c_char_p, [C.c_int32]),
         "fbn_last_error": (C.c_char_p, []),
         "fbn_jt_stats": (C.c_int32, [C.c_void_p, P(fbn_jt_stats_t)]),
@@ -347,14 +348,16 @@ def query_all(jt: JT, slots, marg_total: int):
     return out, lp, st
 
 
-def query_joint(jt: JT, slot: int, qvars, card) -> np.ndarray:
+def query_joint(jt: JT, slot: int, qvars, card, noalloc: bool = False) -> np.ndarray:
     """Joint posterior P(qvars | e) of a calibrated slot, qvars[0] slowest
-    (qvars must lie together in one clique)."""
+    (qvars must lie together in one clique).  noalloc: the entry point that
+    allocates no device memory (static scratch)."""
     q, pq = _i32(qvars)
     n = int(np.prod([int(card[x]) for x in q], dtype=np.int64)) if q.size else 0
     out = np.zeros(max(n, 1), dtype=np.float64)
-    _check(lib().fbn_query_joint(jt._h, slot, q.size, pq, out.ctypes.data_as(C.POINTER(C.c_double)), n),
-           "fbn_query_joint")
+    fn = lib().fbn_query_joint_noalloc if noalloc else lib().fbn_query_joint
+    name = "fbn_query_joint_noalloc" if noalloc else "fbn_query_joint"
+    _check(fn(jt._h, slot, q.size, pq, out.ctypes.data_as(C.POINTER(C.c_double)), n), name)
     return out[:n]
 
 
