@@ -351,44 +351,10 @@ def forest_logpe_err(W, ojts, lp, slot):
     return abs(float(lp[slot]) - tot)
 
 
-def bench_served(args, fbn):
-    """The served workload: eight resident networks, a Poisson trace of
-    evidence queries, continuous batching with footprint admission (FP32),
-    against the plain per-query FP64 engine on the same trace.  Load points:
-    closed loop (every query available at once) for both; open loop at 0.8 x
-    the plain engine's saturation rate for both; open loop at 0.8 x the
-    served saturation rate for the served path."""
-    import fbngen
-    from paper_2212_04241_amd.serve import Server, serve_plain, trace_queries
-    nets = [fbngen.make_net("C5", j) for j in range(8)]
-    times, which, fracs, seeds = fbngen.make_arrivals("C5")
-    n = min(args.trace, len(times))
-    cases = [fbngen.case_for_arrival(nets[int(which[i])], float(fracs[i]), int(seeds[i])) for i in range(n)]
-    queries = trace_queries(times[:n], which[:n], cases)
-    log(f"[bench] C5: 8 networks, {n} trace queries")
-    t0 = time.perf_counter()
-    # tile per tree: --tile, else the tuner's pick for a full batch of each tree
-    srv = Server(nets, budget_bytes=int(args.budget_gb * (1 << 30)), max_batch=args.max_batch,
-                 tile=args.tile or None, layout=args.layout)
-    server_s = time.perf_counter() - t0
-    log(f"[bench] server up in {server_s:.1f} s: {srv.slots} slots per tree, "
-        f"{srv.device_bytes / 2**30:.2f} GiB resident, plan {srv.planned_bytes / 2**30:.2f} GiB of "
-        f"{args.budget_gb} GiB")
-    keep = list(range(min(200, n)))
-    for _ in range(args.warmup):
-        srv.run(queries[: min(n, 256)])
-    # (i) closed loop, served: `steps` replays of the trace
-    tot_q = tot_t = 0.0
-    sat = None
-    for _ in range(args.steps):
-        r = srv.run(queries, None, keep=keep if sat is None else None)
-        sat = sat or r
-        tot_q += n
-        tot_t += r.wall
-    qps_served = tot_q / tot_t
-    log(f"[bench] served closed loop: {qps_served:.1f} q/s ({args.steps} x {n} queries), "
-        f"p50 {1e3 * sat.percentile(50):.2f} ms")
-    # dominant kernel: one profiled (eager) full batch per tree
+def profile_full_batches(fbn, srv, queries):
+    """Per kernel kind (ms, launches, algorithmic bytes) over one eager, HIP-
+    event-timed calibration of a full batch (the first trace queries of its
+    network) on every resident tree."""
     prof = {}
     for k, jt in enumerate(srv.jts):
         qs = [q for q in queries if q.net == k][: srv.slots]
@@ -405,6 +371,74 @@ def bench_served(args, fbn):
             a[1] += launches
             a[2] += byts
         fbn.jt_profile_enable(jt, False)
+    return prof
+
+
+def copy_calibration():
+    """A plain device copy of known size, so that byte counters taken in the
+    same run can be scaled (read 512 MiB, write 512 MiB, three times)."""
+    import torch
+    src = torch.ones(128 << 20, dtype=torch.float32, device="cuda")
+    dst = torch.empty_like(src)
+    for _ in range(3):
+        dst.copy_(src)
+    torch.cuda.synchronize()
+    log("[bench] copy calibration: 3 x 512 MiB device copies")
+
+
+def bench_served(args, fbn):
+    """The served workload: eight resident networks, a Poisson trace of
+    evidence queries, continuous batching with footprint admission (FP32),
+    against the plain per-query FP64 engine on the same trace.  Load points:
+    closed loop (every query available at once) for both; open loop at 0.8 x
+    the plain engine's saturation rate for both; open loop at 0.8 x the
+    served saturation rate for the served path."""
+    import fbngen
+    from paper_2212_04241_amd.serve import Server, serve_plain, trace_queries
+    nets = [fbngen.make_net("C5", j) for j in range(8)]
+    times, which, fracs, seeds = fbngen.make_arrivals("C5")
+    n = min(args.trace, len(times))
+    cases = [fbngen.case_for_arrival(nets[int(which[i])], float(fracs[i]), int(seeds[i])) for i in range(n)]
+    queries = trace_queries(times[:n], which[:n], cases)
+    log(f"[bench] C5: 8 networks, {n} trace queries")
+    t0 = time.perf_counter()
+    # tile per tree: --tiles, else --tile for all, else the tuner's pick for a
+    # full batch of each tree
+    tiles = [int(x) for x in args.tiles.split(",")] if args.tiles else (args.tile or None)
+    srv = Server(nets, budget_bytes=int(args.budget_gb * (1 << 30)), max_batch=args.max_batch,
+                 tile=tiles, layout=args.layout, warm=not args.kernels_only)
+    server_s = time.perf_counter() - t0
+    log(f"[bench] server up in {server_s:.1f} s: {srv.slots} slots per tree, "
+        f"{srv.device_bytes / 2**30:.2f} GiB resident, plan {srv.planned_bytes / 2**30:.2f} GiB of "
+        f"{args.budget_gb} GiB, tiles {srv.tiles}")
+    if args.kernels_only:
+        prof = profile_full_batches(fbn, srv, queries)
+        srv.close()
+        if args.copy_calibration:
+            copy_calibration()
+        roofline = roofline_of({k: tuple(v) for k, v in prof.items()}, "C5", args.layout, args.tile,
+                               "one full batch per resident tree, eager launches, HIP events",
+                               interleaved=args.layout == 2)
+        print(json.dumps({"workload": "C5", "tiles": srv.tiles, "roofline": roofline,
+                          "kernel_ms_one_batch_per_tree": {k: v[0] for k, v in prof.items()},
+                          "kernel_launches": {k: v[1] for k, v in prof.items()}}), flush=True)
+        return
+    keep = list(range(min(200, n)))
+    for _ in range(args.warmup):
+        srv.run(queries[: min(n, 256)])
+    # (i) closed loop, served: `steps` replays of the trace
+    tot_q = tot_t = 0.0
+    sat = None
+    for _ in range(args.steps):
+        r = srv.run(queries, None, keep=keep if sat is None else None)
+        sat = sat or r
+        tot_q += n
+        tot_t += r.wall
+    qps_served = tot_q / tot_t
+    log(f"[bench] served closed loop: {qps_served:.1f} q/s ({args.steps} x {n} queries), "
+        f"p50 {1e3 * sat.percentile(50):.2f} ms")
+    # dominant kernel: one profiled (eager) full batch per tree
+    prof = profile_full_batches(fbn, srv, queries)
     # plain FP64 engine, closed loop over a prefix
     plain_sat = serve_plain(nets, queries, None, limit=args.plain_queries, keep=keep)
     log(f"[bench] plain fp64 closed loop: {plain_sat.qps:.1f} q/s over {len(plain_sat.latency)} queries")
@@ -423,6 +457,27 @@ def bench_served(args, fbn):
     status_nonzero = int(np.count_nonzero(sat.status)) + int(np.count_nonzero(plain_sat.status))
     fallbacks = int(np.count_nonzero(sat.precision == fbn.FBN_FP64))
     srv.close()
+    # the same server with the shrinking reduction (only evidence-consistent
+    # entries read and written), one closed-loop replay: what it changes
+    shrink = None
+    if not args.no_shrink_compare:
+        srv_s = Server(nets, budget_bytes=int(args.budget_gb * (1 << 30)), max_batch=args.max_batch,
+                       tile=srv_tiles, layout=args.layout, shrink_evidence=True)
+        srv_s.run(queries[: min(n, 256)])
+        rs = srv_s.run(queries, None, keep=keep)
+        sprof = profile_full_batches(fbn, srv_s, queries)
+        same = all(np.array_equal(rs.post[i], sat.post[i]) and rs.log_pe[i] == sat.log_pe[i] for i in keep)
+        srv_s.close()
+        dk = max(prof, key=lambda k: prof[k][0])
+        shrink = {"queries_per_s": round(rs.qps, 1), "p50_ms": round(1e3 * rs.percentile(50), 3),
+                  "results_bitwise_equal_on_first": len(keep) if same else -1,
+                  "speedup_vs_streaming_every_entry": round(rs.qps / max(qps_served, 1e-9), 3),
+                  "table_bytes_streamed_vs_every_entry": round(
+                      sum(v[2] for k, v in sprof.items() if k in ("collect", "distribute")) /
+                      max(sum(v[2] for k, v in prof.items() if k in ("collect", "distribute")), 1.0), 3),
+                  f"{dk}_ms_one_batch_per_tree": round(sprof[dk][0], 3)}
+        log(f"[bench] served with the shrinking reduction: {rs.qps:.1f} q/s "
+            f"(x{shrink['speedup_vs_streaming_every_entry']}, bytes x{shrink['table_bytes_streamed_vs_every_entry']})")
 
     roofline = roofline_of({k: tuple(v) for k, v in prof.items()}, "C5", args.layout, args.tile,
                            "one full batch per resident tree, eager launches, HIP events",
@@ -462,6 +517,7 @@ def bench_served(args, fbn):
             "open_loop_at_0.8x_served": {"rate_per_s": round(lam3, 1), "served": lat(srv_3),
                                          "plain": "unstable at this rate (above its saturation)"},
             "served_vs_plain": round(qps_served / max(plain_sat.qps, 1e-9), 2),
+            "served_fp32_shrinking_reduction_closed_loop": shrink,
         },
         "status_nonzero": status_nonzero,
     }
@@ -511,7 +567,8 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--workload", default="C2")
+    ap.add_argument("--workload", default="C5",
+                    help="C5 (default: the served comparison the metric names), C1, C2, C3 or C4")
     ap.add_argument("--plain-queries", type=int, default=300)
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -528,6 +585,12 @@ def main():
     ap.add_argument("--trace", type=int, default=4096, help="C5: trace queries")
     ap.add_argument("--budget-gb", type=float, default=32.0, help="C5: device-memory budget, GiB")
     ap.add_argument("--max-batch", type=int, default=32, help="C5: slots per resident tree at most")
+    ap.add_argument("--tiles", default="",
+                    help="C5: comma-separated tile per tree (default: tuned on the device)")
+    ap.add_argument("--kernels-only", action="store_true",
+                    help="C5: only the profiled full batch per resident tree (for counter runs)")
+    ap.add_argument("--no-shrink-compare", action="store_true",
+                    help="C5: skip the closed-loop replay with the shrinking reduction")
     args = ap.parse_args()
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
@@ -573,15 +636,7 @@ def main():
     log(f"[bench] fp32 batched: {qps32:.1f} q/s, {1e3 * dt32 / args.steps:.3f} ms/step")
     jt32.free()
     if args.copy_calibration:
-        # a plain device copy of known size, so that byte counters taken in
-        # the same run can be scaled (read 512 MiB, write 512 MiB, three times)
-        import torch
-        src = torch.ones(128 << 20, dtype=torch.float32, device="cuda")
-        dst = torch.empty_like(src)
-        for _ in range(3):
-            dst.copy_(src)
-        torch.cuda.synchronize()
-        log("[bench] copy calibration: 3 x 512 MiB device copies")
+        copy_calibration()
     roofline = roofline_of(prof32, key, args.layout, args.tile, interleaved=bool(stats["interleaved"]))
     if not args.fp32_only:
         roofline["stream_copy_GBps"] = round(copy_gbps(), 1)

@@ -93,7 +93,13 @@ typedef struct {
     fbn_allocator allocator;
     void* stream;                 /* hipStream_t                              */
     int32_t layout;               /* FBN_LAYOUT_*                             */
-    int32_t reserved;
+    int32_t shrink_evidence;      /* PER_SLOT layout, the reduction of
+                                   * Section 2 shrinking what is streamed:
+                                   * 1 reads and writes, per slot, only the
+                                   * table entries that agree with its
+                                   * evidence; 0 (default) streams every
+                                   * entry, the zeroed ones included.
+                                   * Results are bitwise the same.            */
 } fbn_jt_options;
 
 typedef struct {

@@ -217,6 +217,7 @@ struct fbn_jt {
     DEvidence* d_ev = nullptr;
     double* d_bmax = nullptr;
     double* d_bmarg = nullptr;
+    double* d_rsum = nullptr;   // per slot: root sums in float64
     int32_t* d_slots = nullptr;
     double* d_out_post = nullptr;
     double* d_out_logpe = nullptr;
@@ -250,6 +251,9 @@ struct fbn_jt {
     int64_t prof_n[FBN_PROFILE_KINDS] = {};
     // per layer: table entries, and separator entries finalised after it
     std::vector<uint64_t> coll_entries, coll_sep, dist_entries, dist_sep;
+    // per slot and layer: the table entries its evidence leaves live (the
+    // bytes the per-slot layout streams with shrink_evidence)
+    std::vector<uint64_t> live_coll, live_dist;
 };
 
 namespace {
@@ -321,7 +325,7 @@ fbn_status wait_staged(fbn_jt* jt) {
 
 // Per-slot strides and the bytes one slot adds to each per-slot buffer, in
 // allocation order.
-constexpr int kSlotBuffers = 17;
+constexpr int kSlotBuffers = 18;
 
 struct SlotLayout {
     uint64_t psi_stride;
@@ -345,7 +349,8 @@ SlotLayout slot_layout(const fbn_jt* jt) {
     const size_t u[kSlotBuffers] = {w * L.psi_stride, w * p.sep_stride, w * p.sep_stride, w * p.sep_stride,
                                     w * L.part_stride, 4ull * L.kexp_stride, 8ull * L.marg_stride,
                                     8ull * L.marg_stride, 8, 4, sizeof(DEvidence) * L.ev_stride, 4,
-                                    8ull * L.marg_stride, 8, 4, 8ull * L.bmax_stride, 8ull * L.bmarg_stride};
+                                    8ull * L.marg_stride, 8, 4, 8ull * L.bmax_stride, 8ull * L.bmarg_stride,
+                                    8ull * std::max<uint32_t>(p.n_roots, 1)};
     std::copy(u, u + kSlotBuffers, L.unit);
     return L;
 }
@@ -407,7 +412,8 @@ fbn_status setup_device(fbn_jt* jt) {
                                  (void**)&jt->d_kexp, (void**)&jt->d_marg, (void**)&jt->d_post,
                                  (void**)&jt->d_logpe, (void**)&jt->d_flags, (void**)&jt->d_ev,
                                  (void**)&jt->d_slots, (void**)&jt->d_out_post, (void**)&jt->d_out_logpe,
-                                 (void**)&jt->d_out_flags, (void**)&jt->d_bmax, (void**)&jt->d_bmarg};
+                                 (void**)&jt->d_out_flags, (void**)&jt->d_bmax, (void**)&jt->d_bmarg,
+                                 (void**)&jt->d_rsum};
     for (int k = 0; k < kSlotBuffers; k++) {
         const size_t bytes = SL.unit[k] * (size_t)S;
         *dsts[k] = dev_alloc(jt, bytes);
@@ -440,6 +446,7 @@ fbn_status setup_device(fbn_jt* jt) {
     c.sepd = jt->d_sepd;
     c.acc = jt->d_acc;
     c.part = jt->d_part;
+    c.rsum = jt->d_rsum;
     c.kexp = jt->d_kexp;
     c.marg = jt->d_marg;
     c.post = jt->d_post;
@@ -464,6 +471,7 @@ fbn_status setup_device(fbn_jt* jt) {
     c.S = p.interleaved ? (uint32_t)S : 0u;
     c.fp32 = f32 ? 1 : 0;
     c.tile = p.stage;
+    c.dense = jt->opt.shrink_evidence ? 0 : 1;
     HIP_OK(hipStreamSynchronize(jt->stream));
     return FBN_OK;
 }
@@ -801,6 +809,14 @@ static fbn_status build_jt_impl(const std::vector<const fbn_net*>& nets, const f
             for (size_t k = 0; k < jt->tree.vars[(size_t)c].size(); k++)
                 jt->occ[(size_t)jt->tree.vars[(size_t)c][k]].push_back({c, (int)k});
         jt->dirty.assign((size_t)opt.max_slots, 0);
+        jt->live_coll.assign((size_t)opt.max_slots * jt->coll_entries.size(), 0);
+        jt->live_dist.assign((size_t)opt.max_slots * jt->dist_entries.size(), 0);
+        for (int32_t s = 0; s < opt.max_slots; s++) {
+            std::copy(jt->coll_entries.begin(), jt->coll_entries.end(),
+                      jt->live_coll.begin() + (size_t)s * jt->coll_entries.size());
+            std::copy(jt->dist_entries.begin(), jt->dist_entries.end(),
+                      jt->live_dist.begin() + (size_t)s * jt->dist_entries.size());
+        }
         if (opt.host_only) {
             jt->device_bytes = footprint(jt, jt->slot_bytes);
         } else {
@@ -896,6 +912,29 @@ fbn_status fbn_set_evidence(fbn_jt* jt, int32_t slot, int32_t n_obs, const int32
         }
     }
     jt->dirty[(size_t)slot] = 1;
+    // live entries per layer (shrinking reduction only, for the kernel
+    // timing's byte counts): a clique holding observed variables keeps
+    // |C| / prod(their cardinalities) entries
+    if (jt->opt.shrink_evidence) {
+        const size_t nh = jt->coll_entries.size(), nd = jt->dist_entries.size();
+        uint64_t* lc = jt->live_coll.data() + (size_t)slot * nh;
+        uint64_t* ld = jt->live_dist.data() + (size_t)slot * nd;
+        std::copy(jt->coll_entries.begin(), jt->coll_entries.end(), lc);
+        std::copy(jt->dist_entries.begin(), jt->dist_entries.end(), ld);
+        std::vector<std::pair<int, uint64_t>> div;  // (clique, product of observed cardinalities)
+        for (int32_t k = 0; k < n_obs; k++)
+            for (const auto& cp : jt->occ[(size_t)vars[k]]) div.push_back({cp.first, (uint64_t)t.card[(size_t)vars[k]]});
+        std::sort(div.begin(), div.end());
+        for (size_t a = 0; a < div.size();) {
+            uint64_t d = 1;
+            size_t b = a;
+            for (; b < div.size() && div[b].first == div[a].first; b++) d *= div[b].second;
+            const uint64_t sz = t.size[(size_t)div[a].first], gone = sz - sz / d;
+            lc[(size_t)t.height[(size_t)div[a].first]] -= gone;
+            ld[(size_t)t.depth[(size_t)div[a].first]] -= gone;
+            a = b;
+        }
+    }
     return FBN_OK;
 }
 
@@ -1023,6 +1062,19 @@ static fbn_status enqueue_calibration(fbn_jt* jt, int32_t n) {
     HIP_OK(launch_begin(c, jt->d_slots, n, s));
     const double w = prec ? 4.0 : 8.0, nb = (double)n;
     if (p.interleaved) return enqueue_interleaved(jt, n, w * nb);
+    // table entries the batch streams per layer: the live ones per slot
+    // (every one unless shrink_evidence)
+    std::vector<double> ent_c(p.collect.size(), 0.0), ent_d(p.distribute.size(), 0.0);
+    if (jt->prof) {
+        const bool dense = jt->opt.shrink_evidence == 0;
+        for (size_t h = 0; h < ent_c.size(); h++) ent_c[h] = dense ? nb * (double)jt->coll_entries[h] : 0.0;
+        for (size_t d = 0; d < ent_d.size(); d++) ent_d[d] = dense ? nb * (double)jt->dist_entries[d] : 0.0;
+        if (!dense)
+            for (int32_t s : jt->staged_slots) {
+                for (size_t h = 0; h < ent_c.size(); h++) ent_c[h] += (double)jt->live_coll[(size_t)s * ent_c.size() + h];
+                for (size_t d = 0; d < ent_d.size(); d++) ent_d[d] += (double)jt->live_dist[(size_t)s * ent_d.size() + d];
+            }
+    }
     // a layer's finalisers: the small separators (a wave or a workgroup
     // each) and the first phase of the large ones' blocks in one launch,
     // then the blocks' second phase; the layer's bytes are booked on the first
@@ -1047,7 +1099,7 @@ static fbn_status enqueue_calibration(fbn_jt* jt, int32_t n) {
     for (size_t h = 0; h < p.collect.size(); h++) {
         const Layer& ly = p.collect[h];
         // reads the prior, writes the working table
-        if ((st = timed(jt, 0, 2.0 * w * nb * (double)jt->coll_entries[h], [&] {
+        if ((st = timed(jt, 0, 2.0 * w * ent_c[h], [&] {
                  return launch_collect(c, prec, jt->d_groups + ly.group0, ly.ngroup, jt->d_slots, n, s);
              })))
             return st;
@@ -1056,7 +1108,7 @@ static fbn_status enqueue_calibration(fbn_jt* jt, int32_t n) {
     for (size_t d = 0; d < p.distribute.size(); d++) {
         const Layer& ly = p.distribute[d];
         // reads the working table
-        if ((st = timed(jt, 2, w * nb * (double)jt->dist_entries[d], [&] {
+        if ((st = timed(jt, 2, w * ent_d[d], [&] {
                  return launch_distribute(c, prec, jt->d_works + ly.group0, ly.ngroup, jt->d_slots, n, s);
              })))
             return st;

@@ -26,6 +26,8 @@ struct Ctx {
     void* acc;             // new separator sums (sep_stride), table precision: every sum is
                            // accumulated in float64 and rounded once when stored
     void* part;            // partial sums (part_stride), table precision, likewise
+    double* rsum;          // per slot: each root's sum (its tree's share of P(e)), float64, unrounded
+                           // (nroots per slot; interleaved: root r of slot s at r * S + s)
     int32_t* kexp;         // collect rescale exponents (kexp_stride)
     double* marg;          // float64 marginal accumulators (marg_stride)
     double* post;          // float64 posteriors (marg_stride)
@@ -40,6 +42,9 @@ struct Ctx {
     uint32_t sep_total, nroots;  // the roots' one-entry separators follow sep_total
     uint32_t S;            // slot-interleaved layout: entry x of slot s at x * S + s (0: per-slot layout)
     uint32_t tile;         // LDS entries reserved per slot in a workgroup
+    int32_t dense;         // per-slot layout: 1 streams every table entry; 0 skips, per slot, the
+                           // entries its evidence zeroes (never read, psi never written there):
+                           // the shrink_evidence option
 };
 
 // Bytes of LDS a layer workgroup stages; slots per workgroup times tile

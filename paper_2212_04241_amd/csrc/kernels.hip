@@ -119,9 +119,23 @@ struct EntryC {
     T prior;
     uint64_t dig, toff;
     uint32_t gi, child0, nchild;
+    uint32_t need;  // bit b: slot b reads and writes this entry
 };
 
-template <typename T, int B, int NC, int U>
+// Slots of the workgroup that must touch an entry with packed digits d:
+// every slot in the batch when tables are streamed whole (SKIP false), else
+// only those whose evidence agrees at d (an entry the evidence zeroes is
+// neither read nor written: it contributes an exact zero to every sum).
+template <int B, bool SKIP>
+__device__ __forceinline__ uint32_t need_mask(uint64_t d, const DEvidence (&ev)[B], uint32_t valid) {
+    if (!SKIP) return valid;
+    uint32_t m = 0;
+#pragma unroll
+    for (int b = 0; b < B; b++) m |= ((d ^ ev[b].want) & ev[b].mask) ? 0u : (1u << b);
+    return m & valid;
+}
+
+template <typename T, int B, int NC, int U, bool SKIP>
 __device__ __forceinline__ void collect_entries(const Ctx& c, const EntryC<T, B> (&e)[U], uint32_t nvalid,
                                                 const DEvidence (&ev)[B], const int (&sl)[B],
                                                 const uint32_t (&ksep)[kMaxKids], const uint32_t (&kmh)[kMaxKids],
@@ -140,23 +154,29 @@ __device__ __forceinline__ void collect_entries(const Ctx& c, const EntryC<T, B>
 #pragma unroll
         for (int b = 0; b < B; b++)
 #pragma unroll
-            for (int k = 0; k < NC; k++) w[u][b][k] = sepc_b[b][jk[u][k]];  // a slot past the batch reads slot 0's
+            for (int k = 0; k < NC; k++) {
+                if (!SKIP || ((e[u].need >> b) & 1u)) w[u][b][k] = sepc_b[b][jk[u][k]];
+                else w[u][b][k] = T(0);
+            }
 #pragma unroll
     for (int u = 0; u < U; u++) {
         if ((uint32_t)u >= nvalid) break;
 #pragma unroll
         for (int b = 0; b < B; b++) {
             if (sl[b] < 0) continue;
-            T v = ((e[u].dig ^ ev[b].want) & ev[b].mask) ? T(0) : e[u].prior;
+            T v = T(0);
+            if (!SKIP || ((e[u].need >> b) & 1u)) {
+                v = ((e[u].dig ^ ev[b].want) & ev[b].mask) ? T(0) : e[u].prior;
 #pragma unroll
-            for (int k = 0; k < NC; k++) v *= w[u][b][k];
-            if (NC == kMaxKids) {
-                for (uint32_t k = kMaxKids; k < e[u].nchild; k++) {
-                    const DChild ch = c.ch[e[u].child0 + k];
-                    v *= sepc_b[b][ch.sep + map[ch.mh + e[u].hi] + map[ch.ml + e[u].lo]];
+                for (int k = 0; k < NC; k++) v *= w[u][b][k];
+                if (NC == kMaxKids) {
+                    for (uint32_t k = kMaxKids; k < e[u].nchild; k++) {
+                        const DChild ch = c.ch[e[u].child0 + k];
+                        v *= sepc_b[b][ch.sep + map[ch.mh + e[u].hi] + map[ch.ml + e[u].lo]];
+                    }
                 }
+                psi_b[b][e[u].toff] = v;
             }
-            psi_b[b][e[u].toff] = v;
             vals[b * c.tile + e[u].gi] = v;
         }
     }
@@ -165,9 +185,9 @@ __device__ __forceinline__ void collect_entries(const Ctx& c, const EntryC<T, B>
 // A group that is one run of one clique: U entries per thread at a time
 // (as many as keep U x B x children loads in registers), their lookups and
 // loads issued together.
-template <typename T, int B, int NC>
+template <typename T, int B, int NC, bool SKIP>
 __device__ __forceinline__ void collect_run(const Ctx& c, uint32_t total, uint32_t r_base, uint32_t L, uint32_t Lmul,
-                                            uint32_t Lsh, uint32_t hdig, uint32_t ldig, bool anyev,
+                                            uint32_t Lsh, uint32_t hdig, uint32_t ldig, bool anyev, uint32_t valid,
                                             const T* r_prior, uint32_t psi0, uint32_t child0, uint32_t nk,
                                             const DEvidence (&ev)[B], const int (&sl)[B],
                                             const uint32_t (&ksep)[kMaxKids], const uint32_t (&kmh)[kMaxKids],
@@ -183,19 +203,20 @@ __device__ __forceinline__ void collect_run(const Ctx& c, uint32_t total, uint32
             const uint32_t i = gi + r_base;
             e[u].hi = mdiv(i, Lmul, Lsh);
             e[u].lo = i - e[u].hi * L;
-            e[u].prior = r_prior[i];
             e[u].dig = anyev ? (c.dig[hdig + e[u].hi] | c.dig[ldig + e[u].lo]) : 0;
+            e[u].need = need_mask<B, SKIP>(e[u].dig, ev, valid);
+            e[u].prior = r_prior[i];
             e[u].toff = (uint64_t)psi0 + i;
             e[u].gi = gi;
             e[u].child0 = child0;
             e[u].nchild = nk;
         }
         const uint32_t nvalid = min((uint32_t)U, (total - g0 + kBlock - 1) / kBlock);
-        collect_entries<T, B, NC, U>(c, e, nvalid, ev, sl, ksep, kmh, kml, psi_b, sepc_b, vals);
+        collect_entries<T, B, NC, U, SKIP>(c, e, nvalid, ev, sl, ksep, kmh, kml, psi_b, sepc_b, vals);
     }
 }
 
-template <typename T, int B>
+template <typename T, int B, bool SKIP>
 __global__ __launch_bounds__(kBlock) void k_collect(Ctx c, const DGroup* __restrict__ groups, uint32_t ngroups,
                                                     const int32_t* __restrict__ slots, int nslots) {
     __shared__ __align__(16) unsigned char stage[kStageBytes];
@@ -208,10 +229,12 @@ __global__ __launch_bounds__(kBlock) void k_collect(Ctx c, const DGroup* __restr
     const Cell cell = xcd_cell(ngroups, ((uint32_t)nslots + B - 1) / B);
     const DGroup g = groups[cell.item];
     int sl[B];
+    uint32_t valid = 0;
 #pragma unroll
     for (int b = 0; b < B; b++) {
         const int k = (int)cell.group * B + b;
         sl[b] = k < nslots ? slots[k] : -1;
+        valid |= (sl[b] >= 0 ? 1u : 0u) << b;
     }
     // ---- run metadata into LDS
     if (threadIdx.x < g.npiece) {
@@ -289,7 +312,7 @@ __global__ __launch_bounds__(kBlock) void k_collect(Ctx c, const DGroup* __restr
         const T* rp = prior + r.off;
         switch (r.nchild) {
 #define FBN_RUN(NC)                                                                                                   \
-    collect_run<T, B, NC>(c, g.total, rb, r.L, r.Lmul, r.Lsh, r.hdig, r.ldig, anyev != 0, rp, r.psi, r.child0,      \
+    collect_run<T, B, NC, SKIP>(c, g.total, rb, r.L, r.Lmul, r.Lsh, r.hdig, r.ldig, anyev != 0, valid, rp, r.psi, r.child0, \
                           r.nchild, ev, sl, ksep, kmh, kml, psi_b, sepc_b, vals)
         case 0: FBN_RUN(0); break;
         case 1: FBN_RUN(1); break;
@@ -335,20 +358,21 @@ __global__ __launch_bounds__(kBlock) void k_collect(Ctx c, const DGroup* __restr
             const uint32_t i = gi + r_base;
             const uint32_t hi = mdiv(i, r_Lmul, r_Lsh);
             const uint32_t lo = i - hi * r_L;
-            const T pv = r_prior[i];
             const uint64_t d = anyev ? (c.dig[r_hdig + hi] | c.dig[r_ldig + lo]) : 0;
+            const uint32_t need = need_mask<B, SKIP>(d, ev, valid);
+            const T pv = r_prior[i];
             const uint64_t toff = (uint64_t)runs[p].psi + i;
-            const EntryC<T, B> e[1] = {{hi, lo, pv, d, toff, gi, runs[p].child0, nk}};
+            const EntryC<T, B> e[1] = {{hi, lo, pv, d, toff, gi, runs[p].child0, nk, need}};
             switch (nk) {
-            case 0: collect_entries<T, B, 0, 1>(c, e, 1u, ev, sl, ksep, kmh, kml, psi_b, sepc_b, vals); break;
-            case 1: collect_entries<T, B, 1, 1>(c, e, 1u, ev, sl, ksep, kmh, kml, psi_b, sepc_b, vals); break;
-            case 2: collect_entries<T, B, 2, 1>(c, e, 1u, ev, sl, ksep, kmh, kml, psi_b, sepc_b, vals); break;
-            case 3: collect_entries<T, B, 3, 1>(c, e, 1u, ev, sl, ksep, kmh, kml, psi_b, sepc_b, vals); break;
-            case 4: collect_entries<T, B, 4, 1>(c, e, 1u, ev, sl, ksep, kmh, kml, psi_b, sepc_b, vals); break;
-            case 5: collect_entries<T, B, 5, 1>(c, e, 1u, ev, sl, ksep, kmh, kml, psi_b, sepc_b, vals); break;
-            case 6: collect_entries<T, B, 6, 1>(c, e, 1u, ev, sl, ksep, kmh, kml, psi_b, sepc_b, vals); break;
-            case 7: collect_entries<T, B, 7, 1>(c, e, 1u, ev, sl, ksep, kmh, kml, psi_b, sepc_b, vals); break;
-            default: collect_entries<T, B, kMaxKids, 1>(c, e, 1u, ev, sl, ksep, kmh, kml, psi_b, sepc_b, vals); break;
+            case 0: collect_entries<T, B, 0, 1, SKIP>(c, e, 1u, ev, sl, ksep, kmh, kml, psi_b, sepc_b, vals); break;
+            case 1: collect_entries<T, B, 1, 1, SKIP>(c, e, 1u, ev, sl, ksep, kmh, kml, psi_b, sepc_b, vals); break;
+            case 2: collect_entries<T, B, 2, 1, SKIP>(c, e, 1u, ev, sl, ksep, kmh, kml, psi_b, sepc_b, vals); break;
+            case 3: collect_entries<T, B, 3, 1, SKIP>(c, e, 1u, ev, sl, ksep, kmh, kml, psi_b, sepc_b, vals); break;
+            case 4: collect_entries<T, B, 4, 1, SKIP>(c, e, 1u, ev, sl, ksep, kmh, kml, psi_b, sepc_b, vals); break;
+            case 5: collect_entries<T, B, 5, 1, SKIP>(c, e, 1u, ev, sl, ksep, kmh, kml, psi_b, sepc_b, vals); break;
+            case 6: collect_entries<T, B, 6, 1, SKIP>(c, e, 1u, ev, sl, ksep, kmh, kml, psi_b, sepc_b, vals); break;
+            case 7: collect_entries<T, B, 7, 1, SKIP>(c, e, 1u, ev, sl, ksep, kmh, kml, psi_b, sepc_b, vals); break;
+            default: collect_entries<T, B, kMaxKids, 1, SKIP>(c, e, 1u, ev, sl, ksep, kmh, kml, psi_b, sepc_b, vals); break;
             }
         }
     }
@@ -395,7 +419,11 @@ __global__ __launch_bounds__(kBlock) void k_collect(Ctx c, const DGroup* __restr
         if (sidx < ns && sub == 0) {
 #pragma unroll
             for (int b = 0; b < B; b++)
-                if (sl[b] >= 0) static_cast<T*>(c.acc)[(uint64_t)sl[b] * c.sep_stride + out] = (T)a[b];
+                if (sl[b] >= 0) {
+                    static_cast<T*>(c.acc)[(uint64_t)sl[b] * c.sep_stride + out] = (T)a[b];
+                    // a root's sum (its tree's share of P(e)) also kept unrounded
+                    if (out >= c.sep_total) c.rsum[(uint64_t)sl[b] * c.nroots + (out - c.sep_total)] = a[b];
+                }
         }
     }
 }
@@ -546,8 +574,10 @@ __device__ __forceinline__ void fin_collect_team(const Ctx& c, const DSepFin* __
     int32_t* kexp = c.kexp + (uint64_t)slot * c.kexp_stride;
 
     double mx = 0.0;
-    finish_range(f, acc + f.sep, part + f.part0, 0u, f.size, lane, tm.size,
-                 [&](uint32_t, double v) { mx = fmax(mx, v); });
+    finish_range(f, acc + f.sep, part + f.part0, 0u, f.size, lane, tm.size, [&](uint32_t, double v) {
+        mx = fmax(mx, v);
+        if (f.edge < 0) c.rsum[(uint64_t)slot * c.nroots + (f.sep - c.sep_total)] = v;
+    });
     if (f.nchunk) tm.sync();  // other lanes rescale these sums below
     mx = tm.max(mx);
 
@@ -583,6 +613,7 @@ struct RunD {
     uint32_t L, Lmul, Lsh;
     int32_t pedge;
     uint32_t psep, pmh, pml, psi;  // psi: working-table offset
+    uint32_t hdig, ldig;           // packed-digit tables (evidence test)
 };
 
 struct TgtD {
@@ -590,20 +621,23 @@ struct TgtD {
     uint32_t out0, gofs, L, pad;
 };
 
-template <typename T, int B>
+template <typename T, int B, bool SKIP>
 __global__ __launch_bounds__(kBlock) void k_dist_gather(Ctx c, const DWork* __restrict__ works, uint32_t nworks,
                                                         const int32_t* __restrict__ slots, int nslots) {
     __shared__ __align__(16) unsigned char stage[kStageBytes];
     __shared__ RunD runs[kMaxPieces];
     __shared__ TgtD tgts[kMaxPieces];
+    __shared__ DEvidence evs[SKIP ? kMaxPieces : 1][B];
     T* vals = reinterpret_cast<T*>(stage);
     const Cell cell = xcd_cell(nworks, ((uint32_t)nslots + B - 1) / B);
     const DWork w = works[cell.item];
     int sl[B];
+    uint32_t valid = 0;
 #pragma unroll
     for (int b = 0; b < B; b++) {
         const int k = (int)cell.group * B + b;
         sl[b] = k < nslots ? slots[k] : -1;
+        valid |= (sl[b] >= 0 ? 1u : 0u) << b;
     }
     const uint32_t* __restrict__ map = c.map;
     const uint32_t lane = threadIdx.x & (kWave - 1);
@@ -618,7 +652,13 @@ __global__ __launch_bounds__(kBlock) void k_dist_gather(Ctx c, const DWork* __re
             const DPiece pc = c.pc[w.piece0 + threadIdx.x];
             const DClique cq = c.cl[pc.clique];
             runs[threadIdx.x] = RunD{cq.off, pc.count, pc.gofs, cq.L, cq.Lmul, cq.Lsh, cq.pedge, cq.psep, cq.pmh,
-                                     cq.pml, cq.psi};
+                                     cq.pml, cq.psi, cq.hdig, cq.ldig};
+            if (SKIP) {
+#pragma unroll
+                for (int b = 0; b < B; b++)
+                    evs[threadIdx.x][b] = sl[b] >= 0 ? c.ev[(uint64_t)sl[b] * c.ev_stride + pc.clique]
+                                                     : DEvidence{0, 0};
+            }
         }
         if (threadIdx.x >= 64 && threadIdx.x - 64 < w.nwt) {
             const uint32_t k = threadIdx.x - 64;
@@ -643,10 +683,19 @@ __global__ __launch_bounds__(kBlock) void k_dist_gather(Ctx c, const DWork* __re
     }
     if (!packed) {
         // four entries per thread at a time, their map lookups and every
-        // slot's psi and ratio loads issued together (a slot past the batch
-        // reads slot 0's tables)
+        // slot's psi and ratio loads issued together; a slot whose evidence
+        // zeroes an entry reads nothing for it (its psi there was never
+        // written), unless tables are streamed whole
         constexpr uint32_t U = 4;
         const bool ratio = q.pedge >= 0;
+        DEvidence ev[B];
+        uint64_t anyev = 0;
+#pragma unroll
+        for (int b = 0; b < B; b++) {
+            ev[b] = SKIP && sl[b] >= 0 ? c.ev[(uint64_t)sl[b] * c.ev_stride + tg.clique] : DEvidence{0, 0};
+            anyev |= ev[b].mask;
+        }
+        const bool test = SKIP && anyev;
         for (uint32_t g0 = threadIdx.x; g0 < n; g0 += U * kBlock) {
             uint32_t ent[U], row[U], lo[U], pr[U];
 #pragma unroll
@@ -664,13 +713,22 @@ __global__ __launch_bounds__(kBlock) void k_dist_gather(Ctx c, const DWork* __re
 #pragma unroll
                 for (uint32_t u = 0; u < U; u++) pr[u] = q.psep + map[q.pmh + row[u]] + map[q.pml + lo[u]];
             }
+            uint32_t nd[U];
+#pragma unroll
+            for (uint32_t u = 0; u < U; u++)
+                nd[u] = need_mask<B, SKIP>(test ? (c.dig[q.hdig + row[u]] | c.dig[q.ldig + lo[u]]) : 0, ev, valid);
             T v[U][B], r[U][B];
 #pragma unroll
             for (uint32_t u = 0; u < U; u++)
 #pragma unroll
                 for (int b = 0; b < B; b++) {
-                    v[u][b] = psi_b[b][(uint64_t)q.psi + ent[u]];
-                    r[u][b] = sepd_b[b][pr[u]];
+                    if (!SKIP || ((nd[u] >> b) & 1u)) {
+                        v[u][b] = psi_b[b][(uint64_t)q.psi + ent[u]];
+                        r[u][b] = sepd_b[b][pr[u]];
+                    } else {
+                        v[u][b] = T(0);
+                        r[u][b] = T(0);
+                    }
                 }
 #pragma unroll
             for (uint32_t u = 0; u < U; u++) {
@@ -684,9 +742,10 @@ __global__ __launch_bounds__(kBlock) void k_dist_gather(Ctx c, const DWork* __re
     } else {
         // packed: the current run's fields, reloaded only when the run changes
         uint32_t p = 0, r_end = 0, r_gofs = 0, r_L = 1, r_Lmul = 0, r_Lsh = 0, r_psep = 0, r_pmh = 0, r_pml = 0;
-        uint32_t r_psi = 0;
+        uint32_t r_psi = 0, r_hdig = 0, r_ldig = 0;
         int32_t r_pedge = -1;
-        bool first = true;
+        bool first = true, test = false;
+        DEvidence ev[B];
         for (uint32_t gi = threadIdx.x; gi < n; gi += kBlock) {
             if (first || gi >= r_end) {
                 if (!first) p++;
@@ -703,18 +762,33 @@ __global__ __launch_bounds__(kBlock) void k_dist_gather(Ctx c, const DWork* __re
                 r_pmh = rr.pmh;
                 r_pml = rr.pml;
                 r_psi = rr.psi;
+                r_hdig = rr.hdig;
+                r_ldig = rr.ldig;
+                uint64_t anyev = 0;
+#pragma unroll
+                for (int b = 0; b < B; b++) {
+                    ev[b] = SKIP ? evs[p][b] : DEvidence{0, 0};
+                    anyev |= ev[b].mask;
+                }
+                test = SKIP && anyev;
             }
             const uint32_t ent = gi - r_gofs;
             const uint32_t row = mdiv(ent, r_Lmul, r_Lsh);
             const uint32_t l = ent - row * r_L;
             const uint32_t pr = r_pedge >= 0 ? r_psep + map[r_pmh + row] + map[r_pml + l] : 0u;
-            // every slot's loads issued together (a slot past the batch reads
-            // slot 0's tables; a root clique reads ratio entry 0, unused)
+            const uint32_t nd = need_mask<B, SKIP>(test ? (c.dig[r_hdig + row] | c.dig[r_ldig + l]) : 0, ev, valid);
+            // every needed slot's loads issued together (a root clique reads
+            // ratio entry 0, unused)
             T v[B], r[B];
 #pragma unroll
             for (int b = 0; b < B; b++) {
-                v[b] = psi_b[b][(uint64_t)r_psi + ent];
-                r[b] = sepd_b[b][pr];
+                if (!SKIP || ((nd >> b) & 1u)) {
+                    v[b] = psi_b[b][(uint64_t)r_psi + ent];
+                    r[b] = sepd_b[b][pr];
+                } else {
+                    v[b] = T(0);
+                    r[b] = T(0);
+                }
             }
 #pragma unroll
             for (int b = 0; b < B; b++)
@@ -1009,13 +1083,11 @@ __global__ __launch_bounds__(kBlock) void k_marginals(Ctx c, const int32_t* __re
     const double* marg = c.marg + (uint64_t)slot * c.marg_stride;
     double* post = c.post + (uint64_t)slot * c.marg_stride;
     {
-        const float* accf = static_cast<const float*>(c.acc) + (uint64_t)slot * c.sep_stride;
-        const double* accd = static_cast<const double*>(c.acc) + (uint64_t)slot * c.sep_stride;
         const int32_t* kexp = c.kexp + (uint64_t)slot * c.kexp_stride;
         double lg = 0.0;
         long long ks = 0;
         for (uint32_t r = threadIdx.x; r < c.nroots; r += kBlock) {
-            const double z = c.fp32 ? (double)accf[c.sep_total + r] : accd[c.sep_total + r];
+            const double z = c.rsum[(uint64_t)slot * c.nroots + r];
             lg += z > 0.0 ? log(z) : -INFINITY;
         }
         for (int e = threadIdx.x; e < c.ne; e += kBlock) ks += kexp[e];
@@ -1086,16 +1158,24 @@ template <typename T, int B>
 void launch_collect_b(const Ctx& c, const DGroup* groups, uint32_t ngroups, const int32_t* slots, int nslots,
                       hipStream_t s) {
     const uint64_t total = (uint64_t)ngroups * (uint64_t)((nslots + B - 1) / B);
-    hipLaunchKernelGGL((k_collect<T, B>), dim3((unsigned)total), dim3(kBlock), 0, s, c, groups, ngroups, slots,
-                       nslots);
+    if (c.dense)
+        hipLaunchKernelGGL((k_collect<T, B, false>), dim3((unsigned)total), dim3(kBlock), 0, s, c, groups, ngroups,
+                           slots, nslots);
+    else
+        hipLaunchKernelGGL((k_collect<T, B, true>), dim3((unsigned)total), dim3(kBlock), 0, s, c, groups, ngroups,
+                           slots, nslots);
 }
 
 template <typename T, int B>
 void launch_gather_b(const Ctx& c, const DWork* works, uint32_t nworks, const int32_t* slots, int nslots,
                      hipStream_t s) {
     const uint64_t total = (uint64_t)nworks * (uint64_t)((nslots + B - 1) / B);
-    hipLaunchKernelGGL((k_dist_gather<T, B>), dim3((unsigned)total), dim3(kBlock), 0, s, c, works, nworks, slots,
-                       nslots);
+    if (c.dense)
+        hipLaunchKernelGGL((k_dist_gather<T, B, false>), dim3((unsigned)total), dim3(kBlock), 0, s, c, works, nworks,
+                           slots, nslots);
+    else
+        hipLaunchKernelGGL((k_dist_gather<T, B, true>), dim3((unsigned)total), dim3(kBlock), 0, s, c, works, nworks,
+                           slots, nslots);
 }
 
 template <typename T>

@@ -162,7 +162,11 @@ __device__ __forceinline__ void collect_piece_i(const Ctx& c, const DPiece& pc, 
                     acc += (double)v[x];
                     if (--seg_left == 0) {
                         if (partial) part += acc;
-                        else if (act) accp<T>(c)[(uint64_t)out * S + s] = acc;
+                        else if (act) {
+                            accp<T>(c)[(uint64_t)out * S + s] = acc;
+                            // a root's sum (its tree's share of P(e)) also kept unrounded
+                            if (out >= c.sep_total) c.rsum[(uint64_t)(out - c.sep_total) * S + s] = acc;
+                        }
                         acc = 0.0;
                         out++;
                         seg_left = q.seg;
@@ -513,7 +517,10 @@ __device__ __forceinline__ void fin_collect_small_i(const Ctx& c, const DSepFin*
     // the whole separator (at most kBigSeparatorInterleaved entries) in registers
     double v[kBigSeparatorInterleaved];
     double mx = 0.0;
-    finish_block_i<T>(f, c, S, s, 0u, f.size, v, [&](uint32_t, double w) { mx = fmax(mx, w); });
+    finish_block_i<T>(f, c, S, s, 0u, f.size, v, [&](uint32_t, double w) {
+        mx = fmax(mx, w);
+        if (f.edge < 0 && f.nchunk) c.rsum[(uint64_t)(f.sep - c.sep_total) * S + s] = w;
+    });
     if (f.edge < 0) {
         if (!(v[0] > 0.0)) atomicOr(&c.flags[s], c.fp32 ? 2 : 1);
         return;
@@ -795,8 +802,7 @@ __global__ __launch_bounds__(kBlock) void k_marginals_i(Ctx c, const int32_t* __
     if (wi != 0) return;
     double lg = 0.0;
     for (uint32_t r = 0; r < c.nroots; r++) {
-        const uint64_t zi = (uint64_t)(c.sep_total + r) * S + s;
-        const double z = c.fp32 ? (double)static_cast<const float*>(c.acc)[zi] : static_cast<const double*>(c.acc)[zi];
+        const double z = c.rsum[(uint64_t)r * S + s];
         lg += z > 0.0 ? log(z) : -INFINITY;
     }
     const long long ks = c.kexp[(uint64_t)c.ne * S + s];  // summed by the collect finalisers

@@ -75,13 +75,39 @@ class ServeResult:
         return float(np.percentile(self.latency, q))
 
 
+def admission_plan(handles, tiles, budget_bytes: int, max_batch: int, layout: int = 0,
+                   shrink_evidence: bool = False) -> dict:
+    """Device-memory plan of a server (host only, no device needed): the fixed
+    bytes of every tree (plan, maps, prior), one FP64 fallback tree (the
+    largest), then as many evidence slots per tree as the rest of the budget
+    holds, at most max_batch.  Footprints come from host-only builds, which
+    report exactly what a device build allocates.  MemoryError when not even
+    one slot per tree fits."""
+    fixed, slot, fb = [], [], []
+    for h, t in zip(handles, tiles):
+        a = fbn.JT(h, host_only=True, precision=fbn.FBN_FP32_RESCALED, max_slots=1, tile_entries=t,
+                   layout=layout, shrink_evidence=shrink_evidence)
+        fixed.append(a.stats["device_bytes"] - a.stats["slot_bytes"])
+        slot.append(a.stats["slot_bytes"])
+        b = fbn.JT(h, host_only=True, precision=fbn.FBN_FP64, max_slots=1, tile_entries=t)
+        fb.append(b.stats["device_bytes"])
+    reserve = max(fb)
+    avail = budget_bytes - sum(fixed) - reserve
+    if avail < sum(slot):
+        raise MemoryError(f"budget {budget_bytes} B cannot hold every network with one slot "
+                          f"(needs {sum(fixed) + reserve + sum(slot)} B)")
+    slots = int(min(max_batch, avail // sum(slot)))
+    return {"slots": slots, "fixed_bytes": fixed, "slot_bytes": slot, "fallback_reserve": reserve,
+            "planned_bytes": sum(fixed) + reserve + slots * sum(slot)}
+
+
 class Server:
     """Resident FP32 junction trees for `nets` (objects with .flat() and
     .card), one stream each, sized by `budget_bytes`."""
 
     def __init__(self, nets, budget_bytes: int = 32 << 30, max_batch: int = 32, depth: int = 2,
-                 graph: bool = True, tile: int | None = 0, warm: bool = True, layout: int = 0,
-                 tile_candidates=(0, 2048)):
+                 graph: bool = True, tile=0, warm: bool = True, layout: int = 0,
+                 tile_candidates=(0, 2048), shrink_evidence: bool = False):
         import torch
         self._torch = torch
         self.nets = list(nets)
@@ -89,9 +115,14 @@ class Server:
         self.layout = layout
         self.depth = max(1, depth)
         handles = [fbn.net_from_spec(n) for n in self.nets]
-        # tile per tree: fixed, or (tile=None) the fastest of tile_candidates
-        # for a full batch of max_batch cases, timed on the device
-        if tile is None:
+        # tile per tree: fixed (one for all, or a list with one per tree), or
+        # (tile=None) the fastest of tile_candidates for a full batch of
+        # max_batch cases, timed on the device
+        if isinstance(tile, (list, tuple)):
+            if len(tile) != len(self.nets):
+                raise ValueError("one tile per network")
+            self.tiles = [int(t) for t in tile]
+        elif tile is None:
             from . import tune
             empty = (np.zeros(0, np.int32), np.zeros(0, np.int32))
             self.tiles = [int(tune.tune(n, [empty] * max_batch, fbn.FBN_FP32_RESCALED, max_batch,
@@ -100,27 +131,16 @@ class Server:
         else:
             self.tiles = [int(tile)] * len(self.nets)
         self.tile = self.tiles[0]
-        fixed, slot, fb = [], [], []
-        for h, t in zip(handles, self.tiles):
-            a = fbn.JT(h, host_only=True, precision=fbn.FBN_FP32_RESCALED, max_slots=1, tile_entries=t,
-                       layout=layout)
-            fixed.append(a.stats["device_bytes"] - a.stats["slot_bytes"])
-            slot.append(a.stats["slot_bytes"])
-            b = fbn.JT(h, host_only=True, precision=fbn.FBN_FP64, max_slots=1, tile_entries=t)
-            fb.append(b.stats["device_bytes"])
-        self.fallback_reserve = max(fb)
-        avail = budget_bytes - sum(fixed) - self.fallback_reserve
-        if avail < sum(slot):
-            raise MemoryError(f"budget {budget_bytes} B cannot hold every network with one slot "
-                              f"(needs {sum(fixed) + self.fallback_reserve + sum(slot)} B)")
-        self.slots = int(min(max_batch, avail // sum(slot)))
-        self.planned_bytes = sum(fixed) + self.fallback_reserve + self.slots * sum(slot)
+        plan = admission_plan(handles, self.tiles, budget_bytes, max_batch, layout, shrink_evidence)
+        self.slots = plan["slots"]
+        self.fallback_reserve = plan["fallback_reserve"]
+        self.planned_bytes = plan["planned_bytes"]
         self.budget_bytes = budget_bytes
         self.streams = [torch.cuda.Stream() for _ in self.nets]
         self.jts = []
         for h, s, t in zip(handles, self.streams, self.tiles):
             jt = fbn.JT(h, precision=fbn.FBN_FP32_RESCALED, max_slots=self.slots, tile_entries=t,
-                        stream=s.cuda_stream, layout=layout)
+                        stream=s.cuda_stream, layout=layout, shrink_evidence=shrink_evidence)
             if graph:
                 fbn.set_graph_mode(jt, True)
             self.jts.append(jt)
@@ -158,11 +178,37 @@ class Server:
                                     tile_entries=self.tiles[net]))
         return self._fb[1]
 
+    # ---- device actions of the loop (the scheduling in run() is device-free)
+    def _launch(self, k: int, slots, qs, buf: int):
+        """Evidence, calibration and an asynchronous read-back of one batch of
+        tree k into pinned buffer `buf`; returns the batch's completion event."""
+        jt = self.jts[k]
+        m = len(slots)
+        fbn.set_evidence_batch(jt, slots, [(q.vars, q.states) for q in qs])
+        fbn.calibrate(jt, slots)
+        post, lp, fl = self._bufs[k][buf]
+        fbn.fetch_async(jt, slots, post[:m], lp[:m], fl[:m])
+        ev = self._torch.cuda.Event()
+        ev.record(self.streams[k])
+        return ev
+
+    def _ready(self, k: int, token) -> bool:
+        return token.query()
+
+    def _results(self, k: int, buf: int):
+        return self._bufs[k][buf]
+
     def run(self, queries, rate: float | None = None, keep=None) -> ServeResult:
         """Serve `queries` in arrival order.  rate=None: closed loop (every query
         has arrived at t=0); else arrivals at t_arrive / rate seconds.  `keep`:
-        query ids whose posteriors are kept in the result."""
-        torch = self._torch
+        query ids whose posteriors are kept in the result.
+
+        Policy: each network keeps its waiting queries in arrival order (FIFO).
+        Every pass visits the trees in turn; a tree first retires its finished
+        batches (oldest first), then, if it has waiting queries, a free slot and
+        a free result buffer (at most `depth` batches in flight), takes the
+        oldest waiting queries up to its free slots as one batch.  No tree
+        waits on another, so no network starves."""
         n = len(queries)
         order = sorted(range(n), key=lambda i: queries[i].t_arrive)
         arr = np.array([0.0 if rate is None else queries[i].t_arrive / rate for i in range(n)])
@@ -191,8 +237,9 @@ class Server:
             busy = False
             for k in range(K):
                 # retire finished batches of tree k, oldest first
-                while inflight[k] and inflight[k][0].event.query():
+                while inflight[k] and self._ready(k, inflight[k][0].event):
                     b = inflight[k].popleft()
+                    b.post, b.logpe, b.flags = self._results(k, b.buf)
                     tnow = time.perf_counter() - t0
                     for r, i in enumerate(b.qids):
                         fl = int(b.flags[r])
@@ -220,15 +267,9 @@ class Server:
                     m = min(len(pending[k]), len(free[k]))
                     qids = [pending[k].popleft() for _ in range(m)]
                     slots = [free[k].pop() for _ in range(m)]
-                    jt = self.jts[k]
-                    fbn.set_evidence_batch(jt, slots, [(queries[i].vars, queries[i].states) for i in qids])
-                    fbn.calibrate(jt, slots)
                     bi = freebuf[k].pop()
-                    post, lp, fl = self._bufs[k][bi]
-                    fbn.fetch_async(jt, slots, post[:m], lp[:m], fl[:m])
-                    ev = torch.cuda.Event()
-                    ev.record(self.streams[k])
-                    inflight[k].append(_Batch(qids, slots, post, lp, fl, ev, bi))
+                    ev = self._launch(k, slots, [queries[i] for i in qids], bi)
+                    inflight[k].append(_Batch(qids, slots, None, None, None, ev, bi))
                     batches += 1
                     busy = True
             if not busy and nxt < n and not any(inflight):
