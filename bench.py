@@ -66,7 +66,7 @@ KIND_KERNEL_IL = {"collect": "k_collect_i", "collect_finalise": "k_fin_collect_i
                   "distribute_finalise": "k_fin_distribute_i", "posteriors": "k_marginals_i"}
 
 
-def counted_traffic(workload, kernel, layout, tile):
+def counted_traffic(workload, kernel, layout, tile, tiles=None):
     """HBM bytes per launch of the dominant kernel from the committed
     FETCH_SIZE / WRITE_SIZE summary (copy-scaled), or None when there is no
     summary for this workload and kernel, it was taken with another layout or
@@ -84,13 +84,15 @@ def counted_traffic(workload, kernel, layout, tile):
         return None
     if kv.get("layout") != str(int(layout)) or kv.get("tile") != str(int(tile)):
         return None
+    if "tiles" in kv and (tiles is None or kv["tiles"] != ",".join(str(int(t)) for t in tiles)):
+        return None
     try:
         return float(kv["traffic_bytes_per_launch"])
     except (KeyError, ValueError):
         return None
 
 
-def roofline_of(prof, workload, layout, tile, note=None, interleaved=False):
+def roofline_of(prof, workload, layout, tile, note=None, interleaved=False, tiles=None):
     """Roofline object for the kernel kind with the most time in `prof`
     (kind -> (ms, launches, algorithmic bytes)), measured by HIP events."""
     kind = max(prof, key=lambda k: prof[k][0])
@@ -98,7 +100,7 @@ def roofline_of(prof, workload, layout, tile, note=None, interleaved=False):
     achieved = byts / (ms * 1e-3) / 1e9 if ms > 0 else 0.0
     kernel = (KIND_KERNEL_IL if interleaved else KIND_KERNEL)[kind]
     r = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-         "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": counted_traffic(workload, kernel, layout, tile),
+         "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": counted_traffic(workload, kernel, layout, tile, tiles),
          "kernel": f"{kernel}<float>", "launches": launches,
          "avg_launch_us": round(1e3 * ms / max(launches, 1), 3),
          "bytes_per_launch": byts / max(launches, 1),
@@ -418,7 +420,7 @@ def bench_served(args, fbn):
             copy_calibration()
         roofline = roofline_of({k: tuple(v) for k, v in prof.items()}, "C5", args.layout, args.tile,
                                "one full batch per resident tree, eager launches, HIP events",
-                               interleaved=args.layout == 2)
+                               interleaved=args.layout == 2, tiles=srv.tiles)
         print(json.dumps({"workload": "C5", "tiles": srv.tiles, "roofline": roofline,
                           "kernel_ms_one_batch_per_tree": {k: v[0] for k, v in prof.items()},
                           "kernel_launches": {k: v[1] for k, v in prof.items()}}), flush=True)
@@ -481,7 +483,7 @@ def bench_served(args, fbn):
 
     roofline = roofline_of({k: tuple(v) for k, v in prof.items()}, "C5", args.layout, args.tile,
                            "one full batch per resident tree, eager launches, HIP events",
-                           interleaved=args.layout == 2)
+                           interleaved=args.layout == 2, tiles=srv_tiles)
     roofline["stream_copy_GBps"] = round(copy_gbps(), 1)
 
     def lat(r):
