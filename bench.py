@@ -248,7 +248,7 @@ def time_batched(fbn, W, precision, steps, warmup, profile, layout=0, tile=0, ev
     return jt, dt, (prof, kinds), post, lp, st
 
 
-def time_plain(fbn, W, n_queries, graph=True):
+def time_plain(fbn, W, n_queries, graph=True, precision=None):
     """One query per calibration on the query's own network, waiting for
     each result (a per-query engine); with graph, the layer sequence is
     replayed as one captured graph.  Returns q/s, latencies and, per
@@ -261,7 +261,8 @@ def time_plain(fbn, W, n_queries, graph=True):
     lat, res, dt = [], {}, 0.0
     for j, idx in groups.items():
         net = W.nets[j]
-        jt = fbn.JT(fbn.net_from_spec(net), precision=fbn.FBN_FP64, max_slots=len(idx), stream=stream.cuda_stream)
+        jt = fbn.JT(fbn.net_from_spec(net), precision=fbn.FBN_FP64 if precision is None else precision,
+                    max_slots=len(idx), stream=stream.cuda_stream)
         if graph:
             fbn.set_graph_mode(jt, True)
         slots = list(range(len(idx)))
@@ -296,6 +297,22 @@ def time_with_host_io(fbn, W, precision, steps, layout=0, tile=0):
         fbn.calibrate(jt, slots)
         fbn.query_all(jt, slots, marg)
     return n * W.per_slot * steps / (time.perf_counter() - t0)
+
+
+def oracle_one_core(ojts, pairs, cases_of, limit_s=10.0):
+    """The oracle on one host core: median seconds per query over `pairs`
+    ((network, case) keys), run one after another, stopping after limit_s."""
+    times = []
+    t_end = time.perf_counter() + limit_s
+    for j, i in pairs:
+        a = time.perf_counter()
+        ojts[j].query(*cases_of(j, i))
+        times.append(time.perf_counter() - a)
+        if time.perf_counter() > t_end:
+            break
+    med = float(np.median(times))
+    return {"median_ms_per_query": round(1e3 * med, 3), "queries_per_s_one_core": round(1.0 / med, 2),
+            "queries_timed": len(times)}
 
 
 def cpu_baseline(W, seconds):
@@ -552,6 +569,8 @@ def bench_served(args, fbn):
         out["cpu_baseline"] = {"value": done / dt, "unit": "queries/s", "cores": threads, "kind": "oracle",
                                "sample": f"{done} oracle queries over the first {len(sample)} trace queries, "
                                          f"{dt:.1f} s, {threads} threads (one query per thread at a time)"}
+        out["cpu_baseline"]["one_core"] = oracle_one_core(
+            ojts, [(queries[i].net, i) for i in sample], lambda j, i: (queries[i].vars, queries[i].states))
         e32 = e64 = l32 = l64 = 0.0
         for i, (olp, op) in results.items():
             e32 = max(e32, float(np.max(np.abs(sat.post[i] - op))))
@@ -663,6 +682,8 @@ def main():
     log(f"[bench] fp64 plain (graph replay): {qps_plain:.1f} q/s, p50 {1e3 * np.median(lat):.3f} ms")
     qps_plain_eager, lat_e, _ = time_plain(fbn, W, args.plain_queries, graph=False)
     log(f"[bench] fp64 plain (eager launches): {qps_plain_eager:.1f} q/s")
+    qps_plain32, lat32, _ = time_plain(fbn, W, args.plain_queries, precision=fbn.FBN_FP32_RESCALED)
+    log(f"[bench] fp32 plain (graph replay): {qps_plain32:.1f} q/s, p50 {1e3 * np.median(lat32):.3f} ms")
     qps_io = time_with_host_io(fbn, W, fbn.FBN_FP32_RESCALED, max(1, args.steps // 4), args.layout, args.tile)
     log(f"[bench] fp32 batched with host i/o: {qps_io:.1f} q/s")
 
@@ -701,12 +722,17 @@ def main():
                                      "queries": int(len(lat)), "launch": "hipGraph replay",
                                      "eager_queries_per_s": round(qps_plain_eager, 1),
                                      "eager_p50_ms": round(1e3 * float(np.median(lat_e)), 4)},
+            "fp32_plain_per_query": {"queries_per_s": round(qps_plain32, 1),
+                                     "p50_ms": round(1e3 * float(np.median(lat32)), 4),
+                                     "p99_ms": round(1e3 * float(np.percentile(lat32, 99)), 4),
+                                     "queries": int(len(lat32)), "launch": "hipGraph replay"},
             "fp32_batched_with_host_io": {"queries_per_s": round(qps_io, 1)},
             "fp32_vs_fp64_plain": round(qps32 / qps_plain, 2),
         },
     }
     if not args.no_cpu_baseline:
         cb, ojts = cpu_baseline(W, args.cpu_seconds)
+        cb["one_core"] = oracle_one_core(ojts, W.sample(20 if len(W.nets) == 1 else 64), lambda j, i: W.cases[j][i])
         out["cpu_baseline"] = cb
         pairs = W.sample(20 if len(W.nets) == 1 else 64)
         forest = len(W.nets) > 1

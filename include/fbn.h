@@ -100,6 +100,17 @@ typedef struct {
                                    * evidence; 0 (default) streams every
                                    * entry, the zeroed ones included.
                                    * Results are bitwise the same.            */
+    int32_t fp64_rerun;           /* FP32 trees: 1 recomputes a slot whose
+                                   * FP32 messages vanished (FBN_E_UNDERFLOW)
+                                   * on a one-slot FP64 tree of the same
+                                   * network, built on first need, inside
+                                   * fbn_calibrate (when it reports results),
+                                   * fbn_query_all / _marginals and
+                                   * fbn_query_joint; that slot's results are
+                                   * then the FP64 ones and its status is the
+                                   * FP64 status.  fbn_fetch_async still
+                                   * reports the raw flags.  0: no rerun.     */
+    int32_t reserved;
 } fbn_jt_options;
 
 typedef struct {
@@ -210,7 +221,8 @@ fbn_status fbn_query_all(fbn_jt* jt, int32_t n_slots, const int32_t* slots, doub
 /* Asynchronous form of fbn_query_all: enqueues the copies on the jt's stream
  * into caller-owned host memory (pinned for true overlap); the caller must
  * synchronise that stream before reading.  per_slot receives raw flags: 0 ok,
- * 1 zero evidence, 2 FP32 underflow. */
+ * bit 0 zero evidence, bit 1 FP32 underflow, bit 2 results recomputed in FP64
+ * (fp64_rerun). */
 fbn_status fbn_fetch_async(fbn_jt* jt, int32_t n_slots, const int32_t* slots, double* post_out,
                            double* log_pe_out, int32_t* flags_out);
 

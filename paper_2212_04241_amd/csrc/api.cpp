@@ -228,6 +228,8 @@ struct fbn_jt {
     bool h_pinned = false;
     std::vector<char> dirty;
     std::vector<int32_t> staged_slots;  // the slot list now in d_slots
+    std::vector<std::vector<std::pair<int32_t, int32_t>>> evidence;  // per slot: (variable, state)
+    fbn_jt* twin = nullptr;             // FP32 with fp64_rerun: one-slot FP64 tree of the same network
     hipEvent_t staged = nullptr;
     bool staged_pending = false;
     // evidence lookup: for each variable, the (clique, layout position) pairs
@@ -560,6 +562,62 @@ fbn_status fetch(fbn_jt* jt, int32_t n, double* post, double* logpe, int32_t* fl
 }  // namespace
 
 static fbn_status enqueue_calibration(fbn_jt* jt, int32_t n);
+static fbn_status finish_build(fbn_jt* jt, fbn_jt** out);
+
+// FP32 trees built with fp64_rerun: the slots whose FP32 messages vanished
+// (flag bit 1) are recomputed on a one-slot FP64 tree of the same network,
+// built on first need, and the FP64 posteriors, log P(e) and flags replace
+// the FP32 ones in this tree's per-slot arrays.  flags[i] (raw flags of
+// slots[i]) is updated; log_pe[i] too when log_pe is given.
+static fbn_status rerun_fp64(fbn_jt* jt, int32_t n, const int32_t* slots, int32_t* flags, double* log_pe) {
+    if (!jt->opt.fp64_rerun || jt->opt.precision != FBN_FP32_RESCALED) return FBN_OK;
+    for (int32_t i = 0; i < n; i++) {
+        if (!(flags[i] & 2)) continue;
+        if (!jt->twin) {
+            auto* tw = new fbn_jt();
+            tw->opt = jt->opt;
+            tw->opt.precision = FBN_FP64;
+            tw->opt.max_slots = 1;
+            tw->opt.layout = FBN_LAYOUT_PER_SLOT;
+            tw->opt.shrink_evidence = 0;
+            tw->opt.fp64_rerun = 0;
+            tw->opt.host_only = 0;
+            tw->opt.stream = jt->stream;
+            tw->tree = jt->tree;
+            fbn_status st = finish_build(tw, &jt->twin);
+            if (st) return st;
+        }
+        fbn_jt* tw = jt->twin;
+        const auto& el = jt->evidence[(size_t)slots[i]];
+        std::vector<int32_t> vs, ss;
+        for (const auto& e : el) {
+            vs.push_back(e.first);
+            ss.push_back(e.second);
+        }
+        fbn_status st = fbn_set_evidence(tw, 0, (int32_t)vs.size(), vs.data(), ss.data());
+        if (st) return st;
+        const int32_t zero = 0;
+        if ((st = fbn_calibrate(tw, 1, &zero, nullptr, nullptr))) return st;
+        const size_t m = jt->ctx.marg_stride;
+        const size_t sl = (size_t)slots[i];
+        HIP_OK(hipMemcpyAsync(jt->d_post + sl * m, tw->d_post, 8 * m, hipMemcpyDeviceToDevice, jt->stream));
+        HIP_OK(hipMemcpyAsync(jt->d_logpe + sl, tw->d_logpe, 8, hipMemcpyDeviceToDevice, jt->stream));
+        HIP_OK(hipMemcpyAsync(jt->d_flags + sl, tw->d_flags, 4, hipMemcpyDeviceToDevice, jt->stream));
+        double lp = 0.0;
+        int32_t f = 0;
+        HIP_OK(hipMemcpyAsync(&lp, tw->d_logpe, 8, hipMemcpyDeviceToHost, jt->stream));
+        HIP_OK(hipMemcpyAsync(&f, tw->d_flags, 4, hipMemcpyDeviceToHost, jt->stream));
+        HIP_OK(hipStreamSynchronize(jt->stream));
+        // bit 2 marks the slot's results as recomputed in FP64: its FP32
+        // tables are not valid, and readers of the tables go to the twin
+        const int32_t marked = f | 4;
+        HIP_OK(hipMemcpyAsync(jt->d_flags + sl, &marked, 4, hipMemcpyHostToDevice, jt->stream));
+        HIP_OK(hipStreamSynchronize(jt->stream));
+        flags[i] = f;
+        if (log_pe) log_pe[i] = lp;
+    }
+    return FBN_OK;
+}
 
 // ====================================================================== ABI
 
@@ -737,6 +795,8 @@ fbn_status fbn_net_cpt(const fbn_net* net, int32_t v, int32_t* card, int32_t* pa
     return FBN_OK;
 }
 
+static fbn_status finish_build(fbn_jt* jt, fbn_jt** out);
+
 static fbn_status build_jt_impl(const std::vector<const fbn_net*>& nets, const fbn_jt_options* opt_in, fbn_jt** out) {
     *out = nullptr;
     fbn_jt_options opt;
@@ -776,6 +836,28 @@ static fbn_status build_jt_impl(const std::vector<const fbn_net*>& nets, const f
             }
             jt->tree = merge_forest(parts);
         }
+        return finish_build(jt, out);
+    } catch (const std::bad_alloc&) {
+        if (jt) {
+            release(jt);
+            delete jt;
+        }
+        return fail(FBN_E_NOMEM_HOST, "out of host memory");
+    } catch (const std::exception& e) {
+        if (jt) {
+            release(jt);
+            delete jt;
+        }
+        return fail(FBN_E_TOO_LARGE, e.what());
+    }
+}
+
+// The rest of a build once jt->tree holds the compiled tree and jt->opt the
+// options: plan, per-layer counts, evidence lookup, device state.  Frees jt
+// and returns the error on failure.
+static fbn_status finish_build(fbn_jt* jt, fbn_jt** out) {
+    const fbn_jt_options& opt = jt->opt;
+    try {
         // default tile: 8 KB of table per slot, so four slots share a workgroup
         // interleaved: one wave per work item, 64 entries each by default
         const bool il = opt.layout == FBN_LAYOUT_INTERLEAVED;
@@ -809,6 +891,7 @@ static fbn_status build_jt_impl(const std::vector<const fbn_net*>& nets, const f
             for (size_t k = 0; k < jt->tree.vars[(size_t)c].size(); k++)
                 jt->occ[(size_t)jt->tree.vars[(size_t)c][k]].push_back({c, (int)k});
         jt->dirty.assign((size_t)opt.max_slots, 0);
+        jt->evidence.assign((size_t)opt.max_slots, {});
         jt->live_coll.assign((size_t)opt.max_slots * jt->coll_entries.size(), 0);
         jt->live_dist.assign((size_t)opt.max_slots * jt->dist_entries.size(), 0);
         for (int32_t s = 0; s < opt.max_slots; s++) {
@@ -832,16 +915,12 @@ static fbn_status build_jt_impl(const std::vector<const fbn_net*>& nets, const f
         *out = jt;
         return FBN_OK;
     } catch (const std::bad_alloc&) {
-        if (jt) {
-            release(jt);
-            delete jt;
-        }
+        release(jt);
+        delete jt;
         return fail(FBN_E_NOMEM_HOST, "out of host memory");
     } catch (const std::exception& e) {
-        if (jt) {
-            release(jt);
-            delete jt;
-        }
+        release(jt);
+        delete jt;
         return fail(FBN_E_TOO_LARGE, e.what());
     }
 }
@@ -864,6 +943,7 @@ fbn_status fbn_build_forest(const fbn_net* const* nets, int32_t n_nets, const fb
 
 void fbn_free_jt(fbn_jt* jt) {
     if (!jt) return;
+    if (jt->twin) fbn_free_jt(jt->twin);
     release(jt);
     delete jt;
 }
@@ -879,6 +959,7 @@ fbn_status fbn_set_stream(fbn_jt* jt, void* stream) {
     jt->stream = static_cast<hipStream_t>(stream);
     jt->opt.stream = stream;
     if (!jt->stream) jt->use_graph = false;
+    if (jt->twin) return fbn_set_stream(jt->twin, stream);
     return FBN_OK;
 }
 
@@ -912,6 +993,9 @@ fbn_status fbn_set_evidence(fbn_jt* jt, int32_t slot, int32_t n_obs, const int32
         }
     }
     jt->dirty[(size_t)slot] = 1;
+    auto& el = jt->evidence[(size_t)slot];
+    el.clear();
+    for (int32_t k = 0; k < n_obs; k++) el.push_back({vars[k], states[k]});
     // live entries per layer (shrinking reduction only, for the kernel
     // timing's byte counts): a clique holding observed variables keeps
     // |C| / prod(their cardinalities) entries
@@ -986,6 +1070,7 @@ fbn_status fbn_calibrate(fbn_jt* jt, int32_t n, const int32_t* slots, double* lo
         std::vector<int32_t> fl((size_t)n);
         if ((st = fetch(jt, n, nullptr, lp.data(), fl.data()))) return st;
         HIP_OK(hipStreamSynchronize(jt->stream));
+        if ((st = rerun_fp64(jt, n, slots, fl.data(), lp.data()))) return st;
         for (int32_t i = 0; i < n; i++) {
             if (log_pe) log_pe[i] = lp[(size_t)i];
             if (per_slot) per_slot[i] = status_of_flag(fl[(size_t)i]);
@@ -1144,6 +1229,14 @@ fbn_status fbn_query_all(fbn_jt* jt, int32_t n, const int32_t* slots, double* ou
     std::vector<int32_t> fl((size_t)n);
     if ((st = fetch(jt, n, out, lp.data(), fl.data()))) return st;
     HIP_OK(hipStreamSynchronize(jt->stream));
+    bool rerun = false;
+    for (int32_t i = 0; i < n; i++) rerun = rerun || (fl[(size_t)i] & 2);
+    if (rerun && jt->opt.fp64_rerun && jt->opt.precision == FBN_FP32_RESCALED) {
+        if ((st = rerun_fp64(jt, n, slots, fl.data(), lp.data()))) return st;
+        if ((st = slots_for_fetch(jt, n, slots))) return st;
+        if ((st = fetch(jt, n, out, nullptr, nullptr))) return st;
+        HIP_OK(hipStreamSynchronize(jt->stream));
+    }
     for (int32_t i = 0; i < n; i++) {
         if (log_pe) log_pe[i] = lp[(size_t)i];
         if (per_slot) per_slot[i] = status_of_flag(fl[(size_t)i]);
@@ -1294,9 +1387,26 @@ fbn_status fbn_query_joint(fbn_jt* jt, int32_t slot, int32_t n_q, const int32_t*
     if (st) return st;
     HIP_OK(hipSetDevice(jt->device));
     if ((st = wait_staged(jt))) return st;
+    // a slot whose FP32 tables vanished (flag 2), or whose results were
+    // recomputed in FP64 (flag 4), is read from the FP64 tree recalibrated
+    // for its evidence when the jt reruns underflows in FP64
+    int32_t f0 = 0;
+    HIP_OK(hipMemcpyAsync(&f0, jt->d_flags + slot, 4, hipMemcpyDeviceToHost, jt->stream));
+    HIP_OK(hipStreamSynchronize(jt->stream));
+    const bool twin = jt->opt.fp64_rerun && jt->opt.precision == FBN_FP32_RESCALED && (f0 & 6);
+    if (twin) {
+        int32_t f = 2;
+        if ((st = rerun_fp64(jt, 1, &slot, &f, nullptr))) return st;
+    }
     void* dev = temp_alloc(jt, 8 * joint_scratch_doubles(a));
     if (!dev) return fail(FBN_E_NOMEM_DEVICE, "device allocation failed");
-    st = joint_run(jt, home, a, static_cast<double*>(dev), out);
+    if (twin) {
+        JointArgs b = a;
+        b.slot = 0;
+        st = joint_run(jt->twin, home, b, static_cast<double*>(dev), out);
+    } else {
+        st = joint_run(jt, home, a, static_cast<double*>(dev), out);
+    }
     const std::string keep = g_err;
     hipStreamSynchronize(jt->stream);
     temp_free(jt, dev);

@@ -40,6 +40,12 @@ namespace {
 constexpr int kWave = 64;
 constexpr int kWaves = kBlock / kWave;
 constexpr int kMaxKids = 8;  // child maps held in registers; more use a loop
+// loads kept in flight per thread: collect entries x slots x children, the
+// distribute stage's entries, and the summed entries per lane of an output
+constexpr int kCollectLoads = 32;
+constexpr int kCollectMaxU = 4;
+constexpr uint32_t kStageEntries = 8;
+constexpr uint32_t kOutEntries = 4;
 
 __device__ __forceinline__ uint32_t mdiv(uint32_t n, uint32_t mul, uint32_t sh) {
     return (uint32_t)(((uint64_t)__umulhi(n, mul) + n) >> sh);
@@ -194,7 +200,8 @@ __device__ __forceinline__ void collect_run(const Ctx& c, uint32_t total, uint32
                                             const uint32_t (&kml)[kMaxKids], T* const (&psi_b)[B],
                                             const T* const (&sepc_b)[B], T* vals) {
     constexpr int NW = NC > 0 ? NC : 1;
-    constexpr int U = B * NW <= 8 ? 4 : (B * NW <= 16 ? 2 : 1);
+    constexpr int U0 = kCollectLoads / (B * NW);
+    constexpr int U = U0 >= kCollectMaxU ? kCollectMaxU : (U0 >= 2 ? 2 : 1);
     for (uint32_t g0 = threadIdx.x; g0 < total; g0 += U * kBlock) {
         EntryC<T, B> e[U];
 #pragma unroll
@@ -686,7 +693,7 @@ __global__ __launch_bounds__(kBlock) void k_dist_gather(Ctx c, const DWork* __re
         // slot's psi and ratio loads issued together; a slot whose evidence
         // zeroes an entry reads nothing for it (its psi there was never
         // written), unless tables are streamed whole
-        constexpr uint32_t U = 4;
+        constexpr uint32_t U = kStageEntries;
         const bool ratio = q.pedge >= 0;
         DEvidence ev[B];
         uint64_t anyev = 0;
@@ -835,10 +842,10 @@ __global__ __launch_bounds__(kBlock) void k_dist_gather(Ctx c, const DWork* __re
             const uint32_t lp = map[t2.lp + t];
             const uint32_t per = nk * t2.nQL;
             // four entries per lane at a time: their map lookups issued together
-            for (uint32_t j0 = sub; j0 < per; j0 += 4 * tpo) {
-                uint32_t idx[4];
+            for (uint32_t j0 = sub; j0 < per; j0 += kOutEntries * tpo) {
+                uint32_t idx[kOutEntries];
 #pragma unroll
-                for (uint32_t y = 0; y < 4; y++) {
+                for (uint32_t y = 0; y < kOutEntries; y++) {
                     const uint32_t j = min(j0 + y * tpo, per - 1);
                     const uint32_t k = mdiv(j, t2.qlmul, t2.qlsh);
                     const uint32_t u = j - k * t2.nQL;
@@ -846,7 +853,7 @@ __global__ __launch_bounds__(kBlock) void k_dist_gather(Ctx c, const DWork* __re
                     idx[y] = gofs + row * L + lp + map[t2.lq + u];
                 }
 #pragma unroll
-                for (uint32_t y = 0; y < 4; y++) {
+                for (uint32_t y = 0; y < kOutEntries; y++) {
                     if (j0 + y * tpo < per) {
 #pragma unroll
                         for (int b = 0; b < B; b++) s[b] += (double)vals[b * c.tile + idx[y]];
