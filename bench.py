@@ -120,7 +120,7 @@ class Workload:
         import fbngen
         self.key = key
         cfg = fbngen.CONFIGS[key]
-        if key == "C4":
+        if key in ("C4", "C4G"):
             self.nets = [fbngen.make_net(key, j) for j in range(cfg.n_nets)]
             self.cases = [fbngen.make_cases(key, n, j) for j, n in enumerate(self.nets)]
             off = fbngen.forest_offsets(self.nets)
@@ -423,7 +423,11 @@ def bench_served(args, fbn):
     t0 = time.perf_counter()
     # tile per tree: --tiles, else --tile for all, else the tuner's pick for a
     # full batch of each tree
-    tiles = [int(x) for x in args.tiles.split(",")] if args.tiles else (args.tile or None)
+    if args.tiles and args.tiles != "auto":
+        tl = [int(x) for x in args.tiles.split(",")]
+        tiles = tl * len(nets) if len(tl) == 1 else tl
+    else:
+        tiles = args.tile or None
     srv = Server(nets, budget_bytes=int(args.budget_gb * (1 << 30)), max_batch=args.max_batch,
                  tile=tiles, layout=args.layout, warm=not args.kernels_only)
     server_s = time.perf_counter() - t0
@@ -606,8 +610,9 @@ def main():
     ap.add_argument("--trace", type=int, default=4096, help="C5: trace queries")
     ap.add_argument("--budget-gb", type=float, default=32.0, help="C5: device-memory budget, GiB")
     ap.add_argument("--max-batch", type=int, default=32, help="C5: slots per resident tree at most")
-    ap.add_argument("--tiles", default="",
-                    help="C5: comma-separated tile per tree (default: tuned on the device)")
+    ap.add_argument("--tiles", default="2048",
+                    help="C5: tile per tree, one value for all or comma-separated per tree; 'auto' times "
+                         "the candidates on the device (it picks 2048 for all or all but one of the trees)")
     ap.add_argument("--kernels-only", action="store_true",
                     help="C5: only the profiled full batch per resident tree (for counter runs)")
     ap.add_argument("--no-shrink-compare", action="store_true",

@@ -226,6 +226,13 @@ CONFIGS = {
     "C4": Config("C4", 4, 256, 64, 1.0, 32_768, None,
                  "256 networks of U[50,500] variables, cards {2..6}, <=3 parents from the previous 30, "
                  "Dirichlet(1); 64 cases each observing 4% of the variables"),
+    # C4 drawn by rejection alone under the 4e6-entry guard: each network is
+    # the first of its seeded draws whose largest clique fits, with every
+    # drawn arc kept (no repair)
+    "C4G": Config("C4G", 4, 256, 64, 1.0, 4_000_000, None,
+                  "256 networks of U[50,500] variables, cards {2..6}, <=3 parents from the previous 30, "
+                  "Dirichlet(1), each the first seeded draw whose largest clique is <= 4e6 entries (no arcs "
+                  "dropped); 64 cases each observing 4% of the variables"),
     "C5": Config("C5", 5, 8, 4096, 1.0, 4_000_000, None,
                  "8 networks of U[400,1000] variables, cards {2..21}, <=3 parents from the previous 50, "
                  "Dirichlet(1); Poisson arrivals, each query picks a network and observes 2-20%"),
@@ -277,7 +284,7 @@ def make_structure(key: str, j: int = 0, attempt: int = 0, card_mode: str = "uni
             w = 1.0 / rs
             card_pos = r_card.choice(rs, size=n, p=w / w.sum())
         card_pos[0] = 63
-    elif key == "C4":
+    elif key in ("C4", "C4G"):
         n = int(r_dag.integers(50, 501))
         par_pos = random_dag(r_dag, n, 3, 30)
         card_pos = r_card.integers(2, 7, size=n)
@@ -329,7 +336,7 @@ def _n_observed(key: str, n: int, rng: np.random.Generator | None = None) -> int
         return max(1, int(np.floor(0.05 * n + 0.5)))
     if key == "C3":
         return 10
-    if key == "C4":
+    if key in ("C4", "C4G"):
         return max(1, int(np.floor(0.04 * n + 0.5)))
     if key == "C5":
         f = float(rng.uniform(0.02, 0.20))

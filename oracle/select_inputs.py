@@ -7,6 +7,8 @@ Acceptance rules (clique sizes are min-fill elimination cliques, in entries):
   C2  largest clique in [1e4, 1e6] (the stated range); first attempt.
   C3  largest clique in [5e6, 2e7]; up to 1000 attempts with cardinalities
       uniform on {2..63}, then attempts with P(r) proportional to 1/r.
+  C4G  largest clique <= 4e6 (the memory guard proposed for the batch):
+      first attempt that meets it, every drawn arc kept; up to 1000 attempts.
   C4, C5  largest clique <= 32768 (C4: the batch of small networks) and
       <= 4e6 (C5).  A few attempts by rejection, then a
       deterministic repair of attempt 0: while min-fill meets a clique above
@@ -94,6 +96,11 @@ def _repair_job(args):
     return j, select_repair(key, j, cap, 3)
 
 
+def _rejection_job(args):
+    key, j, cap = args
+    return j, select_range(key, j, None, cap, ["uniform"], 1000)
+
+
 def main(keys):
     data = {}
     if os.path.exists(OUT):
@@ -103,11 +110,12 @@ def main(keys):
         cfg = fbngen.CONFIGS[key]
         t0 = time.time()
         res = {}
-        if key == "C4":
+        if key in ("C4", "C4G"):
             # many independent networks: one process per core
             from multiprocessing import Pool
+            job = _repair_job if key == "C4" else _rejection_job
             with Pool(max(1, min(7, (os.cpu_count() or 2) - 1))) as pool:
-                for j, r in pool.imap_unordered(_repair_job, [(key, j, cfg.cap) for j in range(cfg.n_nets)]):
+                for j, r in pool.imap_unordered(job, [(key, j, cfg.cap) for j in range(cfg.n_nets)]):
                     res[str(j)] = r
                     print(key, j, {k: v for k, v in r.items() if k != "drop"}, f"{time.time() - t0:.1f}s", flush=True)
             data[key] = {k: res[k] for k in sorted(res, key=int)}

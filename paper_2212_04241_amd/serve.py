@@ -107,7 +107,7 @@ class Server:
 
     def __init__(self, nets, budget_bytes: int = 32 << 30, max_batch: int = 32, depth: int = 2,
                  graph: bool = True, tile=0, warm: bool = True, layout: int = 0,
-                 tile_candidates=(0, 2048), shrink_evidence: bool = False):
+                 tile_candidates=(0, 2048, 4096), shrink_evidence: bool = False):
         import torch
         self._torch = torch
         self.nets = list(nets)

@@ -79,11 +79,14 @@ def measure_on_device(nets, cases, precision, max_slots, layout, tile, reps=5) -
 
 
 def tune(nets, cases, precision: int = fbn.FBN_FP32_RESCALED, max_slots: int | None = None,
-         candidates=None, reps: int = 5, cache: str | None = None, measure=None) -> dict:
+         candidates=None, reps: int = 5, cache: str | None = None, measure=None, tolerance: float = 0.02) -> dict:
     """Best (layout, tile) for calibrating `cases` on the tree of `nets` (one
     network or a list, as for fbn.JT).  Returns {"layout", "tile", "ms",
-    "trials": [[layout, tile, ms], ...], "cached": bool}.  `measure` replaces
-    the device timing (same signature as measure_on_device)."""
+    "trials": [[layout, tile, ms], ...], "cached": bool}.  A candidate replaces
+    an earlier one only when faster by more than `tolerance` (a fraction), so
+    that timing noise between near-equal candidates does not flip the choice
+    from run to run.  `measure` replaces the device timing (same signature as
+    measure_on_device)."""
     cache = cache if cache is not None else os.environ.get("FBN_TUNE_CACHE")
     max_slots = max_slots or len(cases)
     key = network_key(nets, precision, max_slots, len(cases))
@@ -100,7 +103,10 @@ def tune(nets, cases, precision: int = fbn.FBN_FP32_RESCALED, max_slots: int | N
         trials.append([int(layout), int(tile), ms])
     if not trials:
         raise RuntimeError("no candidate configuration could be built")
-    best = min(trials, key=lambda t: t[2])
+    best = trials[0]
+    for t in trials[1:]:
+        if t[2] < best[2] * (1.0 - tolerance):
+            best = t
     out = {"layout": best[0], "tile": best[1], "ms": best[2], "trials": trials}
     if cache:
         data = _load(cache)

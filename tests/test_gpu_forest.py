@@ -127,3 +127,22 @@ def test_forest_c4_full_batch_fp32_graph(layout, tile):
     say("worst fp32 abs error", worst)
     del jt
     torch.cuda.synchronize()
+
+
+@pytest.mark.timeout(600)
+def test_forest_c4g_unrepaired_draws_fp32():
+    # networks drawn by rejection under the 4e6-entry guard, every drawn arc
+    # kept: the first 16 as one forest, FP32 interleaved at tile 256 (the
+    # bench's configuration for this batch); posteriors of four networks and
+    # log P(e) of two slots against the oracle
+    nets = [fbngen.make_net("C4G", j) for j in range(16)]
+    cases = [fbngen.make_cases("C4G", n, j, n_cases=8) for j, n in enumerate(nets)]
+    off = fbngen.forest_offsets(nets)
+    say("forest C4G fp32, 16 networks x 8 cases, T", sum(oracle.compile_net(n, structure_only=True).T for n in nets))
+    jt = fbn.JT([fbn.net_from_spec(n) for n in nets], precision=fbn.FBN_FP32_RESCALED, max_slots=8,
+                layout=fbn.FBN_LAYOUT_INTERLEAVED, tile_entries=256)
+    ids = list(range(8))
+    post, lp, st = _run(jt, nets, cases, off, ids, ids)
+    worst = _check(nets, cases, post, lp, st, ids, [0, 3, 9, 15], [0, 5], fp32=True)
+    say("worst fp32 abs error", worst)
+    jt.free()

@@ -202,3 +202,27 @@ def test_second_batch_of_a_tree_is_enqueued_while_the_first_runs():
             assert np.array_equal(buf[0][r], post[0]) and buf[1][r] == lp[0], k
         one.free()
     jt.free()
+
+
+@pytest.mark.timeout(900)
+def test_served_fp32_matches_oracle_on_200_trace_queries(c5):
+    """The served FP32 path (default server, tuned tiles) against the oracle
+    on the first 200 queries of the arrival trace, every posterior entry."""
+    from concurrent.futures import ThreadPoolExecutor
+    nets, queries = c5
+    srv = Server(nets, budget_bytes=32 << 30, max_batch=32, tile=None)
+    res = srv.run(queries, None, keep=range(len(queries)))
+    srv.close()
+    assert np.all(res.status == 0)
+    ojts = {}
+    with ThreadPoolExecutor(8) as ex:
+        for k, o in zip(range(8), ex.map(lambda k: oracle.compile_net(nets[k]), range(8))):
+            ojts[k] = o
+        ref = list(ex.map(lambda q: ojts[q.net].query(q.vars, q.states), queries))
+    worst = 0.0
+    for i, (olp, opost) in enumerate(ref):
+        e = float(np.max(np.abs(res.post[i] - opost)))
+        worst = max(worst, e)
+        assert e <= FP32_ATOL, (i, e)
+        assert abs(res.log_pe[i] - olp) <= FP32_LOGPE_ATOL * max(1.0, abs(olp)), i
+    say("served fp32 worst abs error over", len(ref), "queries:", worst)
