@@ -840,23 +840,49 @@ __global__ __launch_bounds__(kBlock) void k_dist_gather(Ctx c, const DWork* __re
                 m = map[t2.tb + w.g0 + g] + map[t2.tv + t];
             }
             const uint32_t lp = map[t2.lp + t];
-            const uint32_t per = nk * t2.nQL;
-            // four entries per lane at a time: their map lookups issued together
-            for (uint32_t j0 = sub; j0 < per; j0 += kOutEntries * tpo) {
-                uint32_t idx[kOutEntries];
+            const uint32_t nQL = t2.nQL;
+            // The output's entries are rows k < nk by low offsets u < nQL.  With
+            // at least tpo offsets, lane sub takes offsets sub, sub + tpo, ...
+            // over every row; with fewer, lane sub takes offset sub % nQL and
+            // rows sub / nQL, + q, ... (q = tpo / nQL; lanes past q * nQL idle).
+            // Each offset's index is loaded once and the rows are stepped by
+            // adding L, kOutEntries rows at a time.
+            uint32_t u0 = sub, ustep = tpo, k0 = 0, kstep = 1;
+            if (nQL < tpo) {
+                const uint32_t qq = tpo / nQL;
+                u0 = sub % nQL;
+                ustep = nQL;
+                k0 = sub < qq * nQL ? sub / nQL : nk;
+                kstep = qq;
+            }
+            const uint32_t rg = packed ? map[t2.rg + g] : 0u;
+            for (uint32_t u = u0; u < nQL; u += ustep) {
+                const uint32_t off = gofs + lp + map[t2.lq + u];
+                if (packed) {
+                    for (uint32_t k = k0; k < nk; k += kstep) {
+                        const uint32_t idx = off + (rg + map[t2.rq + k]) * L;
 #pragma unroll
-                for (uint32_t y = 0; y < kOutEntries; y++) {
-                    const uint32_t j = min(j0 + y * tpo, per - 1);
-                    const uint32_t k = mdiv(j, t2.qlmul, t2.qlsh);
-                    const uint32_t u = j - k * t2.nQL;
-                    const uint32_t row = packed ? map[t2.rg + g] + map[t2.rq + k] : rowbase + k;
-                    idx[y] = gofs + row * L + lp + map[t2.lq + u];
-                }
+                        for (int b = 0; b < B; b++) s[b] += (double)vals[b * c.tile + idx];
+                    }
+                } else {
+                    const uint32_t step = kstep * L;
+                    uint32_t idx = off + (rowbase + k0) * L;
+                    uint32_t k = k0;
+                    for (; k + (kOutEntries - 1) * kstep < nk; k += kOutEntries * kstep) {
+                        T x[kOutEntries][B];
 #pragma unroll
-                for (uint32_t y = 0; y < kOutEntries; y++) {
-                    if (j0 + y * tpo < per) {
+                        for (uint32_t y = 0; y < kOutEntries; y++)
 #pragma unroll
-                        for (int b = 0; b < B; b++) s[b] += (double)vals[b * c.tile + idx[y]];
+                            for (int b = 0; b < B; b++) x[y][b] = vals[b * c.tile + idx + y * step];
+#pragma unroll
+                        for (uint32_t y = 0; y < kOutEntries; y++)
+#pragma unroll
+                            for (int b = 0; b < B; b++) s[b] += (double)x[y][b];
+                        idx += kOutEntries * step;
+                    }
+                    for (; k < nk; k += kstep, idx += step) {
+#pragma unroll
+                        for (int b = 0; b < B; b++) s[b] += (double)vals[b * c.tile + idx];
                     }
                 }
             }
