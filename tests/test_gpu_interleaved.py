@@ -195,7 +195,8 @@ def test_tuner_choice_keeps_parity(tmp_path):
     say("tuner on C2")
     r = tune.tune(net, cases, cache=str(tmp_path / "t.json"),
                   candidates=[(tune.PER_SLOT, 0), (tune.PER_SLOT, 2048), (tune.INTERLEAVED, 128)])
-    assert len(r["trials"]) == 3 and r["ms"] == min(t[2] for t in r["trials"])
+    # the choice is within the tuner's 2% tolerance of the fastest trial
+    assert len(r["trials"]) == 3 and r["ms"] <= min(t[2] for t in r["trials"]) * 1.02 + 1e-12
     ref, _ = oracle_run(net, cases[:8])
     post, lp, st, _ = gpu_run(net, cases[:8], precision=fbn.FBN_FP32_RESCALED, tile=r["tile"], layout=r["layout"])
     check_fp32(post, lp, st, ref, "tuned")
