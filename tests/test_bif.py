@@ -113,3 +113,57 @@ def test_bif_rejects_malformed(text, code, words):
         fbn.load_net_mem(text)
     assert ei.value.code == code
     assert words in str(ei.value), str(ei.value)
+
+
+def _to_bif(net, rng, names):
+    """BIF text of a generated network, written independently of the reader:
+    parent rows in a shuffled order, some written through a default row,
+    decimal values that read back exactly (shortest round-trip form)."""
+    out = ["// written by the test", 'network "t" {', "}"]
+    order = rng.permutation(net.n)          # declarations in any order
+    for v in order:
+        st = ", ".join(f"s{v}_{x}" for x in range(int(net.card[v])))
+        out.append(f"variable {names[v]} {{\n  type discrete [ {int(net.card[v])} ] {{ {st} }};\n}}")
+    for v in rng.permutation(net.n):
+        r = int(net.card[v])
+        cpt = np.asarray(net.cpt[v], dtype=np.float64).reshape(-1, r)
+        par = net.parents[v]
+        if not par:
+            out.append(f"probability ( {names[v]} ) {{\n  table " + ", ".join(repr(float(x)) for x in cpt[0]) + ";\n}")
+            continue
+        lines = [f"probability ( {names[v]} | " + ", ".join(names[p] for p in par) + " ) {"]
+        rows = list(range(cpt.shape[0]))
+        default_row = rows[int(rng.integers(0, len(rows)))] if len(rows) > 1 and rng.random() < 0.5 else None
+        for row in rng.permutation(rows):
+            if default_row is not None and np.array_equal(cpt[row], cpt[default_row]) and row != default_row:
+                continue
+            if row == default_row:
+                continue
+            digs, x = [], int(row)
+            for p in reversed(par):
+                digs.append(x % int(net.card[p]))
+                x //= int(net.card[p])
+            digs = digs[::-1]
+            lines.append("  (" + ", ".join(f"s{p}_{d}" for p, d in zip(par, digs)) + ") " +
+                         ", ".join(repr(float(y)) for y in cpt[row]) + ";")
+        if default_row is not None:
+            lines.append("  default " + ", ".join(repr(float(y)) for y in cpt[default_row]) + ";")
+        lines.append("}")
+        out.append("\n".join(lines))
+    return "\n".join(out) + "\n"
+
+
+@pytest.mark.parametrize("seed", range(12))
+def test_bif_round_trip_of_generated_networks(seed):
+    net = fbngen.random_small_net(500 + seed, 12, max_card=4, p_max=3, window=5)
+    rng = np.random.default_rng(seed)
+    names = [f"v{seed}x{v}" for v in range(net.n)]
+    text = _to_bif(net, rng, names)
+    got = fbn.load_net_mem(text)
+    assert fbn.net_n_vars(got) == net.n
+    for v in range(net.n):
+        k = fbn.net_find_var(got, names[v])
+        card, par, cpt = fbn.net_cpt(got, k)
+        assert card == int(net.card[v])
+        assert [fbn.net_var_name(got, p) for p in par] == [names[p] for p in net.parents[v]]
+        assert np.array_equal(cpt, np.asarray(net.cpt[v], dtype=np.float64).ravel()), v
