@@ -862,7 +862,7 @@ static fbn_status finish_build(fbn_jt* jt, fbn_jt** out) {
         // interleaved: one wave per work item, 64 entries each by default
         const bool il = opt.layout == FBN_LAYOUT_INTERLEAVED;
         const int def_tile = il ? 64 : (opt.precision == FBN_FP32_RESCALED ? 1024 : 512);
-        const uint32_t max_stage = (uint32_t)kStageBytes / (opt.precision == FBN_FP32_RESCALED ? 4u : 8u);
+        const uint32_t max_stage = (uint32_t)kSlotStageBytes / (opt.precision == FBN_FP32_RESCALED ? 4u : 8u);
         build_plan(jt->tree, opt.tile_entries ? opt.tile_entries : def_tile, max_stage, jt->plan, il);
         const std::string bad = check_plan(jt->tree, jt->plan);
         if (!bad.empty()) {
@@ -1185,7 +1185,7 @@ static fbn_status enqueue_calibration(fbn_jt* jt, int32_t n) {
         const Layer& ly = p.collect[h];
         // reads the prior, writes the working table
         if ((st = timed(jt, 0, 2.0 * w * ent_c[h], [&] {
-                 return launch_collect(c, prec, jt->d_groups + ly.group0, ly.ngroup, jt->d_slots, n, s);
+                 return launch_collect(c, prec, jt->d_groups + ly.group0, ly.ngroup, ly.stage, jt->d_slots, n, s);
              })))
             return st;
         if ((st = finalise(ly, false, 1, 2.0 * w * nb * (double)jt->coll_sep[h]))) return st;
@@ -1194,7 +1194,7 @@ static fbn_status enqueue_calibration(fbn_jt* jt, int32_t n) {
         const Layer& ly = p.distribute[d];
         // reads the working table
         if ((st = timed(jt, 2, w * ent_d[d], [&] {
-                 return launch_distribute(c, prec, jt->d_works + ly.group0, ly.ngroup, jt->d_slots, n, s);
+                 return launch_distribute(c, prec, jt->d_works + ly.group0, ly.ngroup, ly.stage, jt->d_slots, n, s);
              })))
             return st;
         if ((st = finalise(ly, true, 3, 2.0 * w * nb * (double)jt->dist_sep[d]))) return st;

@@ -47,17 +47,31 @@ struct Ctx {
                            // the shrink_evidence option
 };
 
-// Bytes of LDS a layer workgroup stages; slots per workgroup times tile
-// times the entry width must fit.
-constexpr int kStageBytes = 16384;
-// Slots one workgroup carries for a tile of `tile` entries of width w.
-inline int slots_per_block(uint32_t tile, int w) {
+// Bytes of LDS one slot's tile may take: plans keep every collect group and
+// distribute work item of the per-slot layout within it.
+constexpr int kSlotStageBytes = 16384;
+// Bytes of LDS a layer workgroup stages at most; slots per workgroup times
+// the layer's stage times the entry width must fit.  Twice one slot's bound,
+// so that the largest tiles still share a workgroup between slots.
+constexpr int kStageBytes = 32768;
+// Workgroups (one per compute unit) below which a layer launch trades shared
+// index arithmetic for parallel slots: fewer slots per workgroup, more
+// workgroups.
+constexpr uint64_t kFillGrid = 256;
+// Slots one workgroup carries for a stage of `tile` entries of width w, over
+// `items` work items and `nslots` slots.
+inline int slots_per_block(uint32_t tile, int w, uint64_t items, int nslots) {
+    if (nslots < 4) return 1;
     int b = kStageBytes / (int)(tile * (uint32_t)w);
-    return b >= 8 ? 8 : (b >= 4 ? 4 : (b >= 2 ? 2 : 1));
+    b = b >= 8 && nslots >= 8 ? 8 : (b >= 4 ? 4 : (b >= 2 ? 2 : 1));
+    while (b > 1 && items * (uint64_t)((nslots + b - 1) / b) < kFillGrid) b /= 2;
+    return b;
 }
 
 // prec: 0 = float64 tables, 1 = float32 tables
-hipError_t launch_collect(const Ctx& c, int prec, const DGroup* groups, uint32_t ngroups,
+// stage: LDS entries per slot of the layer's largest group (collect) or work
+// item (distribute); the launch sizes its LDS and slots per workgroup from it.
+hipError_t launch_collect(const Ctx& c, int prec, const DGroup* groups, uint32_t ngroups, uint32_t stage,
                           const int32_t* slots, int nslots, hipStream_t s);
 // A layer's finalisers, first launch: the nsmall small separators `sfins`
 // (the first nbig of them a workgroup each, the rest a wave each) and the
@@ -70,7 +84,7 @@ hipError_t launch_fin_collect(const Ctx& c, int prec, const DSepFin* sfins, uint
 // (distribute = false) or distribute sweep.
 hipError_t launch_fin_blocks(const Ctx& c, int prec, bool distribute, const DSepFin* fins, const DFinBlk* blks,
                              uint32_t nblks, const int32_t* slots, int nslots, hipStream_t s);
-hipError_t launch_distribute(const Ctx& c, int prec, const DWork* works, uint32_t nworks,
+hipError_t launch_distribute(const Ctx& c, int prec, const DWork* works, uint32_t nworks, uint32_t stage,
                              const int32_t* slots, int nslots, hipStream_t s);
 hipError_t launch_fin_distribute(const Ctx& c, int prec, const DSepFin* sfins, uint32_t nsmall, uint32_t nbig,
                                  const DSepFin* fins, const DFinBlk* blks, uint32_t nblks, const int32_t* slots,

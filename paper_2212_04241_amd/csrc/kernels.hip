@@ -226,7 +226,7 @@ __device__ __forceinline__ void collect_run(const Ctx& c, uint32_t total, uint32
 template <typename T, int B, bool SKIP>
 __global__ __launch_bounds__(kBlock) void k_collect(Ctx c, const DGroup* __restrict__ groups, uint32_t ngroups,
                                                     const int32_t* __restrict__ slots, int nslots) {
-    __shared__ __align__(16) unsigned char stage[kStageBytes];
+    extern __shared__ __align__(16) unsigned char stage[];  // B * c.tile entries, sized at launch
     __shared__ RunC runs[kMaxPieces];
     __shared__ KidC kids[kMaxPieces][kMaxKids];
     __shared__ DEvidence evs[kMaxPieces][B];
@@ -631,7 +631,7 @@ struct TgtD {
 template <typename T, int B, bool SKIP>
 __global__ __launch_bounds__(kBlock) void k_dist_gather(Ctx c, const DWork* __restrict__ works, uint32_t nworks,
                                                         const int32_t* __restrict__ slots, int nslots) {
-    __shared__ __align__(16) unsigned char stage[kStageBytes];
+    extern __shared__ __align__(16) unsigned char stage[];  // B * c.tile entries, sized at launch
     __shared__ RunD runs[kMaxPieces];
     __shared__ TgtD tgts[kMaxPieces];
     __shared__ DEvidence evs[SKIP ? kMaxPieces : 1][B];
@@ -1187,15 +1187,18 @@ __global__ void k_zero(uint32_t* __restrict__ p, size_t words) {
         p[k] = 0u;
 }
 
+// The per-slot layer kernels stage B slots of c.tile entries each in LDS
+// allocated at launch; c.tile is the layer's stage.
 template <typename T, int B>
 void launch_collect_b(const Ctx& c, const DGroup* groups, uint32_t ngroups, const int32_t* slots, int nslots,
                       hipStream_t s) {
     const uint64_t total = (uint64_t)ngroups * (uint64_t)((nslots + B - 1) / B);
+    const size_t lds = (size_t)B * c.tile * sizeof(T);
     if (c.dense)
-        hipLaunchKernelGGL((k_collect<T, B, false>), dim3((unsigned)total), dim3(kBlock), 0, s, c, groups, ngroups,
+        hipLaunchKernelGGL((k_collect<T, B, false>), dim3((unsigned)total), dim3(kBlock), lds, s, c, groups, ngroups,
                            slots, nslots);
     else
-        hipLaunchKernelGGL((k_collect<T, B, true>), dim3((unsigned)total), dim3(kBlock), 0, s, c, groups, ngroups,
+        hipLaunchKernelGGL((k_collect<T, B, true>), dim3((unsigned)total), dim3(kBlock), lds, s, c, groups, ngroups,
                            slots, nslots);
 }
 
@@ -1203,20 +1206,21 @@ template <typename T, int B>
 void launch_gather_b(const Ctx& c, const DWork* works, uint32_t nworks, const int32_t* slots, int nslots,
                      hipStream_t s) {
     const uint64_t total = (uint64_t)nworks * (uint64_t)((nslots + B - 1) / B);
+    const size_t lds = (size_t)B * c.tile * sizeof(T);
     if (c.dense)
-        hipLaunchKernelGGL((k_dist_gather<T, B, false>), dim3((unsigned)total), dim3(kBlock), 0, s, c, works, nworks,
-                           slots, nslots);
+        hipLaunchKernelGGL((k_dist_gather<T, B, false>), dim3((unsigned)total), dim3(kBlock), lds, s, c, works,
+                           nworks, slots, nslots);
     else
-        hipLaunchKernelGGL((k_dist_gather<T, B, true>), dim3((unsigned)total), dim3(kBlock), 0, s, c, works, nworks,
-                           slots, nslots);
+        hipLaunchKernelGGL((k_dist_gather<T, B, true>), dim3((unsigned)total), dim3(kBlock), lds, s, c, works,
+                           nworks, slots, nslots);
 }
 
 template <typename T>
 void launch_collect_t(const Ctx& c, const DGroup* groups, uint32_t ngroups, const int32_t* slots, int nslots,
                       hipStream_t s) {
-    const int B = nslots >= 4 ? slots_per_block(c.tile, sizeof(T)) : 1;
-    if (B >= 8 && nslots >= 8) launch_collect_b<T, 8>(c, groups, ngroups, slots, nslots, s);
-    else if (B >= 4) launch_collect_b<T, 4>(c, groups, ngroups, slots, nslots, s);
+    const int B = slots_per_block(c.tile, sizeof(T), ngroups, nslots);
+    if (B == 8) launch_collect_b<T, 8>(c, groups, ngroups, slots, nslots, s);
+    else if (B == 4) launch_collect_b<T, 4>(c, groups, ngroups, slots, nslots, s);
     else if (B == 2) launch_collect_b<T, 2>(c, groups, ngroups, slots, nslots, s);
     else launch_collect_b<T, 1>(c, groups, ngroups, slots, nslots, s);
 }
@@ -1224,9 +1228,9 @@ void launch_collect_t(const Ctx& c, const DGroup* groups, uint32_t ngroups, cons
 template <typename T>
 void launch_gather_t(const Ctx& c, const DWork* works, uint32_t nworks, const int32_t* slots, int nslots,
                      hipStream_t s) {
-    const int B = nslots >= 4 ? slots_per_block(c.tile, sizeof(T)) : 1;
-    if (B >= 8 && nslots >= 8) launch_gather_b<T, 8>(c, works, nworks, slots, nslots, s);
-    else if (B >= 4) launch_gather_b<T, 4>(c, works, nworks, slots, nslots, s);
+    const int B = slots_per_block(c.tile, sizeof(T), nworks, nslots);
+    if (B == 8) launch_gather_b<T, 8>(c, works, nworks, slots, nslots, s);
+    else if (B == 4) launch_gather_b<T, 4>(c, works, nworks, slots, nslots, s);
     else if (B == 2) launch_gather_b<T, 2>(c, works, nworks, slots, nslots, s);
     else launch_gather_b<T, 1>(c, works, nworks, slots, nslots, s);
 }
@@ -1255,11 +1259,14 @@ __global__ __launch_bounds__(kBlock) void k_fin_distribute(Ctx c, const DSepFin*
 
 }  // namespace
 
-hipError_t launch_collect(const Ctx& c, int prec, const DGroup* groups, uint32_t ngroups, const int32_t* slots,
-                          int nslots, hipStream_t s) {
+hipError_t launch_collect(const Ctx& c, int prec, const DGroup* groups, uint32_t ngroups, uint32_t stage,
+                          const int32_t* slots, int nslots, hipStream_t s) {
     if (!ngroups || !nslots) return hipSuccess;
-    if (prec) launch_collect_t<float>(c, groups, ngroups, slots, nslots, s);
-    else launch_collect_t<double>(c, groups, ngroups, slots, nslots, s);
+    if (stage == 0 || stage * (prec ? 4u : 8u) > (uint32_t)kSlotStageBytes) return hipErrorInvalidValue;
+    Ctx cl = c;
+    cl.tile = stage;
+    if (prec) launch_collect_t<float>(cl, groups, ngroups, slots, nslots, s);
+    else launch_collect_t<double>(cl, groups, ngroups, slots, nslots, s);
     return hipGetLastError();
 }
 
@@ -1292,11 +1299,14 @@ hipError_t launch_fin_blocks(const Ctx& c, int prec, bool distribute, const DSep
     return hipGetLastError();
 }
 
-hipError_t launch_distribute(const Ctx& c, int prec, const DWork* works, uint32_t nworks, const int32_t* slots,
-                             int nslots, hipStream_t s) {
+hipError_t launch_distribute(const Ctx& c, int prec, const DWork* works, uint32_t nworks, uint32_t stage,
+                             const int32_t* slots, int nslots, hipStream_t s) {
     if (!nworks || !nslots) return hipSuccess;
-    if (prec) launch_gather_t<float>(c, works, nworks, slots, nslots, s);
-    else launch_gather_t<double>(c, works, nworks, slots, nslots, s);
+    if (stage == 0 || stage * (prec ? 4u : 8u) > (uint32_t)kSlotStageBytes) return hipErrorInvalidValue;
+    Ctx cl = c;
+    cl.tile = stage;
+    if (prec) launch_gather_t<float>(cl, works, nworks, slots, nslots, s);
+    else launch_gather_t<double>(cl, works, nworks, slots, nslots, s);
     return hipGetLastError();
 }
 

@@ -40,6 +40,11 @@ static uint32_t bits_for(int r) {
     return b;
 }
 
+// Table entries one distribute work item stages per slot.
+static uint32_t work_entries(const Plan& p, const DWork& w) {
+    return w.npiece ? w.total : w.ng * w.nk * p.cliques[p.targets[w.target].clique].L;
+}
+
 static uint32_t mdiv_host(uint32_t n, uint32_t mul, uint32_t sh) {
     return (uint32_t)(((uint64_t)(((uint64_t)n * mul) >> 32) + n) >> sh);
 }
@@ -332,9 +337,17 @@ std::string check_plan(const Tree& t, const Plan& p) {
     if (p.stage == 0 || p.stage > (uint32_t)kTileMax || p.stage > p.max_stage) return "stage size";
     for (const DGroup& g : p.groups)
         if (g.total > p.stage) return "group exceeds stage";
-    for (const DWork& w : p.works) {
-        const uint32_t n = w.npiece ? w.total : w.ng * w.nk * p.cliques[p.targets[w.target].clique].L;
-        if (n > p.stage) return "work exceeds stage";
+    for (const DWork& w : p.works)
+        if (work_entries(p, w) > p.stage) return "work exceeds stage";
+    for (const Layer& ly : p.collect) {
+        if (ly.stage == 0 || ly.stage > p.stage) return "collect layer stage";
+        for (uint32_t k = ly.group0; k < ly.group0 + ly.ngroup; k++)
+            if (p.groups[k].total > ly.stage) return "group exceeds its layer's stage";
+    }
+    for (const Layer& ly : p.distribute) {
+        if (ly.stage == 0 || ly.stage > p.stage) return "distribute layer stage";
+        for (uint32_t k = ly.group0; k < ly.group0 + ly.ngroup; k++)
+            if (work_entries(p, p.works[k]) > ly.stage) return "work exceeds its layer's stage";
     }
     return "";
 }
@@ -775,9 +788,19 @@ void build_plan(const Tree& t, int tile, uint32_t max_stage, Plan& p, bool inter
     p.psi_total = po;
     p.stage = (uint32_t)tile;
     for (const DGroup& g : p.groups) p.stage = std::max(p.stage, g.total);
-    for (const DWork& w : p.works) {
-        const uint32_t n = w.npiece ? w.total : w.ng * w.nk * p.cliques[p.targets[w.target].clique].L;
-        p.stage = std::max(p.stage, n);
+    for (const DWork& w : p.works) p.stage = std::max(p.stage, work_entries(p, w));
+    // a layer stages only what its largest item needs, so layers of small
+    // cliques carry more slots per workgroup in less LDS
+    for (Layer& ly : p.collect) {
+        ly.stage = 64;
+        for (uint32_t k = ly.group0; k < ly.group0 + ly.ngroup; k++) ly.stage = std::max(ly.stage, p.groups[k].total);
+        ly.stage = std::min(ly.stage, p.stage);
+    }
+    for (Layer& ly : p.distribute) {
+        ly.stage = 64;
+        for (uint32_t k = ly.group0; k < ly.group0 + ly.ngroup; k++)
+            ly.stage = std::max(ly.stage, work_entries(p, p.works[k]));
+        ly.stage = std::min(ly.stage, p.stage);
     }
 }
 

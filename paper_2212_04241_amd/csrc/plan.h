@@ -12,6 +12,7 @@ struct Layer {
     uint32_t nbig = 0;                // the first nbig fins are large: split over Plan::finblks
     uint32_t fb0 = 0, nfb = 0;        // their blocks, into Plan::finblks
     uint32_t nteam = 0;               // the next nteam fins get a workgroup each, the rest a wave
+    uint32_t stage = 0;               // per-slot layout: LDS entries per slot of its largest group / work item
 };
 
 constexpr uint32_t kBigSeparator = 1024;  // entries above which a separator is split into blocks
