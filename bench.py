@@ -66,11 +66,12 @@ KIND_KERNEL_IL = {"collect": "k_collect_i", "collect_finalise": "k_fin_collect_i
                   "distribute_finalise": "k_fin_distribute_i", "posteriors": "k_marginals_i"}
 
 
-def counted_traffic(workload, kernel, layout, tile, tiles=None):
+def counted_traffic(workload, kernel, layout, tile, tiles=None, slots=None):
     """HBM bytes per launch of the dominant kernel from the committed
     FETCH_SIZE / WRITE_SIZE summary (copy-scaled), or None when there is no
-    summary for this workload and kernel, it was taken with another layout or
-    tile, or the kernel sources changed since the counters were taken."""
+    summary for this workload and kernel, it was taken with another layout,
+    tile or slot count, or the kernel sources changed since the counters were
+    taken."""
     path = os.path.join(PROFILES, f"{kernel}_{workload}_counters.txt")
     if not os.path.exists(path):
         return None
@@ -86,13 +87,15 @@ def counted_traffic(workload, kernel, layout, tile, tiles=None):
         return None
     if "tiles" in kv and (tiles is None or kv["tiles"] != ",".join(str(int(t)) for t in tiles)):
         return None
+    if "slots" in kv and (slots is None or kv["slots"] != str(int(slots))):
+        return None
     try:
         return float(kv["traffic_bytes_per_launch"])
     except (KeyError, ValueError):
         return None
 
 
-def roofline_of(prof, workload, layout, tile, note=None, interleaved=False, tiles=None):
+def roofline_of(prof, workload, layout, tile, note=None, interleaved=False, tiles=None, slots=None):
     """Roofline object for the kernel kind with the most time in `prof`
     (kind -> (ms, launches, algorithmic bytes)), measured by HIP events."""
     kind = max(prof, key=lambda k: prof[k][0])
@@ -100,7 +103,7 @@ def roofline_of(prof, workload, layout, tile, note=None, interleaved=False, tile
     achieved = byts / (ms * 1e-3) / 1e9 if ms > 0 else 0.0
     kernel = (KIND_KERNEL_IL if interleaved else KIND_KERNEL)[kind]
     r = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-         "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": counted_traffic(workload, kernel, layout, tile, tiles),
+         "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": counted_traffic(workload, kernel, layout, tile, tiles, slots),
          "kernel": f"{kernel}<float>", "launches": launches,
          "avg_launch_us": round(1e3 * ms / max(launches, 1), 3),
          "bytes_per_launch": byts / max(launches, 1),
@@ -441,7 +444,7 @@ def bench_served(args, fbn):
             copy_calibration()
         roofline = roofline_of({k: tuple(v) for k, v in prof.items()}, "C5", args.layout, args.tile,
                                "one full batch per resident tree, eager launches, HIP events",
-                               interleaved=args.layout == 2, tiles=srv.tiles)
+                               interleaved=args.layout == 2, tiles=srv.tiles, slots=srv.slots)
         print(json.dumps({"workload": "C5", "tiles": srv.tiles, "roofline": roofline,
                           "kernel_ms_one_batch_per_tree": {k: v[0] for k, v in prof.items()},
                           "kernel_launches": {k: v[1] for k, v in prof.items()}}), flush=True)
@@ -504,7 +507,7 @@ def bench_served(args, fbn):
 
     roofline = roofline_of({k: tuple(v) for k, v in prof.items()}, "C5", args.layout, args.tile,
                            "one full batch per resident tree, eager launches, HIP events",
-                           interleaved=args.layout == 2, tiles=srv_tiles)
+                           interleaved=args.layout == 2, tiles=srv_tiles, slots=slots)
     roofline["stream_copy_GBps"] = round(copy_gbps(), 1)
 
     def lat(r):
@@ -608,8 +611,8 @@ def main():
                     help="skip the autotuner (layout and tile from --layout / --tile)")
     ap.add_argument("--cases", type=int, default=0, help="single-network workloads: the first N cases only")
     ap.add_argument("--trace", type=int, default=4096, help="C5: trace queries")
-    ap.add_argument("--budget-gb", type=float, default=32.0, help="C5: device-memory budget, GiB")
-    ap.add_argument("--max-batch", type=int, default=32, help="C5: slots per resident tree at most")
+    ap.add_argument("--budget-gb", type=float, default=64.0, help="C5: device-memory budget, GiB")
+    ap.add_argument("--max-batch", type=int, default=64, help="C5: slots per resident tree at most")
     ap.add_argument("--tiles", default="2048",
                     help="C5: tile per tree, one value for all or comma-separated per tree; 'auto' times "
                          "the candidates on the device (it picks 2048 for all or all but one of the trees)")

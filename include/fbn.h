@@ -110,7 +110,19 @@ typedef struct {
                                    * then the FP64 ones and its status is the
                                    * FP64 status.  fbn_fetch_async still
                                    * reports the raw flags.  0: no rerun.     */
-    int32_t reserved;
+    int32_t slots_per_block;      /* PER_SLOT layout: most evidence slots one
+                                   * layer workgroup carries, sharing its index
+                                   * arithmetic: 1, 2, 4 or 8.  0 (default):
+                                   * as many as the layer's LDS stage fits in
+                                   * 32 KB, fewer while the layer's grid would
+                                   * not give every compute unit a workgroup.
+                                   * Results are bitwise the same.            */
+    int32_t fin_block;            /* PER_SLOT layout: separator entries per
+                                   * block when a large separator is finalised
+                                   * in blocks, 64 to 4096; 0 (default) 4096.
+                                   * Only the order of the posterior sums'
+                                   * additions changes.  Other values:
+                                   * FBN_E_INVALID_ARG.                       */
 } fbn_jt_options;
 
 typedef struct {

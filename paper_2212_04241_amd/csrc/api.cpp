@@ -474,6 +474,7 @@ fbn_status setup_device(fbn_jt* jt) {
     c.fp32 = f32 ? 1 : 0;
     c.tile = p.stage;
     c.dense = jt->opt.shrink_evidence ? 0 : 1;
+    c.bcap = jt->opt.slots_per_block;
     HIP_OK(hipStreamSynchronize(jt->stream));
     return FBN_OK;
 }
@@ -806,6 +807,11 @@ static fbn_status build_jt_impl(const std::vector<const fbn_net*>& nets, const f
         opt.tile_entries < 0 || opt.tile_entries > kTileMax || opt.layout < FBN_LAYOUT_AUTO ||
         opt.layout > FBN_LAYOUT_INTERLEAVED)
         return fail(FBN_E_INVALID_ARG, "bad options");
+    if (opt.slots_per_block != 0 && opt.slots_per_block != 1 && opt.slots_per_block != 2 &&
+        opt.slots_per_block != 4 && opt.slots_per_block != 8)
+        return fail(FBN_E_INVALID_ARG, "slots_per_block must be 0, 1, 2, 4 or 8");
+    if (opt.fin_block != 0 && (opt.fin_block < 64 || opt.fin_block > (int32_t)kFinBlock))
+        return fail(FBN_E_INVALID_ARG, "fin_block must be 0 or in [64, 4096]");
     if (opt.max_clique_entries == 0 || opt.max_clique_entries > 0x7fffffffull) opt.max_clique_entries = 0x7fffffffull;
     fbn_jt* jt = nullptr;
     try {
@@ -863,7 +869,8 @@ static fbn_status finish_build(fbn_jt* jt, fbn_jt** out) {
         const bool il = opt.layout == FBN_LAYOUT_INTERLEAVED;
         const int def_tile = il ? 64 : (opt.precision == FBN_FP32_RESCALED ? 1024 : 512);
         const uint32_t max_stage = (uint32_t)kSlotStageBytes / (opt.precision == FBN_FP32_RESCALED ? 4u : 8u);
-        build_plan(jt->tree, opt.tile_entries ? opt.tile_entries : def_tile, max_stage, jt->plan, il);
+        build_plan(jt->tree, opt.tile_entries ? opt.tile_entries : def_tile, max_stage, jt->plan, il,
+                   (uint32_t)opt.fin_block);
         const std::string bad = check_plan(jt->tree, jt->plan);
         if (!bad.empty()) {
             delete jt;

@@ -45,6 +45,7 @@ struct Ctx {
     int32_t dense;         // per-slot layout: 1 streams every table entry; 0 skips, per slot, the
                            // entries its evidence zeroes (never read, psi never written there):
                            // the shrink_evidence option
+    int32_t bcap;          // per-slot layout: most slots per layer workgroup (0: no cap)
 };
 
 // Bytes of LDS one slot's tile may take: plans keep every collect group and
@@ -59,10 +60,12 @@ constexpr int kStageBytes = 32768;
 // workgroups.
 constexpr uint64_t kFillGrid = 256;
 // Slots one workgroup carries for a stage of `tile` entries of width w, over
-// `items` work items and `nslots` slots.
-inline int slots_per_block(uint32_t tile, int w, uint64_t items, int nslots) {
+// `items` work items and `nslots` slots;
+// `cap` (0: none) bounds the result.
+inline int slots_per_block(uint32_t tile, int w, uint64_t items, int nslots, int cap) {
     if (nslots < 4) return 1;
     int b = kStageBytes / (int)(tile * (uint32_t)w);
+    if (cap > 0 && b > cap) b = cap;
     b = b >= 8 && nslots >= 8 ? 8 : (b >= 4 ? 4 : (b >= 2 ? 2 : 1));
     while (b > 1 && items * (uint64_t)((nslots + b - 1) / b) < kFillGrid) b /= 2;
     return b;

@@ -1218,7 +1218,7 @@ void launch_gather_b(const Ctx& c, const DWork* works, uint32_t nworks, const in
 template <typename T>
 void launch_collect_t(const Ctx& c, const DGroup* groups, uint32_t ngroups, const int32_t* slots, int nslots,
                       hipStream_t s) {
-    const int B = slots_per_block(c.tile, sizeof(T), ngroups, nslots);
+    const int B = slots_per_block(c.tile, sizeof(T), ngroups, nslots, c.bcap);
     if (B == 8) launch_collect_b<T, 8>(c, groups, ngroups, slots, nslots, s);
     else if (B == 4) launch_collect_b<T, 4>(c, groups, ngroups, slots, nslots, s);
     else if (B == 2) launch_collect_b<T, 2>(c, groups, ngroups, slots, nslots, s);
@@ -1228,7 +1228,7 @@ void launch_collect_t(const Ctx& c, const DGroup* groups, uint32_t ngroups, cons
 template <typename T>
 void launch_gather_t(const Ctx& c, const DWork* works, uint32_t nworks, const int32_t* slots, int nslots,
                      hipStream_t s) {
-    const int B = slots_per_block(c.tile, sizeof(T), nworks, nslots);
+    const int B = slots_per_block(c.tile, sizeof(T), nworks, nslots, c.bcap);
     if (B == 8) launch_gather_b<T, 8>(c, works, nworks, slots, nslots, s);
     else if (B == 4) launch_gather_b<T, 4>(c, works, nworks, slots, nslots, s);
     else if (B == 2) launch_gather_b<T, 2>(c, works, nworks, slots, nslots, s);

@@ -352,10 +352,10 @@ std::string check_plan(const Tree& t, const Plan& p) {
     return "";
 }
 
-void build_plan(const Tree& t, int tile, uint32_t max_stage, Plan& p, bool interleaved) {
+void build_plan(const Tree& t, int tile, uint32_t max_stage, Plan& p, bool interleaved, uint32_t fin_block) {
     p = Plan();
     p.interleaved = interleaved;
-    p.fin_block = interleaved ? kFinBlockInterleaved : kFinBlock;
+    p.fin_block = interleaved ? kFinBlockInterleaved : (fin_block ? std::min(fin_block, kFinBlock) : kFinBlock);
     p.big_separator = interleaved ? kBigSeparatorInterleaved : kBigSeparator;
     p.fin_work = interleaved ? kFinWorkInterleaved : kFinWork;
     max_stage = std::min<uint32_t>(std::max<uint32_t>(max_stage, 64), (uint32_t)kTileMax);

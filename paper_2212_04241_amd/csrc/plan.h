@@ -68,7 +68,8 @@ struct Plan {
 // the work items are sized for one wave each (tile entries), distribute
 // work is never packed, and large separators split into blocks of
 // kFinBlockInterleaved entries.
-void build_plan(const Tree& t, int tile, uint32_t max_stage, Plan& p, bool interleaved = false);
+void build_plan(const Tree& t, int tile, uint32_t max_stage, Plan& p, bool interleaved = false,
+                uint32_t fin_block = 0);
 
 // Checks, on the host, every bound the kernels rely on: tile and run sizes,
 // run alignment to separator segments, table offsets and every value of the

@@ -33,7 +33,7 @@ class fbn_jt_options(C.Structure):
     _fields_ = [("precision", C.c_int32), ("max_slots", C.c_int32), ("max_clique_entries", C.c_uint64),
                 ("host_only", C.c_int32), ("tile_entries", C.c_int32), ("allocator", fbn_allocator),
                 ("stream", C.c_void_p), ("layout", C.c_int32), ("shrink_evidence", C.c_int32),
-                ("fp64_rerun", C.c_int32), ("reserved", C.c_int32)]
+                ("fp64_rerun", C.c_int32), ("slots_per_block", C.c_int32), ("fin_block", C.c_int32)]
 
 
 class fbn_jt_stats_t(C.Structure):
@@ -233,7 +233,8 @@ class JT:
 
     def __init__(self, net, precision: int = FBN_FP64, max_slots: int = 1, max_clique_entries: int = 0,
                  host_only: bool = False, tile_entries: int = 0, stream=None, torch_allocator: bool = False,
-                 layout: int = 0, shrink_evidence: bool = False, fp64_rerun: bool = False):
+                 layout: int = 0, shrink_evidence: bool = False, fp64_rerun: bool = False,
+                 slots_per_block: int = 0, fin_block: int = 0):
         L = lib()
         opt = fbn_jt_options()
         L.fbn_default_options(C.byref(opt))
@@ -246,6 +247,8 @@ class JT:
         opt.layout = layout
         opt.shrink_evidence = 1 if shrink_evidence else 0
         opt.fp64_rerun = 1 if fp64_rerun else 0
+        opt.slots_per_block = slots_per_block
+        opt.fin_block = fin_block
         opt.stream = C.c_void_p(stream) if stream else None
         self._cb = None
         if torch_allocator and not host_only:

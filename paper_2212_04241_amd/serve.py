@@ -76,17 +76,19 @@ class ServeResult:
 
 
 def admission_plan(handles, tiles, budget_bytes: int, max_batch: int, layout: int = 0,
-                   shrink_evidence: bool = False) -> dict:
+                   shrink_evidence: bool = False, knobs=None) -> dict:
     """Device-memory plan of a server (host only, no device needed): the fixed
     bytes of every tree (plan, maps, prior), one FP64 fallback tree (the
     largest), then as many evidence slots per tree as the rest of the budget
     holds, at most max_batch.  Footprints come from host-only builds, which
     report exactly what a device build allocates.  MemoryError when not even
-    one slot per tree fits."""
+    one slot per tree fits.  knobs: per tree, the per-slot options
+    (slots_per_block, fin_block) its device build will use."""
     fixed, slot, fb = [], [], []
-    for h, t in zip(handles, tiles):
+    knobs = knobs or [{}] * len(handles)
+    for h, t, kb in zip(handles, tiles, knobs):
         a = fbn.JT(h, host_only=True, precision=fbn.FBN_FP32_RESCALED, max_slots=1, tile_entries=t,
-                   layout=layout, shrink_evidence=shrink_evidence)
+                   layout=layout, shrink_evidence=shrink_evidence, **kb)
         fixed.append(a.stats["device_bytes"] - a.stats["slot_bytes"])
         slot.append(a.stats["slot_bytes"])
         b = fbn.JT(h, host_only=True, precision=fbn.FBN_FP64, max_slots=1, tile_entries=t)
@@ -107,7 +109,7 @@ class Server:
 
     def __init__(self, nets, budget_bytes: int = 32 << 30, max_batch: int = 32, depth: int = 2,
                  graph: bool = True, tile=0, warm: bool = True, layout: int = 0,
-                 tile_candidates=(0, 2048, 4096), shrink_evidence: bool = False):
+                 tile_candidates=(0, 2048, 4096), shrink_evidence: bool = False, refine: bool = False):
         import torch
         self._torch = torch
         self.nets = list(nets)
@@ -117,7 +119,9 @@ class Server:
         handles = [fbn.net_from_spec(n) for n in self.nets]
         # tile per tree: fixed (one for all, or a list with one per tree), or
         # (tile=None) the fastest of tile_candidates for a full batch of
-        # max_batch cases, timed on the device
+        # max_batch cases, timed on the device, with the tuner's per-slot
+        # knobs (slots per workgroup, finaliser block) when `refine`
+        self.knobs = [{} for _ in self.nets]
         if isinstance(tile, (list, tuple)):
             if len(tile) != len(self.nets):
                 raise ValueError("one tile per network")
@@ -125,22 +129,25 @@ class Server:
         elif tile is None:
             from . import tune
             empty = (np.zeros(0, np.int32), np.zeros(0, np.int32))
-            self.tiles = [int(tune.tune(n, [empty] * max_batch, fbn.FBN_FP32_RESCALED, max_batch,
-                                        [(layout or tune.PER_SLOT, t) for t in tile_candidates],
-                                        reps=3)["tile"]) for n in self.nets]
+            picks = [tune.tune(n, [empty] * max_batch, fbn.FBN_FP32_RESCALED, max_batch,
+                               [(layout or tune.PER_SLOT, t) for t in tile_candidates], reps=3, refine=refine)
+                     for n in self.nets]
+            self.tiles = [int(r["tile"]) for r in picks]
+            self.knobs = [{"slots_per_block": int(r["slots_per_block"]), "fin_block": int(r["fin_block"])}
+                          for r in picks]
         else:
             self.tiles = [int(tile)] * len(self.nets)
         self.tile = self.tiles[0]
-        plan = admission_plan(handles, self.tiles, budget_bytes, max_batch, layout, shrink_evidence)
+        plan = admission_plan(handles, self.tiles, budget_bytes, max_batch, layout, shrink_evidence, self.knobs)
         self.slots = plan["slots"]
         self.fallback_reserve = plan["fallback_reserve"]
         self.planned_bytes = plan["planned_bytes"]
         self.budget_bytes = budget_bytes
         self.streams = [torch.cuda.Stream() for _ in self.nets]
         self.jts = []
-        for h, s, t in zip(handles, self.streams, self.tiles):
+        for h, s, t, kb in zip(handles, self.streams, self.tiles, self.knobs):
             jt = fbn.JT(h, precision=fbn.FBN_FP32_RESCALED, max_slots=self.slots, tile_entries=t,
-                        stream=s.cuda_stream, layout=layout, shrink_evidence=shrink_evidence)
+                        stream=s.cuda_stream, layout=layout, shrink_evidence=shrink_evidence, **kb)
             if graph:
                 fbn.set_graph_mode(jt, True)
             self.jts.append(jt)

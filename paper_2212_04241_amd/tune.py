@@ -2,7 +2,10 @@
 slot-interleaved) and the table entries per work item (the tile, which sets
 how the entries of each layer are packed into or split across workgroups)
 for one junction tree, a precision and a batch size, by timing calibrations
-of a representative batch of evidence cases on the device.
+of a representative batch of evidence cases on the device.  A per-slot
+choice is then refined one axis at a time: the most evidence slots a layer
+workgroup carries (sharing its index arithmetic) and the separator entries
+per finaliser block.
 
 The best configuration depends on the tree's shape (how large the cliques
 and separators of each layer are) and on the batch: small tiles give more
@@ -29,6 +32,10 @@ PER_SLOT, INTERLEAVED = fbn.FBN_LAYOUT_PER_SLOT, fbn.FBN_LAYOUT_INTERLEAVED
 # (layout, tile entries); tile 0 is the library's default for the layout
 DEFAULT_CANDIDATES = [(PER_SLOT, 0), (PER_SLOT, 512), (PER_SLOT, 2048), (PER_SLOT, 4096),
                       (INTERLEAVED, 0), (INTERLEAVED, 32), (INTERLEAVED, 128), (INTERLEAVED, 256)]
+# per-slot refinements, tried in this order, each against the best so far;
+# 0 is the library's default (slots: as many as the LDS stage fits, fewer
+# when the grid would not fill the chip; finaliser blocks: 4096 entries)
+REFINE_AXES = (("slots_per_block", (1, 2, 4)), ("fin_block", (1024, 2048)))
 
 
 def network_key(nets, precision: int, max_slots: int, batch: int) -> str:
@@ -60,12 +67,12 @@ def _store(path, data):
     os.replace(tmp, path)
 
 
-def measure_on_device(nets, cases, precision, max_slots, layout, tile, reps=5) -> float:
+def measure_on_device(nets, cases, precision, max_slots, layout, tile, reps=5, **knobs) -> float:
     """Milliseconds per calibration of `cases` (one per slot) with the given
-    layout and tile: the median of `reps` synchronised calibrations after one
-    warm-up calibration."""
+    layout, tile and per-slot knobs (slots_per_block, fin_block): the median
+    of `reps` synchronised calibrations after one warm-up calibration."""
     handles = [fbn.net_from_spec(n) for n in nets] if isinstance(nets, (list, tuple)) else fbn.net_from_spec(nets)
-    jt = fbn.JT(handles, precision=precision, max_slots=max_slots, layout=layout, tile_entries=tile)
+    jt = fbn.JT(handles, precision=precision, max_slots=max_slots, layout=layout, tile_entries=tile, **knobs)
     slots = list(range(len(cases)))
     fbn.set_evidence_batch(jt, slots, cases)
     fbn.calibrate(jt, slots, want_results=True)          # warm-up, synchronises
@@ -79,20 +86,26 @@ def measure_on_device(nets, cases, precision, max_slots, layout, tile, reps=5) -
 
 
 def tune(nets, cases, precision: int = fbn.FBN_FP32_RESCALED, max_slots: int | None = None,
-         candidates=None, reps: int = 5, cache: str | None = None, measure=None, tolerance: float = 0.02) -> dict:
-    """Best (layout, tile) for calibrating `cases` on the tree of `nets` (one
-    network or a list, as for fbn.JT).  Returns {"layout", "tile", "ms",
-    "trials": [[layout, tile, ms], ...], "cached": bool}.  A candidate replaces
-    an earlier one only when faster by more than `tolerance` (a fraction), so
-    that timing noise between near-equal candidates does not flip the choice
-    from run to run.  `measure` replaces the device timing (same signature as
-    measure_on_device)."""
+         candidates=None, reps: int = 5, cache: str | None = None, measure=None, tolerance: float = 0.02,
+         refine: bool = True) -> dict:
+    """Best configuration for calibrating `cases` on the tree of `nets` (one
+    network or a list, as for fbn.JT).  Returns {"layout", "tile",
+    "slots_per_block", "fin_block", "ms", "trials": [[layout, tile, ms], ...],
+    "refine": [[knob, value, ms], ...], "cached": bool}.  The (layout, tile)
+    candidates come first; a per-slot winner is then refined along
+    REFINE_AXES (when `refine`), each axis from the best so far.  A candidate
+    replaces the best only when faster by more than `tolerance` (a fraction),
+    so that timing noise between near-equal candidates does not flip the
+    choice from run to run.  `measure` replaces the device timing (same
+    signature as measure_on_device)."""
     cache = cache if cache is not None else os.environ.get("FBN_TUNE_CACHE")
     max_slots = max_slots or len(cases)
     key = network_key(nets, precision, max_slots, len(cases))
+    if not refine:
+        key += "-norefine"
     data = _load(cache)
     if key in data:
-        return dict(data[key], cached=True)
+        return dict({"slots_per_block": 0, "fin_block": 0, "refine": []}, **data[key], cached=True)
     measure = measure or measure_on_device
     trials = []
     for layout, tile in (candidates or DEFAULT_CANDIDATES):
@@ -107,7 +120,22 @@ def tune(nets, cases, precision: int = fbn.FBN_FP32_RESCALED, max_slots: int | N
     for t in trials[1:]:
         if t[2] < best[2] * (1.0 - tolerance):
             best = t
-    out = {"layout": best[0], "tile": best[1], "ms": best[2], "trials": trials}
+    knobs = {"slots_per_block": 0, "fin_block": 0}
+    ms_best, steps = best[2], []
+    if refine and best[0] != INTERLEAVED:
+        for name, values in REFINE_AXES:
+            pick = knobs[name]
+            for v in values:
+                try:
+                    ms = float(measure(nets, cases, precision, max_slots, best[0], best[1], reps,
+                                       **dict(knobs, **{name: v})))
+                except fbn.FbnError:
+                    continue
+                steps.append([name, int(v), ms])
+                if ms < ms_best * (1.0 - tolerance):
+                    ms_best, pick = ms, int(v)
+            knobs[name] = pick
+    out = {"layout": best[0], "tile": best[1], **knobs, "ms": ms_best, "trials": trials, "refine": steps}
     if cache:
         data = _load(cache)
         data[key] = out

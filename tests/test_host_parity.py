@@ -270,7 +270,8 @@ def test_tuner_picks_the_fastest_and_caches(tmp_path):
     cases = fbngen.make_cases("C1", net)[:4]
     calls = []
 
-    def fake(nets, cs, precision, max_slots, layout, tile, reps):
+    def fake(nets, cs, precision, max_slots, layout, tile, reps, **kw):
+        assert not kw                      # an interleaved winner is not refined
         calls.append((layout, tile))
         if tile == 512:
             raise fbn.FbnError(fbn.FBN_E_INVALID_ARG, "fake")
@@ -290,3 +291,57 @@ def test_tuner_picks_the_fastest_and_caches(tmp_path):
     assert len(calls) > n
     k1 = tune.network_key(net, 1, 4, 4)
     assert k1 == tune.network_key(net, 1, 4, 4) != tune.network_key(net, 0, 4, 4)
+
+
+def test_tuner_refines_a_per_slot_choice_one_axis_at_a_time(tmp_path):
+    from paper_2212_04241_amd import tune
+    net = fbngen.make_net("C1", 0)
+    cases = fbngen.make_cases("C1", net)[:8]
+    calls = []
+
+    def fake(nets, cs, precision, max_slots, layout, tile, reps, slots_per_block=0, fin_block=0):
+        calls.append((layout, tile, slots_per_block, fin_block))
+        if layout == tune.INTERLEAVED:
+            return 9.0
+        base = {0: 5.0, 512: 6.0, 2048: 4.0, 4096: 4.5}[tile]
+        # slots per block 2 is 10% faster, 4 only 1% (inside the tolerance);
+        # finaliser blocks of 1024 a further 5% on top of the chosen slots
+        base *= {0: 1.0, 1: 1.3, 2: 0.9, 4: 0.99}[slots_per_block]
+        if fin_block == 1024:
+            assert slots_per_block == 2     # refined from the best so far
+            base *= 0.95
+        return base
+
+    r = tune.tune(net, cases, cache=str(tmp_path / "t.json"), measure=fake)
+    assert (r["layout"], r["tile"], r["slots_per_block"], r["fin_block"]) == (tune.PER_SLOT, 2048, 2, 1024)
+    assert r["ms"] == pytest.approx(4.0 * 0.9 * 0.95)
+    assert [s[:2] for s in r["refine"]] == [["slots_per_block", 1], ["slots_per_block", 2], ["slots_per_block", 4],
+                                            ["fin_block", 1024], ["fin_block", 2048]]
+    assert all(c[:2] == (tune.PER_SLOT, 2048) for c in calls[len(tune.DEFAULT_CANDIDATES):])
+    # cached with its knobs; refine=False is its own key and tries no knob
+    n = len(calls)
+    assert tune.tune(net, cases, cache=str(tmp_path / "t.json"), measure=fake)["fin_block"] == 1024
+    r3 = tune.tune(net, cases, cache=str(tmp_path / "t.json"), measure=fake, refine=False)
+    assert len(calls) == n + len(tune.DEFAULT_CANDIDATES) and r3["slots_per_block"] == 0 and r3["refine"] == []
+
+
+@pytest.mark.parametrize("field,value", [("slots_per_block", 3), ("slots_per_block", 16), ("slots_per_block", -1),
+                                         ("fin_block", 32), ("fin_block", 8192), ("fin_block", -4)])
+def test_bad_per_slot_knobs_are_rejected(field, value):
+    net = fbn.net_from_spec(fbngen.make_net("C1", 0))
+    with pytest.raises(fbn.FbnError) as ei:
+        fbn.JT(net, host_only=True, **{field: value})
+    assert ei.value.code == fbn.FBN_E_INVALID_ARG
+
+
+def test_finaliser_block_size_reshapes_only_the_finaliser_scratch():
+    # C2's large separators are finalised in blocks: smaller blocks mean more
+    # of them, so more per-block posterior scratch per slot; the tree and every
+    # table are unchanged
+    net = fbn.net_from_spec(fbngen.make_net("C2", 0))
+    a = fbn.JT(net, host_only=True, precision=fbn.FBN_FP32_RESCALED)
+    b = fbn.JT(net, host_only=True, precision=fbn.FBN_FP32_RESCALED, fin_block=256)
+    c = fbn.JT(net, host_only=True, precision=fbn.FBN_FP32_RESCALED, slots_per_block=1)
+    for k in ("T", "K", "max_clique", "sep_total", "n_cliques"):
+        assert a.stats[k] == b.stats[k] == c.stats[k]
+    assert b.stats["slot_bytes"] >= a.stats["slot_bytes"] == c.stats["slot_bytes"]
