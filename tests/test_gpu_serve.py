@@ -206,11 +206,14 @@ def test_second_batch_of_a_tree_is_enqueued_while_the_first_runs():
 
 @pytest.mark.timeout(900)
 def test_served_fp32_matches_oracle_on_200_trace_queries(c5):
-    """The served FP32 path (default server, tuned tiles) against the oracle
-    on the first 200 queries of the arrival trace, every posterior entry."""
+    """The served FP32 path in the configuration the benchmark times (64
+    slots per tree in a 64 GiB budget, tile 2048 on every tree) against the
+    oracle on the first 200 queries of the arrival trace, every posterior
+    entry."""
     from concurrent.futures import ThreadPoolExecutor
     nets, queries = c5
-    srv = Server(nets, budget_bytes=32 << 30, max_batch=32, tile=None)
+    srv = Server(nets, budget_bytes=64 << 30, max_batch=64, tile=[2048] * len(nets))
+    assert srv.slots == 64
     res = srv.run(queries, None, keep=range(len(queries)))
     srv.close()
     assert np.all(res.status == 0)
