@@ -318,6 +318,20 @@ def oracle_one_core(ojts, pairs, cases_of, limit_s=10.0):
             "queries_timed": len(times)}
 
 
+def host_cpu() -> dict:
+    """The host the CPU baseline ran on: logical cores and the model name."""
+    model = None
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    return {"nproc": os.cpu_count(), "model": model}
+
+
 def cpu_baseline(W, seconds):
     import oracle
     sample = W.sample(200 if len(W.nets) == 1 else 512)
@@ -340,7 +354,7 @@ def cpu_baseline(W, seconds):
             f"{len(ojts)} networks")
     return {"value": done / dt, "unit": "queries/s", "cores": threads, "kind": "oracle",
             "sample": f"{done} oracle queries cycling over {what}, {dt:.1f} s, "
-                      f"{threads} threads (one query per thread at a time)"}, ojts
+                      f"{threads} threads (one query per thread at a time)", "host": host_cpu()}, ojts
 
 
 def accuracy(W, ojts, get, pairs, fp32):
@@ -463,6 +477,10 @@ def bench_served(args, fbn):
     qps_served = tot_q / tot_t
     log(f"[bench] served closed loop: {qps_served:.1f} q/s ({args.steps} x {n} queries), "
         f"p50 {1e3 * sat.percentile(50):.2f} ms")
+    # useful bandwidth: the materialised-Hugin table bytes (3 T w) of each
+    # query's own network, per second
+    T_net = [int(jt.stats["T"]) for jt in srv.jts]
+    bytes_per_query = float(np.mean([3.0 * T_net[q.net] for q in queries]))
     # dominant kernel: one profiled (eager) full batch per tree
     prof = profile_full_batches(fbn, srv, queries)
     # plain FP64 engine, closed loop over a prefix
@@ -536,9 +554,11 @@ def bench_served(args, fbn):
         "roofline": roofline,
         "paths": {
             "served_fp32_closed_loop": lat(sat) | {"batches": sat.batches, "fp64_fallbacks": fallbacks,
+                                                   "useful_GBps": round(qps_served * bytes_per_query * 4 / 1e9, 1),
                                                    "kernel_ms_one_batch_per_tree":
                                                        {k: round(v[0], 3) for k, v in prof.items()}},
-            "plain_fp64_closed_loop": lat(plain_sat),
+            "plain_fp64_closed_loop": lat(plain_sat) | {
+                "useful_GBps": round(plain_sat.qps * bytes_per_query * 8 / 1e9, 1)},
             "open_loop_at_0.8x_plain": {"rate_per_s": round(lam2, 1), "served": lat(srv_2), "plain": lat(plain_2)},
             "open_loop_at_0.8x_served": {"rate_per_s": round(lam3, 1), "served": lat(srv_3),
                                          "plain": "unstable at this rate (above its saturation)"},
@@ -575,7 +595,8 @@ def bench_served(args, fbn):
         dt = time.perf_counter() - t0
         out["cpu_baseline"] = {"value": done / dt, "unit": "queries/s", "cores": threads, "kind": "oracle",
                                "sample": f"{done} oracle queries over the first {len(sample)} trace queries, "
-                                         f"{dt:.1f} s, {threads} threads (one query per thread at a time)"}
+                                         f"{dt:.1f} s, {threads} threads (one query per thread at a time)",
+                               "host": host_cpu()}
         out["cpu_baseline"]["one_core"] = oracle_one_core(
             ojts, [(queries[i].net, i) for i in sample], lambda j, i: (queries[i].vars, queries[i].states))
         e32 = e64 = l32 = l64 = 0.0
