@@ -71,6 +71,7 @@ struct DClique {
     uint32_t psep;       // separator-arena offset of the parent separator (root: virtual entry)
     uint32_t pmh, pml;   // parent-map tables (uint32 pool): entry -> parent separator index
     uint32_t seg;        // size / |parent separator| (root: size)
+    uint32_t segmul, segsh;  // division by seg: entry i lies in parent-separator entry i / seg
     uint32_t child0;     // first DChild record
     uint32_t home0;      // first DHome record
     uint16_t nchild, nhome;

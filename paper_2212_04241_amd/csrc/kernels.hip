@@ -619,7 +619,7 @@ struct RunD {
     uint32_t count, gofs;
     uint32_t L, Lmul, Lsh;
     int32_t pedge;
-    uint32_t psep, pmh, pml, psi;  // psi: working-table offset
+    uint32_t psep, segmul, segsh, psi;  // parent separator entry = psep + entry / seg; psi: working-table offset
     uint32_t hdig, ldig;           // packed-digit tables (evidence test)
 };
 
@@ -658,8 +658,8 @@ __global__ __launch_bounds__(kBlock) void k_dist_gather(Ctx c, const DWork* __re
         if (threadIdx.x < w.npiece) {
             const DPiece pc = c.pc[w.piece0 + threadIdx.x];
             const DClique cq = c.cl[pc.clique];
-            runs[threadIdx.x] = RunD{cq.off, pc.count, pc.gofs, cq.L, cq.Lmul, cq.Lsh, cq.pedge, cq.psep, cq.pmh,
-                                     cq.pml, cq.psi, cq.hdig, cq.ldig};
+            runs[threadIdx.x] = RunD{cq.off, pc.count, pc.gofs, cq.L, cq.Lmul, cq.Lsh, cq.pedge, cq.psep, cq.segmul,
+                                     cq.segsh, cq.psi, cq.hdig, cq.ldig};
             if (SKIP) {
 #pragma unroll
                 for (int b = 0; b < B; b++)
@@ -718,7 +718,7 @@ __global__ __launch_bounds__(kBlock) void k_dist_gather(Ctx c, const DWork* __re
             }
             if (ratio) {
 #pragma unroll
-                for (uint32_t u = 0; u < U; u++) pr[u] = q.psep + map[q.pmh + row[u]] + map[q.pml + lo[u]];
+                for (uint32_t u = 0; u < U; u++) pr[u] = q.psep + mdiv(ent[u], q.segmul, q.segsh);
             }
             uint32_t nd[U];
 #pragma unroll
@@ -748,7 +748,7 @@ __global__ __launch_bounds__(kBlock) void k_dist_gather(Ctx c, const DWork* __re
         }
     } else {
         // packed: the current run's fields, reloaded only when the run changes
-        uint32_t p = 0, r_end = 0, r_gofs = 0, r_L = 1, r_Lmul = 0, r_Lsh = 0, r_psep = 0, r_pmh = 0, r_pml = 0;
+        uint32_t p = 0, r_end = 0, r_gofs = 0, r_L = 1, r_Lmul = 0, r_Lsh = 0, r_psep = 0, r_segmul = 0, r_segsh = 0;
         uint32_t r_psi = 0, r_hdig = 0, r_ldig = 0;
         int32_t r_pedge = -1;
         bool first = true, test = false;
@@ -766,8 +766,8 @@ __global__ __launch_bounds__(kBlock) void k_dist_gather(Ctx c, const DWork* __re
                 r_Lsh = rr.Lsh;
                 r_pedge = rr.pedge;
                 r_psep = rr.psep;
-                r_pmh = rr.pmh;
-                r_pml = rr.pml;
+                r_segmul = rr.segmul;
+                r_segsh = rr.segsh;
                 r_psi = rr.psi;
                 r_hdig = rr.hdig;
                 r_ldig = rr.ldig;
@@ -782,7 +782,7 @@ __global__ __launch_bounds__(kBlock) void k_dist_gather(Ctx c, const DWork* __re
             const uint32_t ent = gi - r_gofs;
             const uint32_t row = mdiv(ent, r_Lmul, r_Lsh);
             const uint32_t l = ent - row * r_L;
-            const uint32_t pr = r_pedge >= 0 ? r_psep + map[r_pmh + row] + map[r_pml + l] : 0u;
+            const uint32_t pr = r_pedge >= 0 ? r_psep + mdiv(ent, r_segmul, r_segsh) : 0u;
             const uint32_t nd = need_mask<B, SKIP>(test ? (c.dig[r_hdig + row] | c.dig[r_ldig + l]) : 0, ev, valid);
             // every needed slot's loads issued together (a root clique reads
             // ratio entry 0, unused)

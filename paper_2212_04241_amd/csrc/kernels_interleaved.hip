@@ -259,7 +259,8 @@ __device__ __forceinline__ void dist_pairs_i(const Ctx& c, const DWork& w, const
             const DChild cd = c.ch[q.child0 + ch];
             xj[ch] = cd.sep + map[cd.mh + row] + map[cd.ml + l];
         }
-        const uint32_t rj = ratio ? q.psep + map[q.pmh + row] + map[q.pml + l] : 0u;
+        // the parent separator leads the clique's layout: entry / seg
+        const uint32_t rj = ratio ? q.psep + mdiv_i(row * q.L + l, q.segmul, q.segsh) : 0u;
         const uint32_t mj = map[tg.tb + w.g0 + gg] + map[tg.tv + t];
         for (uint32_t x0 = 0; x0 < cnt; x0 += U) {
             T m[U][NW], r[U];
@@ -332,7 +333,7 @@ __device__ __forceinline__ void dist_pairs_psi_i(const Ctx& c, const DWork& w, c
         const uint32_t row = map[tg.rg + w.g0 + gg] + map[tg.rq + w.k0 + k];
         const uint32_t l = map[tg.lp + t] + map[tg.lq + u];
         const uint32_t ej = row * q.L + l;  // within the clique
-        const uint32_t rj = ratio ? q.psep + map[q.pmh + row] + map[q.pml + l] : 0u;
+        const uint32_t rj = ratio ? q.psep + mdiv_i(ej, q.segmul, q.segsh) : 0u;
         const uint32_t mj = map[tg.tb + w.g0 + gg] + map[tg.tv + t];
         for (uint32_t x0 = 0; x0 < cnt; x0 += kDistBatch) {
             T v[kDistBatch], r[kDistBatch];

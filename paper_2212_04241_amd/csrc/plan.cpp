@@ -169,6 +169,15 @@ std::string check_plan(const Tree& t, const Plan& p) {
         const bool is_root = t.pedge[c] < 0;
         const uint32_t psize = is_root ? 1u : (uint32_t)t.e_size[(size_t)t.pedge[c]];
         if (d.seg == 0 || d.size != d.seg * psize) return "segment";
+        for (uint32_t i : {0u, d.size - 1, d.size / 2, d.size / 3, d.seg, d.seg - 1, d.L, d.size / 7})
+            if (i < d.size && mdiv_host(i, d.segmul, d.segsh) != i / d.seg) return "segment magic";
+        if (!is_root && (uint64_t)d.pmh + rows <= p.maps.size() && (uint64_t)d.pml + d.L <= p.maps.size()) {
+            // the parent separator leads the layout: entry i lies in its entry
+            // i / seg, which the distribute gathers compute instead of loading
+            for (uint32_t i : {0u, d.size - 1, d.size / 2, d.size / 3, d.seg, d.seg - 1, d.L, d.size / 7})
+                if (i < d.size && p.maps[d.pmh + i / d.L] + p.maps[d.pml + i % d.L] != i / d.seg)
+                    return "parent map is not i / seg";
+        }
         if ((uint64_t)d.psep + psize > p.sep_real) return "parent separator offset";
         auto check_map = [&](uint32_t mh, uint32_t ml, uint32_t limit) -> bool {
             if ((uint64_t)mh + rows > p.maps.size() || (uint64_t)ml + d.L > p.maps.size()) return false;
@@ -496,6 +505,7 @@ void build_plan(const Tree& t, int tile, uint32_t max_stage, Plan& p, bool inter
             d.pmh = enumerate(hi_pos, card_at, w, p.maps);
             d.pml = enumerate(lo_pos, card_at, w, p.maps);
         }
+        magic_u32(d.seg, d.segmul, d.segsh);
         // child maps: separator variables ascending, last fastest
         d.child0 = (uint32_t)p.children.size();
         d.nchild = (uint16_t)t.children[(size_t)c].size();
