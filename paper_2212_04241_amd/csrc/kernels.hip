@@ -473,9 +473,10 @@ __device__ __forceinline__ bool team_of(uint32_t bx, uint32_t nbig, uint32_t nfi
 }
 
 // Finish the entries [b, e) of separator f (acc and part offset to the
-// separator): an entry whose sum was split over chunks gets its partials
-// added by tpe lanes of one wave (a power of two, about four partials per
-// lane), combined by a fixed xor-shuffle tree, and stored; fn(m, v) is then
+// separator; partials chunk-major, chunk k of entry m at k * size + m): an
+// entry whose sum was split over chunks gets its partials added by tpe lanes
+// of one wave (a power of two), combined by a fixed xor-shuffle tree, and
+// stored; fn(m, v) is then
 // called once per entry, v its finished value.  t is the thread's index in
 // its team of nt threads (a wave or a workgroup); every thread of the team
 // must make the call.
@@ -494,19 +495,24 @@ __device__ __forceinline__ void finish_range(const DSepFin& f, T* acc, const T* 
         }
         return;
     }
-    uint32_t tpe = 1;
-    while (tpe < (uint32_t)kWave && tpe * 4 < f.nchunk) tpe *= 2;
+    // partials are chunk-major (chunk k of entry m at k * size + m): a wave
+    // takes epw consecutive entries (as many as the separator has, up to a
+    // wave) with an entry's tpe lanes epw apart, so every load reads runs of
+    // epw consecutive partials; the split depends on the separator alone, so
+    // an entry's sum has one order however the separator is cut into blocks
+    uint32_t epw = 1;
+    while (epw < (uint32_t)kWave && epw < f.size) epw *= 2;
+    const uint32_t tpe = (uint32_t)kWave / epw;
     const uint32_t lane = t & (kWave - 1), wv = t / kWave, nw = nt / kWave;
-    const uint32_t epw = (uint32_t)kWave / tpe, sub = lane & (tpe - 1), eo = lane / tpe;
+    const uint32_t sub = lane / epw, eo = lane & (epw - 1);
     for (uint32_t m0 = b + wv * epw; m0 < e; m0 += nw * epw) {
         const uint32_t m = m0 + eo;
         double v = 0.0;
         if (m < e) {
-            const T* pp = part + (uint64_t)m * f.nchunk;
 #pragma unroll 4
-            for (uint32_t k = sub; k < f.nchunk; k += tpe) v += pp[k];
+            for (uint32_t k = sub; k < f.nchunk; k += tpe) v += part[(uint64_t)k * f.size + m];
         }
-        for (uint32_t o = tpe / 2; o > 0; o >>= 1) v += __shfl_xor(v, (int)o, kWave);
+        for (uint32_t o = tpe / 2; o > 0; o >>= 1) v += __shfl_xor(v, (int)(o * epw), kWave);
         if (m < e && sub == 0) {
             acc[m] = (T)v;
             fn(m, v);
@@ -817,7 +823,7 @@ __global__ __launch_bounds__(kBlock) void k_dist_gather(Ctx c, const DWork* __re
         for (int b = 0; b < B; b++) s[b] = 0.0;
         uint32_t m = 0, sep = 0, gofs = 0;
         int32_t part0 = -1;
-        uint32_t nchunk = 0;
+        uint32_t tsz = 0;  // target size: chunk-major partials
         if (o < nout) {
             DTarget t2 = tg;
             uint32_t L = q.L, g, t, nk, rowbase;
@@ -888,7 +894,7 @@ __global__ __launch_bounds__(kBlock) void k_dist_gather(Ctx c, const DWork* __re
             }
             sep = t2.sep;
             part0 = t2.part0;
-            nchunk = t2.nchunk;
+            tsz = t2.G * t2.nPL;
         }
 #pragma unroll
         for (int b = 0; b < B; b++)
@@ -898,7 +904,7 @@ __global__ __launch_bounds__(kBlock) void k_dist_gather(Ctx c, const DWork* __re
             for (int b = 0; b < B; b++) {
                 if (sl[b] < 0) continue;
                 if (part0 < 0) static_cast<T*>(c.acc)[(uint64_t)sl[b] * c.sep_stride + sep + m] = (T)s[b];
-                else static_cast<T*>(c.part)[(uint64_t)sl[b] * c.part_stride + (uint32_t)part0 + m * nchunk + w.chunk] = (T)s[b];
+                else static_cast<T*>(c.part)[(uint64_t)sl[b] * c.part_stride + (uint32_t)part0 + w.chunk * tsz + m] = (T)s[b];
             }
         }
     }

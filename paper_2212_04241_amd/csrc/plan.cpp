@@ -582,7 +582,10 @@ void build_plan(const Tree& t, int tile, uint32_t max_stage, Plan& p, bool inter
                     for (uint32_t k = 0; k < nchunk; k++) {
                         const uint32_t b = (uint32_t)((uint64_t)k * seg / nchunk);
                         const uint32_t e = (uint32_t)((uint64_t)(k + 1) * seg / nchunk);
-                        pk.add_part((uint32_t)c, s * seg + b, e - b, (int32_t)(parts + s * nchunk + k));
+                        // per-slot partials are chunk-major (chunk k of entry s at
+                        // k * size + s), slot-interleaved ones entry-major
+                        const uint32_t at = interleaved ? parts + s * nchunk + k : parts + k * f.size + s;
+                        pk.add_part((uint32_t)c, s * seg + b, e - b, (int32_t)at);
                     }
                 parts += f.size * nchunk;
             }
