@@ -475,8 +475,8 @@ __device__ __forceinline__ bool team_of(uint32_t bx, uint32_t nbig, uint32_t nfi
 // Finish the entries [b, e) of separator f (acc and part offset to the
 // separator; partials chunk-major, chunk k of entry m at k * size + m): an
 // entry whose sum was split over chunks gets its partials added by tpe lanes
-// of one wave (a power of two), combined by a fixed xor-shuffle tree, and
-// stored; fn(m, v) is then
+// of one wave (a power of two, about four partials per lane), combined by a
+// fixed xor-shuffle tree, and stored; fn(m, v) is then
 // called once per entry, v its finished value.  t is the thread's index in
 // its team of nt threads (a wave or a workgroup); every thread of the team
 // must make the call.
@@ -496,13 +496,16 @@ __device__ __forceinline__ void finish_range(const DSepFin& f, T* acc, const T* 
         return;
     }
     // partials are chunk-major (chunk k of entry m at k * size + m): a wave
-    // takes epw consecutive entries (as many as the separator has, up to a
-    // wave) with an entry's tpe lanes epw apart, so every load reads runs of
-    // epw consecutive partials; the split depends on the separator alone, so
-    // an entry's sum has one order however the separator is cut into blocks
-    uint32_t epw = 1;
-    while (epw < (uint32_t)kWave && epw < f.size) epw *= 2;
-    const uint32_t tpe = (uint32_t)kWave / epw;
+    // takes epw consecutive entries with an entry's tpe lanes epw apart, so
+    // every load reads runs of epw consecutive partials.  tpe gives each lane
+    // about four partials, more when the separator has fewer than 64 / tpe
+    // entries; the split depends on the separator alone, so an entry's sum
+    // has one order however the separator is cut into blocks
+    uint32_t tpe = 1;
+    while (tpe < (uint32_t)kWave && tpe * 4 < f.nchunk) tpe *= 2;
+    uint32_t epw = (uint32_t)kWave / tpe;
+    while (epw > 1 && epw / 2 >= f.size) epw /= 2;
+    tpe = (uint32_t)kWave / epw;
     const uint32_t lane = t & (kWave - 1), wv = t / kWave, nw = nt / kWave;
     const uint32_t sub = lane / epw, eo = lane & (epw - 1);
     for (uint32_t m0 = b + wv * epw; m0 < e; m0 += nw * epw) {
