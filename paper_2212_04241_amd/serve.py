@@ -109,7 +109,8 @@ class Server:
 
     def __init__(self, nets, budget_bytes: int = 32 << 30, max_batch: int = 32, depth: int = 2,
                  graph: bool = True, tile=0, warm: bool = True, layout: int = 0,
-                 tile_candidates=(0, 2048, 4096), shrink_evidence: bool = False, refine: bool = False):
+                 tile_candidates=(0, 2048, 4096), shrink_evidence: bool = False, refine: bool = False,
+                 batch_cap: int | None = None):
         import torch
         self._torch = torch
         self.nets = list(nets)
@@ -140,6 +141,8 @@ class Server:
         self.tile = self.tiles[0]
         plan = admission_plan(handles, self.tiles, budget_bytes, max_batch, layout, shrink_evidence, self.knobs)
         self.slots = plan["slots"]
+        # queries per batch at most (default: every free slot)
+        self.batch_cap = max(1, min(batch_cap or self.slots, self.slots))
         self.fallback_reserve = plan["fallback_reserve"]
         self.planned_bytes = plan["planned_bytes"]
         self.budget_bytes = budget_bytes
@@ -271,7 +274,7 @@ class Server:
                     busy = True
                 # launch a batch from the waiting queries
                 if pending[k] and free[k] and freebuf[k]:
-                    m = min(len(pending[k]), len(free[k]))
+                    m = min(len(pending[k]), len(free[k]), self.batch_cap)
                     qids = [pending[k].popleft() for _ in range(m)]
                     slots = [free[k].pop() for _ in range(m)]
                     bi = freebuf[k].pop()

@@ -15,11 +15,12 @@ class FakeServer(Server):
     """Server with a fake device: a batch completes after `polls` readiness
     checks; its posteriors are (qid, slot) stamps; flags come from `flags`."""
 
-    def __init__(self, n_nets, slots, depth=2, polls=2, flags=None, card_sum=4):
+    def __init__(self, n_nets, slots, depth=2, polls=2, flags=None, card_sum=4, batch_cap=None):
         self.nets = [None] * n_nets
         self.card_sum = [card_sum] * n_nets
         self.jts = [None] * n_nets
         self.slots = slots
+        self.batch_cap = batch_cap or slots
         self.depth = depth
         self.polls = polls
         self.flags = flags or {}
@@ -83,6 +84,19 @@ def test_slots_and_buffers_never_oversubscribed():
     for k, slots, qids in srv.launches:
         assert 1 <= len(slots) <= 3 and len(set(slots)) == len(slots)
     assert max(srv.max_inflight_batches) <= 2
+
+
+def test_batch_cap_splits_a_backlog_into_batches_in_flight_together():
+    srv = FakeServer(1, slots=8, depth=2, polls=4, batch_cap=4)
+    srv.run(_queries([0] * 40), None)
+    assert all(len(slots) <= 4 for _, slots, _ in srv.launches)
+    assert srv.max_inflight_batches[0] == 2          # two half-size batches overlap
+    served = [q for _, _, qids in srv.launches for q in qids]
+    assert served == list(range(40))
+    # without the cap one batch takes every free slot, so a second cannot start
+    srv = FakeServer(1, slots=8, depth=2, polls=4)
+    srv.run(_queries([0] * 40), None)
+    assert srv.max_inflight_batches[0] == 1 and len(srv.launches[0][1]) == 8
 
 
 def test_no_network_starves_behind_a_backlog():
