@@ -39,8 +39,19 @@ int main(int argc, char** argv) {
     /* a device call on a host-only tree is refused, not attempted */
     const int32_t zero = 0;
     const fbn_status refused = fbn_calibrate(jt, 1, &zero, NULL, NULL);
-    printf("vars %d first %s late %d yes %d card %d parents %d cpt %zu cliques %d edges %d T %llu refused %d\n", n,
-           name, v, s, card, npar, len, st.n_cliques, st.n_edges, (unsigned long long)st.T, refused);
+    /* the per-slot knobs: accepted values build, others are refused */
+    fbn_jt* jt2 = NULL;
+    opt.slots_per_block = 4;
+    opt.fin_block = 1024;
+    const fbn_status knobs_ok = fbn_build_jt(net, &opt, &jt2);
+    fbn_free_jt(jt2);
+    jt2 = NULL;
+    opt.slots_per_block = 3;
+    const fbn_status knobs_bad = fbn_build_jt(net, &opt, &jt2);
+    printf("vars %d first %s late %d yes %d card %d parents %d cpt %zu cliques %d edges %d T %llu refused %d "
+           "knobs_ok %d knobs_bad %d null %d\n",
+           n, name, v, s, card, npar, len, st.n_cliques, st.n_edges, (unsigned long long)st.T, refused, knobs_ok,
+           knobs_bad, jt2 == NULL);
     fbn_free_jt(jt);
     fbn_free_net(net);
     fbn_free_jt(NULL);

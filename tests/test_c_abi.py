@@ -1,7 +1,8 @@
 """The C ABI used from C: tests/c/abi_host.c, compiled with gcc as C99
 against include/fbn.h and linked to the built library, loads the hand-written
-BIF network, looks names up, compiles a host-only tree and checks that a
-device call on it is refused (CPU only: no device call is made)."""
+BIF network, looks names up, compiles a host-only tree, checks that a
+device call on it is refused and that the per-slot option fields reach the
+library as C lays out the struct (CPU only: no device call is made)."""
 import os
 import shutil
 import subprocess
@@ -31,3 +32,6 @@ def test_header_compiles_as_c_and_the_host_calls_work(tmp_path):
     assert kv["card"] == "2" and kv["parents"] == "2" and kv["cpt"] == "12"
     assert int(kv["cliques"]) >= 3 and int(kv["T"]) > 0
     assert int(kv["refused"]) == fbn.FBN_E_STATE
+    # the options struct as C sees it: the per-slot knobs reach the library
+    assert int(kv["knobs_ok"]) == fbn.FBN_OK
+    assert int(kv["knobs_bad"]) == fbn.FBN_E_INVALID_ARG and kv["null"] == "1"
